@@ -1,0 +1,191 @@
+"""ctypes binding of the FP64 CPU oracle (oracle/af_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
+CPU-baseline leg of the benchmark, never by the product package.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "af_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+LIM_SMOOTH, LIM_PP, LIM_POINT, LIM_CENTRE, LIM_LOWONLY = 1, 2, 4, 8, 16
+LIM_ALL = LIM_SMOOTH | LIM_PP | LIM_POINT | LIM_CENTRE
+FLAG_CELL_LOW, FLAG_POINT_LOW, FLAG_NONFINITE = 1, 2, 4
+
+
+def build(force: bool = True) -> str:
+    """compile the oracle with gcc (FP64, no contraction, OpenMP over rows)"""
+    if force or not os.path.exists(LIB):
+        cmd = ["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp",
+               "-o", LIB, SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+    return LIB
+
+
+class Cfg(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n1", C.c_int), ("n2", C.c_int),
+                ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
+                ("gamma", C.c_double), ("mu", C.c_double), ("Pr", C.c_double),
+                ("Cs", C.c_double), ("cfl_c", C.c_double), ("cfl_v", C.c_double),
+                ("limiter", C.c_int), ("bc", C.c_int * 4), ("max_halvings", C.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        dp = C.POINTER(C.c_double)
+        cp = C.POINTER(Cfg)
+        L.orc_state_len.argtypes = [cp]
+        L.orc_state_len.restype = C.c_long
+        L.orc_fe.argtypes = [cp, dp, C.c_double, dp, dp, dp]
+        L.orc_fe.restype = C.c_int
+        L.orc_rhs.argtypes = [cp, dp, dp]
+        L.orc_rhs.restype = None
+        L.orc_dt.argtypes = [cp, dp]
+        L.orc_dt.restype = C.c_double
+        L.orc_step.argtypes = [cp, dp, C.c_double, C.c_double, C.c_double, dp,
+                               C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.orc_step.restype = C.c_int
+        L.orc_run.argtypes = [cp, dp, C.c_double, C.c_double, C.c_long,
+                              C.POINTER(C.c_long), dp]
+        L.orc_run.restype = C.c_int
+        L.orc_Theta.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.orc_Theta.restype = C.c_double
+        L.orc_pressure.argtypes = [cp, dp]
+        L.orc_pressure.restype = C.c_double
+        L.orc_flux_c.argtypes = [cp, C.c_int, dp, dp]
+        L.orc_flux_v.argtypes = [cp, C.c_int, dp, dp, dp]
+        L.orc_bvisc.argtypes = [cp, C.c_int, dp, dp]
+        L.orc_bvisc.restype = C.c_double
+        for f in ("orc_op_dplus", "orc_op_dminus", "orc_op_dc"):
+            getattr(L, f).argtypes = [dp, C.c_double]
+            getattr(L, f).restype = C.c_double
+        L.orc_op_d2.argtypes = [dp, dp, C.c_double]
+        L.orc_op_d2.restype = C.c_double
+        L.orc_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def make_cfg(grid, gamma=1.4, mu=1e-3, Pr=0.72, limiter=LIM_ALL, cfl_c=0.2, cfl_v=0.075,
+             Cs=1.0, max_halvings=40) -> Cfg:
+    c = Cfg()
+    c.dim, c.n1, c.n2 = grid.dim, grid.n1, grid.n2
+    c.x0, c.x1, c.y0, c.y1 = grid.x0, grid.x1, grid.y0, grid.y1
+    c.gamma, c.mu, c.Pr, c.Cs = gamma, mu, Pr, Cs
+    c.cfl_c, c.cfl_v = cfl_c, cfl_v
+    c.limiter = limiter
+    for k in range(4):
+        c.bc[k] = int(grid.bc[k])
+    c.max_halvings = max_halvings
+    return c
+
+
+def nfaces(cfg: Cfg) -> int:
+    if cfg.dim == 1:
+        return cfg.n1 + 1
+    return cfg.n2 * (cfg.n1 + 1) + (cfg.n2 + 1) * cfg.n1
+
+
+def fe(cfg: Cfg, U: np.ndarray, dt: float, want_theta: bool = False):
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    out = np.empty_like(U)
+    if want_theta:
+        ts = np.empty(nfaces(cfg))
+        tp = np.empty(nfaces(cfg))
+        fl = lib().orc_fe(C.byref(cfg), _p(U), dt, _p(out), _p(ts), _p(tp))
+        return out, fl, ts, tp
+    fl = lib().orc_fe(C.byref(cfg), _p(U), dt, _p(out), None, None)
+    return out, fl
+
+
+def rhs(cfg: Cfg, U: np.ndarray) -> np.ndarray:
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    out = np.empty_like(U)
+    lib().orc_rhs(C.byref(cfg), _p(U), _p(out))
+    return out
+
+
+def dt(cfg: Cfg, U: np.ndarray) -> float:
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    return lib().orc_dt(C.byref(cfg), _p(U))
+
+
+def step(cfg: Cfg, U: np.ndarray, dt: float = 0.0, t: float = 0.0, t_final: float = 1e30):
+    """one SSP-RK3 step in place; returns (status, dt_used, halvings, flags)"""
+    assert U.dtype == np.float64 and U.flags.c_contiguous
+    dtu = C.c_double()
+    h = C.c_int()
+    fl = C.c_int()
+    st = lib().orc_step(C.byref(cfg), _p(U), dt, t, t_final, C.byref(dtu), C.byref(h), C.byref(fl))
+    return st, dtu.value, h.value, fl.value
+
+
+def run(cfg: Cfg, U: np.ndarray, t0: float, t_final: float, max_steps: int = 1 << 40):
+    assert U.dtype == np.float64 and U.flags.c_contiguous
+    ns = C.c_long()
+    t = C.c_double()
+    st = lib().orc_run(C.byref(cfg), _p(U), t0, t_final, max_steps, C.byref(ns), C.byref(t))
+    return st, ns.value, t.value
+
+
+def theta(zL, zH, eps):
+    return lib().orc_Theta(zL, zH, eps)
+
+
+def pressure(cfg, U):
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    return lib().orc_pressure(C.byref(cfg), _p(U))
+
+
+def flux_c(cfg, d, U):
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    F = np.zeros(4)
+    lib().orc_flux_c(C.byref(cfg), d, _p(U), _p(F))
+    return F[:len(U)]
+
+
+def flux_v(cfg, d, U, S):
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    F = np.zeros(4)
+    lib().orc_flux_v(C.byref(cfg), d, _p(U), _p(S), _p(F))
+    return F[:len(U)]
+
+
+def bvisc(cfg, d, U, S):
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    return lib().orc_bvisc(C.byref(cfg), d, _p(U), _p(S))
+
+
+def op(name: str, z, dx: float) -> float:
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    return getattr(lib(), "orc_op_" + name)(_p(z), dx)
+
+
+def op_d2(k, z, dx: float) -> float:
+    k = np.ascontiguousarray(k, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    return lib().orc_op_d2(_p(k), _p(z), dx)
+
+
+def threads() -> int:
+    return lib().orc_threads()

@@ -1,0 +1,101 @@
+/*
+ * af_oracle.h -- plain FP64 CPU oracle of the compact fourth-order
+ * positivity-preserving Active Flux (AF) method for the 1D/2D compressible
+ * Navier-Stokes equations (Duan, Barsukow, Klingenberg).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the HIP path.  It
+ * may be loaded by the test suite, by the smoke check and by the CPU-baseline
+ * leg of the benchmark, and by nothing else.  It shares no code, header,
+ * table or helper with the HIP library; the two are written independently
+ * from the paper.
+ *
+ * State layout (identical to the product library's documented layout, since
+ * both are fed the same input buffers):
+ *   1D: [avg: 3 x n][pts: 3 x np]          np = n (periodic) or n+1
+ *       component-major, point k sits at x0 + k*dx, cell i spans
+ *       [x0+i*dx, x0+(i+1)*dx].
+ *   2D: [avg: 4 x n2 x n1][xe: 4 x n2 x n1x][ye: 4 x n2y x n1][co: 4 x n2y x n1x]
+ *       n1x = n1 (x periodic) or n1+1, n2y likewise; x fastest.
+ *       xe(i,j) sits at (x0+i dx, y0+(j+1/2) dy)   (x-face midpoints)
+ *       ye(i,j) sits at (x0+(i+1/2) dx, y0+j dy)   (y-face midpoints)
+ *       co(i,j) sits at (x0+i dx, y0+j dy)         (cell corners)
+ *   Components: 1D (rho, rho u, E); 2D (rho, rho u, rho v, E).
+ */
+#ifndef AF_ORACLE_H
+#define AF_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* boundary kinds (per side: x-low, x-high, y-low, y-high) */
+enum { ORC_PERIODIC = 0, ORC_OUTFLOW = 1, ORC_NOSLIP = 2, ORC_SYMMETRY = 3 };
+
+/* limiter switches */
+enum {
+  ORC_LIM_SMOOTH = 1,  /* smoothness-indicator blend theta^s            */
+  ORC_LIM_PP = 2,      /* density/pressure limiting of cell-average fluxes */
+  ORC_LIM_POINT = 4,   /* scaling limiter of point values                 */
+  ORC_LIM_CENTRE = 8,  /* scaling limiter of reconstructed centre values  */
+  ORC_LIM_LOWONLY = 16 /* diagnostic: use only the low-order LLF fluxes   */
+};
+
+/* status flags raised by one forward-Euler stage */
+enum {
+  ORC_FLAG_CELL_LOW = 1,  /* a low-order cell intermediate state is not admissible  */
+  ORC_FLAG_POINT_LOW = 2, /* a low-order point state is not admissible              */
+  ORC_FLAG_NONFINITE = 4  /* a non-finite value in the stage output                  */
+};
+
+typedef struct orc_cfg {
+  int dim;              /* 1 or 2 */
+  int n1, n2;           /* cells per axis (n2 unused in 1D) */
+  double x0, x1, y0, y1;
+  double gamma, mu, Pr;
+  double Cs;            /* smoothness-limiter strength (paper: 1) */
+  double cfl_c, cfl_v;  /* CFL numbers of the inviscid and viscous parts */
+  int limiter;          /* ORC_LIM_* bits */
+  int bc[4];            /* x-low, x-high, y-low, y-high */
+  int max_halvings;
+} orc_cfg;
+
+/* sizes (in doubles) */
+long orc_state_len(const orc_cfg* c);
+
+/* forward-Euler stage with all enabled limiters: Ufe = FE(U, dt).
+ * theta_out (optional, may be NULL): per face [dir][4 comps unused]... see .c */
+int orc_fe(const orc_cfg* c, const double* U, double dt, double* Ufe,
+           double* theta_s_out, double* theta_pp_out);
+
+/* unlimited semi-discrete right-hand side dU/dt (cell averages and points) */
+void orc_rhs(const orc_cfg* c, const double* U, double* dUdt);
+
+/* CFL time step over cell averages */
+double orc_dt(const orc_cfg* c, const double* U);
+
+/* one SSP-RK3 step with the halving retry.  dt<=0 -> CFL dt.  dt is clipped
+ * to t_final - t.  Returns 0 on success, nonzero if max_halvings exceeded. */
+int orc_step(const orc_cfg* c, double* U, double dt, double t, double t_final,
+             double* dt_used, int* halvings, int* flags_out);
+
+/* run from t0 to t_final (or max_steps); returns 0 or the failing status */
+int orc_run(const orc_cfg* c, double* U, double t0, double t_final,
+            long max_steps, long* nsteps, double* t_out);
+
+/* building blocks exposed for property tests */
+double orc_Theta(double zL, double zH, double eps);
+double orc_pressure(const orc_cfg* c, const double* U);
+void orc_flux_c(const orc_cfg* c, int dir, const double* U, double* F);
+void orc_flux_v(const orc_cfg* c, int dir, const double* U, const double* S,
+                double* F);
+double orc_bvisc(const orc_cfg* c, int dir, const double* U, const double* S);
+double orc_op_dplus(const double* z, double dx);
+double orc_op_dminus(const double* z, double dx);
+double orc_op_dc(const double* z, double dx);
+double orc_op_d2(const double* k, const double* z, double dx);
+int orc_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,232 @@
+"""Seeded synthetic inputs: grids, initial data and state packing.
+
+This module builds the inputs that both the HIP library and the CPU oracle
+are fed.  It holds none of the Active Flux arithmetic: it only evaluates
+initial conditions (given as primitive variables rho, u, v, p), converts them
+to conservative variables, averages them over cells with tensor Gauss-Legendre
+quadrature and samples them at the point degrees of freedom.
+
+State layout (shared contract, documented in include/af.h):
+  1D: [avg: 3 x n][pts: 3 x np]                      np = n or n+1
+  2D: [avg: 4 x n2 x n1][xe: 4 x n2 x n1x][ye: 4 x n2y x n1][co: 4 x n2y x n1x]
+      n1x = n1 if x is periodic else n1+1 (n2y likewise), x fastest.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Callable, Sequence
+
+import numpy as np
+
+PERIODIC, OUTFLOW, NOSLIP, SYMMETRY = 0, 1, 2, 3
+
+
+@dataclass
+class Grid:
+    dim: int
+    n1: int
+    n2: int = 1
+    x0: float = 0.0
+    x1: float = 1.0
+    y0: float = 0.0
+    y1: float = 1.0
+    bc: Sequence[int] = field(default_factory=lambda: (PERIODIC,) * 4)
+
+    @property
+    def dx(self) -> float:
+        return (self.x1 - self.x0) / self.n1
+
+    @property
+    def dy(self) -> float:
+        return (self.y1 - self.y0) / self.n2
+
+    @property
+    def ncomp(self) -> int:
+        return 3 if self.dim == 1 else 4
+
+    @property
+    def n1x(self) -> int:
+        return self.n1 if self.bc[0] == PERIODIC else self.n1 + 1
+
+    @property
+    def n2y(self) -> int:
+        return self.n2 if self.bc[2] == PERIODIC else self.n2 + 1
+
+    def blocks(self):
+        """(name, rows, cols) of each DOF array, in storage order."""
+        if self.dim == 1:
+            return [("avg", 1, self.n1), ("pts", 1, self.n1x)]
+        return [("avg", self.n2, self.n1), ("xe", self.n2, self.n1x),
+                ("ye", self.n2y, self.n1), ("co", self.n2y, self.n1x)]
+
+    @property
+    def state_len(self) -> int:
+        return self.ncomp * sum(r * c for _, r, c in self.blocks())
+
+    @property
+    def dof_sites(self) -> int:
+        """number of DOF sites (each a vector of ncomp conservative values)"""
+        return sum(r * c for _, r, c in self.blocks())
+
+    def split(self, U: np.ndarray) -> dict:
+        """views of a state vector as {name: array[ncomp, rows, cols]}"""
+        out, off = {}, 0
+        for name, r, c in self.blocks():
+            n = self.ncomp * r * c
+            out[name] = U[off:off + n].reshape(self.ncomp, r, c)
+            off += n
+        return out
+
+    def point_coords(self, name: str):
+        """physical coordinates (x, y) of the sites of one point array"""
+        if self.dim == 1:
+            return self.x0 + np.arange(self.n1x) * self.dx, None
+        if name == "xe":
+            xs = self.x0 + np.arange(self.n1x) * self.dx
+            ys = self.y0 + (np.arange(self.n2) + 0.5) * self.dy
+        elif name == "ye":
+            xs = self.x0 + (np.arange(self.n1) + 0.5) * self.dx
+            ys = self.y0 + np.arange(self.n2y) * self.dy
+        else:
+            xs = self.x0 + np.arange(self.n1x) * self.dx
+            ys = self.y0 + np.arange(self.n2y) * self.dy
+        return np.meshgrid(xs, ys)
+
+
+def conservative(prim: Sequence[np.ndarray], gamma: float) -> list:
+    """(rho,u,p) or (rho,u,v,p) -> (rho, rho u, [rho v,] E)"""
+    if len(prim) == 3:
+        r, u, p = prim
+        return [r, r * u, p / (gamma - 1.0) + 0.5 * r * u * u]
+    r, u, v, p = prim
+    return [r, r * u, r * v, p / (gamma - 1.0) + 0.5 * r * (u * u + v * v)]
+
+
+def make_state(grid: Grid, prim_fn: Callable, gamma: float, nq: int = 5) -> np.ndarray:
+    """Cell averages by nq-point tensor Gauss-Legendre quadrature of the
+    conservative variables, point values sampled exactly."""
+    gx, gw = np.polynomial.legendre.leggauss(nq)
+    gx = 0.5 * (gx + 1.0)
+    gw = 0.5 * gw
+    U = np.zeros(grid.state_len)
+    parts = grid.split(U)
+    if grid.dim == 1:
+        xl = grid.x0 + np.arange(grid.n1) * grid.dx
+        acc = [np.zeros(grid.n1) for _ in range(3)]
+        for q in range(nq):
+            cons = conservative(prim_fn(xl + gx[q] * grid.dx), gamma)
+            for k in range(3):
+                acc[k] += gw[q] * cons[k]
+        for k in range(3):
+            parts["avg"][k, 0] = acc[k]
+        xs, _ = grid.point_coords("pts")
+        cons = conservative(prim_fn(xs), gamma)
+        for k in range(3):
+            parts["pts"][k, 0] = cons[k]
+        return U
+    xl = grid.x0 + np.arange(grid.n1) * grid.dx
+    yl = grid.y0 + np.arange(grid.n2) * grid.dy
+    XL, YL = np.meshgrid(xl, yl)
+    acc = [np.zeros((grid.n2, grid.n1)) for _ in range(4)]
+    for a in range(nq):
+        for b in range(nq):
+            cons = conservative(prim_fn(XL + gx[a] * grid.dx, YL + gx[b] * grid.dy), gamma)
+            for k in range(4):
+                acc[k] += gw[a] * gw[b] * cons[k]
+    for k in range(4):
+        parts["avg"][k] = acc[k]
+    for name in ("xe", "ye", "co"):
+        X, Y = grid.point_coords(name)
+        cons = conservative(prim_fn(X, Y), gamma)
+        for k in range(4):
+            parts[name][k] = cons[k]
+    return U
+
+
+# ---------------------------------------------------------------------------
+# named workloads
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Physics:
+    gamma: float = 1.4
+    mu: float = 1e-3
+    Pr: float = 0.72
+
+
+def density_wave_1d(n: int, amp: float = 0.2):
+    """1D periodic [0,1]: rho = 1 + amp sin(2 pi x), u = 1, p = 1."""
+    g = Grid(dim=1, n1=n, bc=(PERIODIC, PERIODIC, PERIODIC, PERIODIC))
+
+    def f(x):
+        return (1.0 + amp * np.sin(2 * np.pi * x), np.ones_like(x), np.ones_like(x))
+    return g, f
+
+
+def vortex_wave_2d(n: int, strength: float = 0.5, r0: float = 0.1):
+    """2D periodic [0,1]^2: rho = 1 + 0.2 sin(2 pi (x+y)), (u,v) = (1,1) plus a
+    Gaussian vortex centred at (1/2,1/2) summed over the 3x3 periodic images,
+    p = 1."""
+    g = Grid(dim=2, n1=n, n2=n)
+
+    def f(x, y):
+        du = np.zeros_like(x)
+        dv = np.zeros_like(x)
+        for sx in (-1.0, 0.0, 1.0):
+            for sy in (-1.0, 0.0, 1.0):
+                xx = x - 0.5 - sx
+                yy = y - 0.5 - sy
+                psi = np.exp(-(xx * xx + yy * yy) / (2 * r0 * r0))
+                du += -strength * yy * psi / r0
+                dv += strength * xx * psi / r0
+        return (1.0 + 0.2 * np.sin(2 * np.pi * (x + y)), 1.0 + du, 1.0 + dv, np.ones_like(x))
+    return g, f
+
+
+def shock_tube_2d(n1: int = 1000, n2: int = 500, gamma: float = 1.4,
+                  rho_left: float = 120.0, rho_right: float = 1.2):
+    """Viscous shock tube on [0,1]x[0,0.5]: diaphragm at x=1/2 (a point on the
+    line x=1/2 takes the right state), p = rho/gamma, at rest; no-slip
+    adiabatic walls at x=0, x=1, y=0, symmetry at y=0.5."""
+    g = Grid(dim=2, n1=n1, n2=n2, x0=0.0, x1=1.0, y0=0.0, y1=0.5,
+             bc=(NOSLIP, NOSLIP, NOSLIP, SYMMETRY))
+
+    def f(x, y):
+        left = x < 0.5
+        r = np.where(left, rho_left, rho_right)
+        z = np.zeros_like(x)
+        return (r, z, z.copy(), r / gamma)
+    return g, f
+
+
+def leblanc_1d(n: int = 800):
+    """LeBlanc-type near-vacuum Riemann problem on [-0.5,0.5], outflow."""
+    g = Grid(dim=1, n1=n, x0=-0.5, x1=0.5, bc=(OUTFLOW, OUTFLOW, OUTFLOW, OUTFLOW))
+
+    def f(x):
+        left = x < -0.2
+        r = np.where(left, 1.0, 1e-2)
+        p = np.where(left, 6.666667e-2, 6.666667e-11)
+        return (r, np.zeros_like(x), p)
+    return g, f
+
+
+def random_smooth_2d(n1: int, n2: int, seed: int, bc=(PERIODIC,) * 4,
+                     x1: float = 1.0, y1: float = 1.0, amp: float = 0.1):
+    """Seeded smooth periodic-in-[0,1] field made of a few random Fourier
+    modes; admissible for amp <= 0.2."""
+    rng = np.random.default_rng(seed)
+    coef = rng.uniform(-1.0, 1.0, size=(4, 3, 4))
+    g = Grid(dim=2, n1=n1, n2=n2, x1=x1, y1=y1, bc=tuple(bc))
+
+    def field_(x, y, k):
+        s = np.zeros_like(x)
+        for m in range(3):
+            a, b, c, d = coef[k, m]
+            s += a * np.sin(2 * np.pi * ((m + 1) * x / x1 + b)) * np.cos(2 * np.pi * (m * y / y1 + c)) * (0.5 + 0.5 * d)
+        return s
+
+    def f(x, y):
+        return (1.0 + amp * field_(x, y, 0), 0.5 + amp * field_(x, y, 1),
+                -0.3 + amp * field_(x, y, 2), 1.0 + amp * field_(x, y, 3))
+    return g, f
