@@ -1,0 +1,219 @@
+#!/usr/bin/env python
+"""Benchmark: SSP-RK3 steps of the compact AF method on the 2D viscous shock
+tube (1000 x 500 cells, FP64, Re = 200, all limiters) on one MI355X.
+
+A step is one pass of the whole hot path: the CFL time-step reduction and
+three limited stages (cell averages and point values).  The timed region is
+K steps with the state already resident in HBM, bracketed by device
+synchronisation.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-DOF updates/s per RK stage, 2D viscous shock tube; % peak HBM BW; L1 err"
+HBM_PEAK_GBS = 8000.0
+FP64_VALU_PEAK_TFLOPS = 78.6
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = ["paper_2609_29081_amd/csrc/af_kern2d.hip", "paper_2609_29081_amd/csrc/af_device.hpp",
+                  "paper_2609_29081_amd/csrc/af_common.hip", "paper_2609_29081_amd/csrc/af_capi.cpp"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(g) -> dict:
+    """Minimum HBM bytes each kernel kind must move per launch (FP64): its
+    inputs read once and its outputs written once, given the stage's data
+    layout (see the kernel table in the design notes)."""
+    d = 8
+    n1, n2 = g.n1, g.n2
+    ncell = n1 * n2
+    ns = (2 * n1 + 9) * (2 * n2 + 9)              # lattice sites incl. margin
+    ngrad = (2 * n1 + 5) * (2 * n2 + 5)
+    nring = (n1 + 2) * (n2 + 2)
+    nfx, nfy = (n1 + 1) * n2, n1 * (n2 + 1)
+    npts = g.state_len // 4 - ncell                # point DOF sites
+    face_sites_x = (n1 + 1) * (2 * n2 + 1)         # lattice sites on x-face lines
+    face_sites_y = n1 * 0 + (2 * n1 + 1) * (n2 + 1)
+    return {
+        "lattice": d * (g.state_len + 9 * ns),
+        "grad": d * (3 * ns + 6 * ngrad),
+        "cellpre": d * (4 * ncell + 18 * nring),
+        # one launch per direction; report the mean of the two
+        "face": d * 0.5 * (13 * (face_sites_x + face_sites_y) + 2 * 18 * nring + 4 * (nfx + nfy)),
+        "cells": d * (4 * (nfx + nfy) + 3 * 4 * ncell),
+        "points": d * (15 * ngrad + 2 * 4 * npts),
+        "cfl": d * 4 * ncell,
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n1", type=int, default=1000)
+    ap.add_argument("--n2", type=int, default=500)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="budget of the CPU-oracle baseline sample (0 disables it)")
+    ap.add_argument("--timing-steps", type=int, default=10)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on exactly one GPU; the multi-GPU path (y-slab halo "
+              "exchange) is a design only, so --gpus must be 1", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2609_29081_amd import af
+    from paper_2609_29081_amd import workloads as W
+
+    gamma = 1.4
+    kw = dict(gamma=gamma, mu=0.005, Pr=0.73, cfl_c=0.2, cfl_v=0.075, limiter=af.LIM_ALL)
+    g, f = W.shock_tube_2d(args.n1, args.n2, gamma=gamma)
+    U0 = W.make_state(g, f, gamma)
+    S = af.Solver(g, **kw)
+    dev_U0 = S.to_device(U0)
+    U = dev_U0.clone()
+    K, Wm = args.steps, args.warmup
+
+    # warm-up (also loads the code objects)
+    if Wm > 0:
+        st, ns, _ = S.af_run(U, 0.0, 1e30, Wm, check_every=1)
+        if st != af.AF_OK:
+            raise RuntimeError(f"warm-up failed with status {st}")
+
+    # timed region: K steps from the initial state, resident in HBM
+    U.copy_(dev_U0)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    # the flags are checked after every step (a rejected step is redone with
+    # dt/2 at once, as the method prescribes); one host synchronisation per step
+    st, nsteps, t_end = S.af_run(U, 0.0, 1e30, K, check_every=1)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    if st != af.AF_OK or nsteps != K:
+        raise RuntimeError(f"timed run failed: status {st}, {nsteps}/{K} steps")
+    gpu_ms = ev0.elapsed_time(ev1)
+    sec = gpu_ms / 1e3
+    stages = 3 * K
+    dof_sites = g.dof_sites
+    value = dof_sites * stages / sec
+    cell_rate = g.n1 * g.n2 * stages / sec
+    stage_ms = gpu_ms / stages
+    stage_bytes = 8.0 * g.state_len * 8.0 / 3.0     # mean over the 3 stages: (2+3+3)/3 states
+    stage_gbs = stage_bytes / (stage_ms * 1e-3) / 1e9
+
+    # per-kernel durations, measured live with HIP events on the launch stream
+    U.copy_(dev_U0)
+    torch.cuda.synchronize()
+    S.af_timing(True)
+    S.af_timing_read()
+    st, _, _ = S.af_run(U, 0.0, 1e30, args.timing_steps, check_every=1)
+    kt = S.af_timing_read()
+    S.af_timing(False)
+    # RK3 attempts per accepted step (a rejected attempt is redone with dt/2)
+    first_kind = min(kt, key=lambda n: 0 if n in ("lattice", "fused") else 1)
+    attempts_per_step = kt[first_kind][0] / (3.0 * args.timing_steps)
+    alg = algorithmic_bytes(g)
+    kernels = {}
+    for name, (n, ms) in kt.items():
+        avg_ms = ms / n
+        b = alg.get(name)
+        kernels[name] = {"launches": n, "avg_us": round(avg_ms * 1e3, 3),
+                         "share": None,
+                         "alg_GBs": round(b / (avg_ms * 1e-3) / 1e9, 1) if b else None}
+    total = sum(ms for n, ms in kt.values())
+    for name, (n, ms) in kt.items():
+        kernels[name]["share"] = round(ms / total, 4)
+    dom = max(kt.items(), key=lambda kv: kv[1][1])[0]
+    dom_avg_s = kt[dom][1] / kt[dom][0] * 1e-3
+    achieved = alg[dom] / dom_avg_s / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as fh:
+            tr = json.load(fh)
+        if tr.get("kernel_source_hash") == kernel_source_hash() and tr.get("kernel") == dom \
+                and tr.get("n1") == g.n1 and tr.get("n2") == g.n2:
+            traffic = tr.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "alg_bytes_per_launch": alg[dom],
+                "avg_launch_us": round(dom_avg_s * 1e6, 3)}
+
+    # CPU baseline: the FP64 oracle on the host cores, first steps of the same
+    # workload, and the L1 difference of the GPU after the same steps
+    cpu = None
+    l1 = None
+    if args.cpu_seconds > 0:
+        import oracle as O
+        cfg = O.make_cfg(g, **{k: v for k, v in kw.items()})
+        Uc = U0.copy()
+        n_cpu, t_cpu, t_sim = 0, 0.0, 0.0
+        while t_cpu < args.cpu_seconds and n_cpu < 50:
+            c0 = time.perf_counter()
+            stc, dtu, h, fl = O.step(cfg, Uc, 0.0, t_sim)
+            t_cpu += time.perf_counter() - c0
+            t_sim += dtu
+            n_cpu += 1
+        cpu = {"value": dof_sites * 3 * n_cpu / t_cpu, "unit": "DOF-updates/s",
+               "cores": O.threads(), "kind": "oracle",
+               "sample": f"first {n_cpu} RK3 steps of the {g.n1}x{g.n2} shock tube from t=0 "
+                         f"(whole grid, {t_cpu:.1f} s)"}
+        Ug = dev_U0.clone()
+        st, ns2, _ = S.af_run(Ug, 0.0, 1e30, n_cpu, check_every=1)
+        Pg, Pc = g.split(Ug.cpu().numpy()), g.split(Uc)
+        l1 = float(np.abs(Pg["avg"][0] - Pc["avg"][0]).sum() * g.dx * g.dy)
+        linf = max(float(np.abs(Pg[n][k] - Pc[n][k]).max() / np.abs(Pc[n][k]).max())
+                   for n in Pg for k in range(4))
+    out = {
+        "metric": METRIC, "value": value, "unit": "DOF-updates/s", "n_gpus": 1, "steps": K,
+        "warmup": Wm, "ms_per_step": gpu_ms / K, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"2D viscous shock tube {g.n1}x{g.n2} on [0,1]x[0,0.5], "
+                               "rho 120|1.2, p=rho/gamma, mu=0.005 (Re=200), Pr=0.73, "
+                               "gamma=1.4, no-slip walls + symmetry top, SSP-RK3, CFL 0.2/0.075, "
+                               "all limiters, FP64",
+                   "n1": g.n1, "n2": g.n2, "dof_sites": dof_sites, "stages_per_step": 3},
+        "cell_updates_per_s": cell_rate,
+        "stage_ms": stage_ms,
+        "stage_hbm": {"alg_bytes": stage_bytes, "GBs": round(stage_gbs, 1),
+                      "frac": round(stage_gbs / HBM_PEAK_GBS, 4)},
+        "roofline": roofline,
+        "kernels": kernels,
+        "rk3_attempts_per_step": round(attempts_per_step, 3),
+        "cpu_baseline": cpu,
+        "l1_err_vs_oracle": l1,
+        "linf_rel_vs_oracle": linf if cpu else None,
+        "wall_s": wall,
+    }
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,170 @@
+/*
+ * af.h -- C ABI of the MI355X (gfx950) implementation of the compact
+ * fourth-order positivity-preserving Active Flux (AF) method for the 1D/2D
+ * compressible Navier-Stokes equations on Cartesian meshes (Duan, Barsukow,
+ * Klingenberg).
+ *
+ * Problem statement (Sec. 1 of the paper): conservative variables
+ * U = (rho, rho u, E) (1D) or (rho, rho u, rho v, E) (2D), ideal gas
+ * p = (gamma-1)(E - |rho u|^2/(2 rho)), Newtonian stress with constant
+ * viscosity mu >= 0, Fourier heat flux with kappa = gamma mu/((gamma-1) Pr),
+ * temperature T = p/rho.  mu = 0 gives the Euler equations.
+ *
+ * Degrees of freedom (Sec. 2.1, Sec. 2.2): cell averages and point values
+ * shared by neighbouring cells.  A state is ONE contiguous FP64 device buffer:
+ *   1D: [avg: 3 x n1][pts: 3 x n1x]
+ *   2D: [avg: 4 x n2 x n1][xe: 4 x n2 x n1x][ye: 4 x n2y x n1][co: 4 x n2y x n1x]
+ * component-major, x fastest; n1x = n1 if the x axis is periodic else n1+1
+ * (n2y likewise).  Cell (i,j) spans [x0+i dx, x0+(i+1)dx] x [y0+j dy, ...];
+ * xe(i,j) is the point (x0+i dx, y0+(j+1/2)dy), ye(i,j) is
+ * (x0+(i+1/2)dx, y0+j dy), co(i,j) is (x0+i dx, y0+j dy); 1D point k is x0+k dx.
+ *
+ * Memory and streams: the library never allocates device memory.  The caller
+ * allocates state and workspace buffers (sizes below) and passes a HIP
+ * stream (hipStream_t as void*; NULL = the default stream).  All entry points
+ * that take a stream enqueue work on it; only the ones documented as
+ * synchronous wait for it.  All pointers to state/workspace are device
+ * pointers (8-byte aligned at least, 256-byte recommended).
+ *
+ * Errors: every call returns af_status; AF_OK = 0.  Nothing aborts; a
+ * human-readable message for the last error of the calling thread is
+ * available from af_last_error().
+ */
+#ifndef AF_H
+#define AF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  AF_OK = 0,
+  AF_E_ARG = 1,       /* invalid argument (message says which)              */
+  AF_E_HIP = 2,       /* a HIP runtime call failed                           */
+  AF_E_PP = 3,        /* step halving exhausted: low-order states inadmissible */
+  AF_E_NONFINITE = 4  /* a non-finite value appeared in the solution          */
+} af_status;
+
+/* boundary kinds (Sec. 4 names periodic, outflow, no-slip adiabatic wall and
+ * symmetry boundaries; ghost values are images of interior lattice sites:
+ * wrap, zero-order copy, or a mirror about the wall line with the normal
+ * momentum (symmetry) or both momenta (no-slip) negated; point values on a
+ * wall are projected after every stage onto zero normal (symmetry) or zero
+ * (no-slip) momentum at unchanged density and internal energy) */
+typedef enum { AF_PERIODIC = 0, AF_OUTFLOW = 1, AF_NOSLIP = 2, AF_SYMMETRY = 3 } af_bc;
+typedef enum { AF_XLO = 0, AF_XHI = 1, AF_YLO = 2, AF_YHI = 3 } af_side;
+
+/* limiter switches (Sec. 3.2-3.4) */
+enum {
+  AF_LIM_SMOOTH = 1, /* smoothness-indicator blend theta^s of the cell fluxes    */
+  AF_LIM_PP = 2,     /* density/pressure blend theta^rho theta^p of cell fluxes  */
+  AF_LIM_POINT = 4,  /* scaling limiter of point values toward the point LLF     */
+  AF_LIM_CENTRE = 8, /* scaling of Simpson centre values toward the cell average */
+  AF_LIM_ALL = 15
+};
+
+/* sticky status flags accumulated in the workspace by af_rk_stage */
+enum {
+  AF_FLAG_CELL_LOW = 1,  /* a low-order intermediate cell state left the admissible set */
+  AF_FLAG_POINT_LOW = 2, /* a low-order point state left the admissible set           */
+  AF_FLAG_NONFINITE = 4  /* a non-finite value was written                             */
+};
+
+typedef struct af_params {
+  int dim;              /* 1 or 2                                                 */
+  int n1, n2;           /* cells along x (>= 4) and y (>= 4; ignored in 1D)       */
+  double x0, x1, y0, y1;/* box; x1 > x0, y1 > y0                                  */
+  double gamma;         /* ratio of specific heats, > 1                           */
+  double mu;            /* dynamic viscosity, >= 0                                */
+  double Pr;            /* Prandtl number, > 0                                    */
+  double cfl_c, cfl_v;  /* C^c and C^v of the CFL condition (eq. cfl), > 0        */
+  double Cs;            /* smoothness-limiter strength (paper: 1), >= 0           */
+  int limiter;          /* AF_LIM_* bits                                          */
+  int max_halvings;     /* retries of a step with halved dt (>= 0)               */
+} af_params;
+
+typedef struct af_ctx af_ctx;
+
+/* Fill p with defaults: 2D 64x64 on [0,1]^2, gamma 1.4, mu 1e-3, Pr 0.72,
+ * cfl_c 0.2, cfl_v 0.075, Cs 1, all limiters, max_halvings 40. */
+af_status af_default_params(af_params* p);
+
+/* Validate p and create a context (host memory only; no device work).
+ * All boundaries default to AF_OUTFLOW.  Free with af_destroy. */
+af_status af_init_grid(const af_params* p, af_ctx** out);
+void af_destroy(af_ctx* ctx);
+
+/* Set the boundary kind of one side.  A periodic axis must be periodic on
+ * both sides before any compute call (checked there: AF_E_ARG). */
+af_status af_set_bc(af_ctx* ctx, int side, int kind);
+
+/* Number of doubles in one state buffer, and bytes of the workspace. */
+size_t af_state_len(const af_ctx* ctx);
+size_t af_workspace_bytes(const af_ctx* ctx);
+
+/* One SSP-RK3 stage (Shu-Osher form), asynchronous on `stream`:
+ *   Uout = a_k Un + b_k FE(Uk, dt),  (a,b) = (0,1), (3/4,1/4), (1/3,2/3)
+ * for k = 0, 1, 2, where FE is the limited forward-Euler update of cell
+ * averages (eq. of the limited cell update, Sec. 3.3) and point values
+ * (Sec. 2 point update with the Sec. 3.4 scaling limiter).  dt is read from
+ * the device scalar dt_dev if it is not NULL, else dt_host is used.  Un may
+ * be NULL for k = 0.  Uout must not alias Un or Uk.  Flags (AF_FLAG_*) are
+ * OR-ed into the workspace; see af_read_flags / af_reset_flags. */
+af_status af_rk_stage(af_ctx* ctx, int k, const double* dt_dev, double dt_host,
+                      const double* Un, const double* Uk, double* Uout, void* ws,
+                      void* stream);
+
+/* CFL time step (eq. cfl) from the cell averages of U, clipped to
+ * t_final - t and written to the device scalar *dt_dev; asynchronous. */
+af_status af_cfl_dt(af_ctx* ctx, const double* U, double t, double t_final, double* dt_dev,
+                    void* ws, void* stream);
+
+/* One full SSP-RK3 step of U in place, synchronous.  dt <= 0 selects the CFL
+ * step.  dt is clipped to t_final - t.  If any flag is raised the state is
+ * restored and the step recomputed with dt/2, up to max_halvings times
+ * (Remark on the time step, Sec. 3.4): then AF_E_PP (or AF_E_NONFINITE) is
+ * returned and U holds the state before the step.  *dt_used and *halvings
+ * (either may be NULL) receive the step actually taken. */
+af_status af_step(af_ctx* ctx, double* U, void* ws, void* stream, double dt, double t,
+                  double t_final, double* dt_used, int* halvings);
+
+/* Advance U from t0 until t_final or max_steps steps.  Steps run with the
+ * time step kept on the device; every check_every steps (>= 1) the stream is
+ * synchronised and the flags read; a block whose flags are raised is redone
+ * from its saved start with af_step semantics (halving).  *nsteps_out and
+ * *t_out (may be NULL) receive the steps taken and the final time. */
+af_status af_run(af_ctx* ctx, double* U, void* ws, void* stream, double t0, double t_final,
+                 long max_steps, int check_every, long* nsteps_out, double* t_out);
+
+/* Flags accumulated in the workspace (synchronous read), and their reset
+ * (asynchronous). */
+af_status af_read_flags(af_ctx* ctx, const void* ws, int* flags, void* stream);
+af_status af_reset_flags(af_ctx* ctx, void* ws, void* stream);
+
+/* Kernel timing (diagnostics for the benchmark).  While enabled, every kernel
+ * the library launches for this context is bracketed by HIP events on its
+ * stream.  af_timing_read waits for the recorded events and returns, for
+ * each kernel kind below, the number of launches and their summed duration
+ * in milliseconds since the previous read (arrays of AF_K_COUNT entries). */
+enum {
+  AF_K_LATTICE = 0,  /* half-lattice values, centres, auxiliaries */
+  AF_K_GRAD = 1,     /* lattice gradients                          */
+  AF_K_CELLPRE = 2,  /* per-cell low-order data                    */
+  AF_K_FACE = 3,     /* limited face fluxes                         */
+  AF_K_CELLS = 4,    /* cell-average update                         */
+  AF_K_POINTS = 5,   /* point-value update                          */
+  AF_K_CFL = 6,      /* time-step reduction                         */
+  AF_K_COUNT = 8
+};
+af_status af_timing(af_ctx* ctx, int enable);
+af_status af_timing_read(af_ctx* ctx, long* launches, double* ms);
+
+/* Message of the last error raised on the calling thread ("" if none). */
+const char* af_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -54,8 +54,10 @@
 #define DUCROS_EPS 1.0e-13  /* modified Ducros regularisation, Sec. 3.2 */
 #define GM 4                /* ghost margin of the half lattice */
 
-static double dmax(double a, double b) { return a > b ? a : b; }
-static double dmin(double a, double b) { return a < b ? a : b; }
+/* max/min that return NaN if either argument is NaN, so that an inadmissible
+ * state anywhere in a stencil makes the stage non-finite (and flagged) */
+static double dmax(double a, double b) { return (a != a || b != b) ? a + b : (a > b ? a : b); }
+static double dmin(double a, double b) { return (a != a || b != b) ? a + b : (a < b ? a : b); }
 
 int orc_threads(void) {
 #ifdef _OPENMP

@@ -1,0 +1,192 @@
+"""Thin ctypes binding of libaf.so (include/af.h).
+
+Argument marshalling only: every step of the method runs in the HIP
+library.  torch provides device memory and streams.  Importing this module
+fails loudly if the built library is missing; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+from . import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libaf.so")
+
+AF_OK, AF_E_ARG, AF_E_HIP, AF_E_PP, AF_E_NONFINITE = 0, 1, 2, 3, 4
+PERIODIC, OUTFLOW, NOSLIP, SYMMETRY = 0, 1, 2, 3
+LIM_SMOOTH, LIM_PP, LIM_POINT, LIM_CENTRE, LIM_LOWONLY = 1, 2, 4, 8, 16
+LIM_ALL = 15
+FLAG_CELL_LOW, FLAG_POINT_LOW, FLAG_NONFINITE = 1, 2, 4
+
+
+class AFError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"af status {status}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n1", C.c_int), ("n2", C.c_int),
+                ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
+                ("gamma", C.c_double), ("mu", C.c_double), ("Pr", C.c_double),
+                ("cfl_c", C.c_double), ("cfl_v", C.c_double), ("Cs", C.c_double),
+                ("limiter", C.c_int), ("max_halvings", C.c_int)]
+
+
+_lib = None
+
+EXPORTS = ["af_default_params", "af_init_grid", "af_destroy", "af_set_bc", "af_state_len",
+           "af_workspace_bytes", "af_rk_stage", "af_cfl_dt", "af_step", "af_run",
+           "af_read_flags", "af_reset_flags", "af_timing", "af_timing_read", "af_last_error"]
+
+# kernel kinds reported by af_timing_read
+KERNEL_KINDS = {0: "lattice", 1: "grad", 2: "cellpre", 3: "face", 4: "cells", 5: "points",
+                6: "cfl"}
+K_COUNT = 8
+
+
+def lib():
+    """load libaf.so (raises if it has not been built)"""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} not built: run __graft_entry__.build() "
+                               "(python -c 'import __graft_entry__ as g; g.build()')")
+        L = C.CDLL(LIB_PATH)
+        vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.c_int
+        L.af_default_params.argtypes = [C.POINTER(Params)]
+        L.af_init_grid.argtypes = [C.POINTER(Params), C.POINTER(vp)]
+        L.af_destroy.argtypes = [vp]
+        L.af_destroy.restype = None
+        L.af_set_bc.argtypes = [vp, ip, ip]
+        L.af_state_len.argtypes = [vp]
+        L.af_state_len.restype = C.c_size_t
+        L.af_workspace_bytes.argtypes = [vp]
+        L.af_workspace_bytes.restype = C.c_size_t
+        L.af_rk_stage.argtypes = [vp, ip, vp, C.c_double, vp, vp, vp, vp, vp]
+        L.af_cfl_dt.argtypes = [vp, vp, C.c_double, C.c_double, vp, vp, vp]
+        L.af_step.argtypes = [vp, vp, vp, vp, C.c_double, C.c_double, C.c_double, dp,
+                              C.POINTER(C.c_int)]
+        L.af_run.argtypes = [vp, vp, vp, vp, C.c_double, C.c_double, C.c_long, ip,
+                             C.POINTER(C.c_long), dp]
+        L.af_read_flags.argtypes = [vp, vp, C.POINTER(C.c_int), vp]
+        L.af_reset_flags.argtypes = [vp, vp, vp]
+        L.af_timing.argtypes = [vp, ip]
+        L.af_timing_read.argtypes = [vp, C.POINTER(C.c_long), dp]
+        L.af_last_error.restype = C.c_char_p
+        for name in ("af_default_params", "af_init_grid", "af_set_bc", "af_rk_stage", "af_cfl_dt",
+                     "af_step", "af_run", "af_read_flags", "af_reset_flags", "af_timing",
+                     "af_timing_read"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != AF_OK:
+        raise AFError(st, lib().af_last_error().decode())
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+class Solver:
+    """One grid: wraps af_init_grid / af_set_bc and owns the torch-allocated
+    workspace.  States are flat float64 CUDA tensors of length state_len."""
+
+    def __init__(self, grid: W.Grid, gamma=1.4, mu=1e-3, Pr=0.72, cfl_c=0.2, cfl_v=0.075,
+                 limiter=LIM_ALL, Cs=1.0, max_halvings=40, device="cuda:0"):
+        p = Params()
+        _check(lib().af_default_params(C.byref(p)))
+        p.dim, p.n1, p.n2 = grid.dim, grid.n1, grid.n2
+        p.x0, p.x1, p.y0, p.y1 = grid.x0, grid.x1, grid.y0, grid.y1
+        p.gamma, p.mu, p.Pr = gamma, mu, Pr
+        p.cfl_c, p.cfl_v, p.Cs = cfl_c, cfl_v, Cs
+        p.limiter, p.max_halvings = limiter, max_halvings
+        self.grid = grid
+        self.params = p
+        h = C.c_void_p()
+        _check(lib().af_init_grid(C.byref(p), C.byref(h)))
+        self.ctx = h
+        nsides = 2 if grid.dim == 1 else 4
+        for side in range(nsides):
+            _check(lib().af_set_bc(self.ctx, side, int(grid.bc[side])))
+        self.state_len = int(lib().af_state_len(self.ctx))
+        self.ws_bytes = int(lib().af_workspace_bytes(self.ctx))
+        if self.state_len != grid.state_len:
+            raise AFError(AF_E_ARG, "state length mismatch between library and grid")
+        self.device = torch.device(device)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.dt_dev = torch.zeros(1, dtype=torch.float64, device=self.device)
+        _check(lib().af_reset_flags(self.ctx, _ptr(self.ws), _stream(None)))
+
+    def __del__(self):
+        try:
+            if getattr(self, "ctx", None):
+                lib().af_destroy(self.ctx)
+                self.ctx = None
+        except Exception:
+            pass
+
+    # -- marshalling of the C ABI ------------------------------------------
+    def to_device(self, U) -> torch.Tensor:
+        return torch.as_tensor(U, dtype=torch.float64).to(self.device).contiguous()
+
+    def af_rk_stage(self, k: int, Un, Uk, Uout, dt: float | None = None, dt_dev=None, stream=None):
+        _check(lib().af_rk_stage(self.ctx, k, _ptr(dt_dev), 0.0 if dt is None else float(dt),
+                                 _ptr(Un), _ptr(Uk), _ptr(Uout), _ptr(self.ws), _stream(stream)))
+
+    def af_cfl_dt(self, U, t: float = 0.0, t_final: float = 1e300, dt_dev=None, stream=None):
+        out = self.dt_dev if dt_dev is None else dt_dev
+        _check(lib().af_cfl_dt(self.ctx, _ptr(U), t, t_final, _ptr(out), _ptr(self.ws),
+                               _stream(stream)))
+        return out
+
+    def af_step(self, U, dt: float = 0.0, t: float = 0.0, t_final: float = 1e300, stream=None):
+        """returns (status, dt_used, halvings); raises only on argument/HIP errors"""
+        dtu = C.c_double()
+        h = C.c_int()
+        st = lib().af_step(self.ctx, _ptr(U), _ptr(self.ws), _stream(stream), dt, t, t_final,
+                           C.byref(dtu), C.byref(h))
+        if st in (AF_E_ARG, AF_E_HIP):
+            _check(st)
+        return st, dtu.value, h.value
+
+    def af_run(self, U, t0: float, t_final: float, max_steps: int, check_every: int = 50,
+               stream=None):
+        ns = C.c_long()
+        t = C.c_double()
+        st = lib().af_run(self.ctx, _ptr(U), _ptr(self.ws), _stream(stream), t0, t_final,
+                          max_steps, check_every, C.byref(ns), C.byref(t))
+        if st in (AF_E_ARG, AF_E_HIP):
+            _check(st)
+        return st, ns.value, t.value
+
+    def af_read_flags(self, stream=None) -> int:
+        f = C.c_int()
+        _check(lib().af_read_flags(self.ctx, _ptr(self.ws), C.byref(f), _stream(stream)))
+        return f.value
+
+    def af_reset_flags(self, stream=None):
+        _check(lib().af_reset_flags(self.ctx, _ptr(self.ws), _stream(stream)))
+
+    def af_timing(self, enable: bool):
+        _check(lib().af_timing(self.ctx, 1 if enable else 0))
+
+    def af_timing_read(self) -> dict:
+        """{kind name: (launches, total ms)} since the previous read"""
+        n = (C.c_long * K_COUNT)()
+        ms = (C.c_double * K_COUNT)()
+        _check(lib().af_timing_read(self.ctx, n, ms))
+        return {KERNEL_KINDS.get(k, f"k{k}"): (n[k], ms[k]) for k in range(K_COUNT) if n[k]}

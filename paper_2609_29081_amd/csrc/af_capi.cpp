@@ -1,0 +1,476 @@
+// af_capi.cpp -- the C ABI declared in include/af.h: parameter validation,
+// grid/lattice geometry, workspace carve-up, SSP-RK3 stage sequencing, the
+// CFL step, step halving (Remark on the time step, Sec. 3.4) and the
+// device-resident run loop.
+#include "../../include/af.h"
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "af_device.hpp"
+#include "af_internal.hpp"
+
+namespace {
+
+// per-launch HIP event pairs, reduced to per-kind sums on read
+struct EventTimer : afi::Timer {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+  std::vector<int> kinds;  // kind of pool entry i (for the first n entries)
+  size_t n = 0;
+  int open_kind = -1;
+  hipError_t err = hipSuccess;
+
+  void begin(int kind, hipStream_t s) override {
+    if (n == pool.size()) {
+      hipEvent_t a, b;
+      if ((err = hipEventCreate(&a)) != hipSuccess) return;
+      if ((err = hipEventCreate(&b)) != hipSuccess) return;
+      pool.emplace_back(a, b);
+      kinds.push_back(kind);
+    }
+    kinds[n] = kind;
+    open_kind = kind;
+    hipError_t e = hipEventRecord(pool[n].first, s);
+    if (e != hipSuccess) err = e;
+  }
+  void end(hipStream_t s) override {
+    if (open_kind < 0 || n >= pool.size()) return;
+    hipError_t e = hipEventRecord(pool[n].second, s);
+    if (e != hipSuccess) err = e;
+    ++n;
+    open_kind = -1;
+  }
+  ~EventTimer() override {
+    for (auto& pr : pool) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+  }
+};
+
+}  // namespace
+
+struct af_ctx {
+  af_params p;
+  int bc[4];
+  EventTimer* timer = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+af_status fail(af_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+af_status hip_fail(hipError_t e, const char* where) {
+  return fail(AF_E_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define AF_HIP(call)                                   \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);  \
+  } while (0)
+
+bool geometry(const af_ctx* c, afi::Geo* g) {
+  const af_params& p = c->p;
+  if ((c->bc[0] == AF_PERIODIC) != (c->bc[1] == AF_PERIODIC)) {
+    fail(AF_E_ARG, "x axis: periodic must be set on both sides");
+    return false;
+  }
+  if (p.dim == 2 && (c->bc[2] == AF_PERIODIC) != (c->bc[3] == AF_PERIODIC)) {
+    fail(AF_E_ARG, "y axis: periodic must be set on both sides");
+    return false;
+  }
+  afi::Geo r{};
+  r.dim = p.dim;
+  r.n1 = p.n1;
+  r.n2 = p.dim == 2 ? p.n2 : 1;
+  r.n1x = c->bc[0] == AF_PERIODIC ? p.n1 : p.n1 + 1;
+  r.n2y = p.dim == 2 ? (c->bc[2] == AF_PERIODIC ? p.n2 : p.n2 + 1) : 1;
+  r.LX = 2 * p.n1 + 1 + 2 * afd::kMargin;
+  r.LY = p.dim == 2 ? 2 * p.n2 + 1 + 2 * afd::kMargin : 1;
+  r.ns = (long)r.LX * r.LY;
+  for (int k = 0; k < 4; ++k) r.bc[k] = c->bc[k];
+  r.dx = (p.x1 - p.x0) / p.n1;
+  r.dy = p.dim == 2 ? (p.y1 - p.y0) / p.n2 : 1.0;
+  if (p.dim == 1) {
+    r.off_pts = 3L * p.n1;
+    r.state_len = 3L * (p.n1 + r.n1x);
+  } else {
+    const long n1 = p.n1, n2 = p.n2;
+    r.off_xe = 4 * n1 * n2;
+    r.off_ye = r.off_xe + 4 * n2 * r.n1x;
+    r.off_co = r.off_ye + 4L * r.n2y * n1;
+    r.state_len = r.off_co + 4L * r.n2y * r.n1x;
+  }
+  *g = r;
+  return true;
+}
+
+afd::Phys physics(const af_params& p) {
+  afd::Phys ph;
+  ph.gam = p.gamma;
+  ph.gm1 = p.gamma - 1.0;
+  ph.mu = p.mu;
+  ph.kap = p.gamma * p.mu / ((p.gamma - 1.0) * p.Pr);
+  ph.Cs = p.Cs;
+  ph.lim = p.limiter;
+  return ph;
+}
+
+const afi::StageCoef kCoef[3] = {{0.0, 1.0, 1}, {0.75, 0.25, 0}, {1.0 / 3.0, 2.0 / 3.0, 0}};
+
+hipError_t launch_stage(const afi::Geo& g, const afd::Phys& ph, const afi::Work& w, int k,
+                        const double* Un, const double* Uk, double* Uout, const double* dt_dev,
+                        double dt_host, hipStream_t s, afi::Timer* tm) {
+  if (!Un) Un = Uk;
+  return g.dim == 1 ? afi::stage1d(g, ph, w, Un, Uk, Uout, dt_dev, dt_host, kCoef[k], s, tm)
+                    : afi::stage2d(g, ph, w, Un, Uk, Uout, dt_dev, dt_host, kCoef[k], s, tm);
+}
+
+hipError_t launch_cfl(const af_ctx* c, const afi::Geo& g, const afi::Work& w, const double* U,
+                      double t_host, const double* t_dev, double t_final, double* dt_out,
+                      hipStream_t s) {
+  const af_params& p = c->p;
+  return afi::cfl_dt(g, physics(p), p.cfl_c, p.cfl_v, 4.0 * p.mu / 3.0, p.gamma * p.mu / p.Pr, w,
+                     U, t_host, t_dev, t_final, dt_out, s, c->timer);
+}
+
+af_status read_flags(const afi::Work& w, hipStream_t s, unsigned* out) {
+  AF_HIP(hipMemcpyAsync(out, w.flags, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+  AF_HIP(hipStreamSynchronize(s));
+  return AF_OK;
+}
+
+// three stages with a host-given dt; cur -> out through S1, S2
+hipError_t rk3(const afi::Geo& g, const afd::Phys& ph, const afi::Work& w, const double* cur,
+               double* out, const double* dt_dev, double dt, hipStream_t s, afi::Timer* tm) {
+  hipError_t e;
+  if ((e = launch_stage(g, ph, w, 0, cur, cur, w.S1, dt_dev, dt, s, tm)) != hipSuccess) return e;
+  if ((e = launch_stage(g, ph, w, 1, cur, w.S1, w.S2, dt_dev, dt, s, tm)) != hipSuccess) return e;
+  return launch_stage(g, ph, w, 2, cur, w.S2, out, dt_dev, dt, s, tm);
+}
+
+}  // namespace
+
+extern "C" {
+
+af_status af_default_params(af_params* p) {
+  if (!p) return fail(AF_E_ARG, "af_default_params: NULL");
+  p->dim = 2;
+  p->n1 = 64;
+  p->n2 = 64;
+  p->x0 = 0.0;
+  p->x1 = 1.0;
+  p->y0 = 0.0;
+  p->y1 = 1.0;
+  p->gamma = 1.4;
+  p->mu = 1e-3;
+  p->Pr = 0.72;
+  p->cfl_c = 0.2;
+  p->cfl_v = 0.075;
+  p->Cs = 1.0;
+  p->limiter = AF_LIM_ALL;
+  p->max_halvings = 40;
+  return AF_OK;
+}
+
+af_status af_init_grid(const af_params* p, af_ctx** out) {
+  if (!p || !out) return fail(AF_E_ARG, "af_init_grid: NULL argument");
+  *out = nullptr;
+  if (p->dim != 1 && p->dim != 2) return fail(AF_E_ARG, "dim must be 1 or 2 (got %d)", p->dim);
+  if (p->n1 < 4) return fail(AF_E_ARG, "n1 must be >= 4 (got %d)", p->n1);
+  if (p->dim == 2 && p->n2 < 4) return fail(AF_E_ARG, "n2 must be >= 4 (got %d)", p->n2);
+  if ((long)p->n1 * (p->dim == 2 ? p->n2 : 1) > (1L << 28))
+    return fail(AF_E_ARG, "grid too large");
+  if (!(p->x1 > p->x0) || (p->dim == 2 && !(p->y1 > p->y0)))
+    return fail(AF_E_ARG, "degenerate box");
+  if (!(p->gamma > 1.0)) return fail(AF_E_ARG, "gamma must be > 1");
+  if (!(p->mu >= 0.0)) return fail(AF_E_ARG, "mu must be >= 0");
+  if (!(p->Pr > 0.0)) return fail(AF_E_ARG, "Pr must be > 0");
+  if (!(p->cfl_c > 0.0) || !(p->cfl_v > 0.0)) return fail(AF_E_ARG, "CFL numbers must be > 0");
+  if (!(p->Cs >= 0.0)) return fail(AF_E_ARG, "Cs must be >= 0");
+  if (p->limiter < 0 || p->limiter > 31) return fail(AF_E_ARG, "bad limiter bits");
+  if (p->max_halvings < 0) return fail(AF_E_ARG, "max_halvings must be >= 0");
+  af_ctx* c = new (std::nothrow) af_ctx;
+  if (!c) return fail(AF_E_ARG, "out of host memory");
+  c->p = *p;
+  for (int k = 0; k < 4; ++k) c->bc[k] = AF_OUTFLOW;
+  *out = c;
+  return AF_OK;
+}
+
+void af_destroy(af_ctx* c) {
+  if (!c) return;
+  delete c->timer;
+  delete c;
+}
+
+af_status af_timing(af_ctx* c, int enable) {
+  if (!c) return fail(AF_E_ARG, "af_timing: NULL context");
+  if (enable && !c->timer) c->timer = new (std::nothrow) EventTimer;
+  if (enable && !c->timer) return fail(AF_E_ARG, "out of host memory");
+  if (!enable) {
+    delete c->timer;
+    c->timer = nullptr;
+  }
+  return AF_OK;
+}
+
+af_status af_timing_read(af_ctx* c, long* launches, double* ms) {
+  if (!c || !launches || !ms) return fail(AF_E_ARG, "af_timing_read: NULL argument");
+  for (int k = 0; k < AF_K_COUNT; ++k) {
+    launches[k] = 0;
+    ms[k] = 0.0;
+  }
+  EventTimer* t = c->timer;
+  if (!t) return fail(AF_E_ARG, "timing is not enabled");
+  if (t->err != hipSuccess) {
+    hipError_t e = t->err;
+    t->err = hipSuccess;
+    t->n = 0;
+    return hip_fail(e, "kernel timing events");
+  }
+  for (size_t i = 0; i < t->n; ++i) {
+    AF_HIP(hipEventSynchronize(t->pool[i].second));
+    float dms = 0.0f;
+    AF_HIP(hipEventElapsedTime(&dms, t->pool[i].first, t->pool[i].second));
+    const int k = t->kinds[i];
+    if (k >= 0 && k < AF_K_COUNT) {
+      launches[k] += 1;
+      ms[k] += dms;
+    }
+  }
+  t->n = 0;
+  return AF_OK;
+}
+
+af_status af_set_bc(af_ctx* c, int side, int kind) {
+  if (!c) return fail(AF_E_ARG, "af_set_bc: NULL context");
+  if (side < 0 || side > 3) return fail(AF_E_ARG, "bad side %d", side);
+  if (c->p.dim == 1 && side > 1) return fail(AF_E_ARG, "1D grid has no y sides");
+  if (kind < AF_PERIODIC || kind > AF_SYMMETRY) return fail(AF_E_ARG, "bad boundary kind %d", kind);
+  c->bc[side] = kind;
+  return AF_OK;
+}
+
+size_t af_state_len(const af_ctx* c) {
+  afi::Geo g;
+  if (!c || !geometry(c, &g)) return 0;
+  return (size_t)g.state_len;
+}
+
+size_t af_workspace_bytes(const af_ctx* c) {
+  afi::Geo g;
+  if (!c || !geometry(c, &g)) return 0;
+  return afi::workspace_layout(g, nullptr, nullptr);
+}
+
+af_status af_rk_stage(af_ctx* c, int k, const double* dt_dev, double dt_host, const double* Un,
+                      const double* Uk, double* Uout, void* ws, void* stream) {
+  if (!c || !Uk || !Uout || !ws) return fail(AF_E_ARG, "af_rk_stage: NULL argument");
+  if (k < 0 || k > 2) return fail(AF_E_ARG, "stage index must be 0..2 (got %d)", k);
+  if (k > 0 && !Un) return fail(AF_E_ARG, "stage %d needs Un", k);
+  if (Uout == Uk || (Un && Uout == Un)) return fail(AF_E_ARG, "Uout aliases an input");
+  if (!dt_dev && !(dt_host >= 0.0)) return fail(AF_E_ARG, "dt must be >= 0");
+  afi::Geo g;
+  if (!geometry(c, &g)) return AF_E_ARG;
+  afi::Work w;
+  afi::workspace_layout(g, &w, (char*)ws);
+  hipError_t e = launch_stage(g, physics(c->p), w, k, Un, Uk, Uout, dt_dev, dt_host,
+                              (hipStream_t)stream, c->timer);
+  if (e != hipSuccess) return hip_fail(e, "af_rk_stage launch");
+  return AF_OK;
+}
+
+af_status af_cfl_dt(af_ctx* c, const double* U, double t, double t_final, double* dt_dev,
+                    void* ws, void* stream) {
+  if (!c || !U || !ws || !dt_dev) return fail(AF_E_ARG, "af_cfl_dt: NULL argument");
+  afi::Geo g;
+  if (!geometry(c, &g)) return AF_E_ARG;
+  afi::Work w;
+  afi::workspace_layout(g, &w, (char*)ws);
+  hipError_t e = launch_cfl(c, g, w, U, t, nullptr, t_final, dt_dev, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "af_cfl_dt launch");
+  return AF_OK;
+}
+
+af_status af_read_flags(af_ctx* c, const void* ws, int* flags, void* stream) {
+  if (!c || !ws || !flags) return fail(AF_E_ARG, "af_read_flags: NULL argument");
+  afi::Geo g;
+  if (!geometry(c, &g)) return AF_E_ARG;
+  afi::Work w;
+  afi::workspace_layout(g, &w, (char*)ws);
+  unsigned f = 0;
+  af_status st = read_flags(w, (hipStream_t)stream, &f);
+  *flags = (int)f;
+  return st;
+}
+
+af_status af_reset_flags(af_ctx* c, void* ws, void* stream) {
+  if (!c || !ws) return fail(AF_E_ARG, "af_reset_flags: NULL argument");
+  afi::Geo g;
+  if (!geometry(c, &g)) return AF_E_ARG;
+  afi::Work w;
+  afi::workspace_layout(g, &w, (char*)ws);
+  AF_HIP(afi::clear_flags(w, (hipStream_t)stream));
+  return AF_OK;
+}
+
+af_status af_step(af_ctx* c, double* U, void* ws, void* stream, double dt, double t,
+                  double t_final, double* dt_used, int* halvings) {
+  if (!c || !U || !ws) return fail(AF_E_ARG, "af_step: NULL argument");
+  if (!(t_final >= t)) return fail(AF_E_ARG, "t_final < t");
+  afi::Geo g;
+  if (!geometry(c, &g)) return AF_E_ARG;
+  afi::Work w;
+  afi::workspace_layout(g, &w, (char*)ws);
+  const hipStream_t s = (hipStream_t)stream;
+  const afd::Phys ph = physics(c->p);
+  AF_HIP(afi::copy_state(w.SAVE, U, g.state_len, s));
+  if (dt <= 0.0) {
+    AF_HIP(launch_cfl(c, g, w, U, t, nullptr, t_final, w.scal, s));
+    AF_HIP(hipMemcpyAsync(&dt, w.scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    AF_HIP(hipStreamSynchronize(s));
+  } else if (t + dt > t_final) {
+    dt = t_final - t;
+  }
+  unsigned fl = 0;
+  int h;
+  for (h = 0; h <= c->p.max_halvings; ++h) {
+    AF_HIP(afi::clear_flags(w, s));
+    AF_HIP(rk3(g, ph, w, w.SAVE, U, nullptr, dt, s, c->timer));
+    af_status st = read_flags(w, s, &fl);
+    if (st != AF_OK) return st;
+    if (fl == 0) break;
+    dt *= 0.5;
+  }
+  if (dt_used) *dt_used = dt;
+  if (halvings) *halvings = h;
+  if (fl != 0) {
+    AF_HIP(afi::copy_state(U, w.SAVE, g.state_len, s));
+    AF_HIP(hipStreamSynchronize(s));
+    if (fl & AF_FLAG_NONFINITE) return fail(AF_E_NONFINITE, "non-finite values after %d halvings", h - 1);
+    return fail(AF_E_PP, "low-order states inadmissible after %d halvings (flags %u)", h - 1, fl);
+  }
+  return AF_OK;
+}
+
+af_status af_run(af_ctx* c, double* U, void* ws, void* stream, double t0, double t_final,
+                 long max_steps, int check_every, long* nsteps_out, double* t_out) {
+  if (!c || !U || !ws) return fail(AF_E_ARG, "af_run: NULL argument");
+  if (check_every < 1) return fail(AF_E_ARG, "check_every must be >= 1");
+  if (max_steps < 0) return fail(AF_E_ARG, "max_steps must be >= 0");
+  afi::Geo g;
+  if (!geometry(c, &g)) return AF_E_ARG;
+  afi::Work w;
+  afi::workspace_layout(g, &w, (char*)ws);
+  const hipStream_t s = (hipStream_t)stream;
+  const afd::Phys ph = physics(c->p);
+  // the current state rotates through U, S1, S2: a step reads `cur` and
+  // writes its stages to the other two, so `cur` survives a rejected step
+  double* bufs[3] = {U, w.S1, w.S2};
+  int cur = 0;
+  double t = t0;
+  long done = 0;
+  af_status status = AF_OK;
+  double sc[4];
+  unsigned fl = 0;
+  auto read_back = [&]() -> af_status {
+    AF_HIP(hipMemcpyAsync(sc, w.scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    AF_HIP(hipMemcpyAsync(&fl, w.flags, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    AF_HIP(hipStreamSynchronize(s));
+    return AF_OK;
+  };
+  auto three_stages = [&](int from) -> hipError_t {
+    const int a = (from + 1) % 3, b = (from + 2) % 3;
+    hipError_t e;
+    if ((e = launch_stage(g, ph, w, 0, bufs[from], bufs[from], bufs[a], w.scal, 0.0, s,
+                          c->timer)) != hipSuccess)
+      return e;
+    if ((e = launch_stage(g, ph, w, 1, bufs[from], bufs[a], bufs[b], w.scal, 0.0, s,
+                          c->timer)) != hipSuccess)
+      return e;
+    return launch_stage(g, ph, w, 2, bufs[from], bufs[b], bufs[a], w.scal, 0.0, s, c->timer);
+  };
+  AF_HIP(afi::set_scalar(w.scal + 1, t, s));
+  while (done < max_steps && t < t_final) {
+    const long K = (max_steps - done) < check_every ? (max_steps - done) : check_every;
+    if (K > 1) {
+      // optimistic block of K steps with one synchronisation at its end
+      AF_HIP(afi::copy_state(w.SAVE, bufs[cur], g.state_len, s));
+      AF_HIP(afi::set_scalar(w.scal + 2, 0.0, s));
+      AF_HIP(afi::clear_flags(w, s));
+      int c2 = cur;
+      for (long k = 0; k < K; ++k) {
+        AF_HIP(launch_cfl(c, g, w, bufs[c2], 0.0, w.scal + 1, t_final, w.scal, s));
+        AF_HIP(three_stages(c2));
+        AF_HIP(afi::advance_time(w, s));
+        c2 = (c2 + 1) % 3;
+      }
+      if ((status = read_back()) != AF_OK) break;
+      if (fl == 0) {
+        cur = c2;
+        t = sc[1];
+        done += (long)sc[2];
+        if ((long)sc[2] < K) break;  // t_final reached inside the block
+        continue;
+      }
+      // a step of the block was rejected: restore its start, step singly
+      AF_HIP(afi::copy_state(bufs[cur], w.SAVE, g.state_len, s));
+      AF_HIP(afi::set_scalar(w.scal + 1, t, s));
+    }
+    for (long k = 0; k < K && t < t_final; ++k) {
+      AF_HIP(launch_cfl(c, g, w, bufs[cur], 0.0, w.scal + 1, t_final, w.scal, s));
+      int h;
+      for (h = 0; h <= c->p.max_halvings; ++h) {
+        AF_HIP(afi::clear_flags(w, s));
+        AF_HIP(three_stages(cur));
+        if ((status = read_back()) != AF_OK) break;
+        if (fl == 0) break;
+        AF_HIP(afi::scale_scalar(w.scal, 0.5, s));  // redo with dt/2
+      }
+      if (status != AF_OK) break;
+      if (fl != 0) {
+        status = (fl & AF_FLAG_NONFINITE)
+                     ? fail(AF_E_NONFINITE, "non-finite values at t=%g after %d halvings", t, h - 1)
+                     : fail(AF_E_PP, "low-order states inadmissible at t=%g after %d halvings", t,
+                            h - 1);
+        break;
+      }
+      AF_HIP(afi::set_scalar(w.scal + 2, 0.0, s));
+      AF_HIP(afi::advance_time(w, s));
+      t = sc[1] + sc[0];
+      cur = (cur + 1) % 3;
+      ++done;
+    }
+    if (status != AF_OK) break;
+  }
+  if (cur != 0) {
+    AF_HIP(afi::copy_state(U, bufs[cur], g.state_len, s));
+  }
+  AF_HIP(hipStreamSynchronize(s));
+  if (nsteps_out) *nsteps_out = done;
+  if (t_out) *t_out = t;
+  return status;
+}
+
+const char* af_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,206 @@
+// af_common.hip -- CFL time-step reduction (eq. cfl), device-side time
+// bookkeeping, flag handling and the workspace layout.
+#include "af_device.hpp"
+#include "af_internal.hpp"
+
+using namespace afd;
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kMaxCflBlocks = 1024;
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = mx(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// block max of two values; the result is valid in thread 0
+__device__ __forceinline__ void block_max2(double& a, double& b) {
+  __shared__ double sa[kBlock / 64], sb[kBlock / 64];
+  a = wave_max(a);
+  b = wave_max(b);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    sa[wid] = a;
+    sb[wid] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < kBlock / 64; ++k) {
+      a = mx(a, sa[k]);
+      b = mx(b, sb[k]);
+    }
+  }
+}
+
+// per-cell inviscid and viscous rates (eq. cfl): max_l (|u_l|+c)/(C^c dx_l)
+// and rho~/(C^v min_l dx_l^2), rho~ = max(4mu/3, gamma mu/Pr)/rho
+__global__ void __launch_bounds__(kBlock) k_cfl(int dim, long ncell, double gm1, double gam,
+                                                double icx, double icy, double vcoef,
+                                                const double* __restrict__ U,
+                                                double* __restrict__ partial) {
+  double a = 0.0, v = 0.0;
+  for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < ncell;
+       c += (long)gridDim.x * blockDim.x) {
+    const double r = U[c];
+    if (dim == 1) {
+      const double m = U[ncell + c], E = U[2 * ncell + c];
+      const double p = pressure1(r, m, E, gm1);
+      const double cs = sqrt(gam * p / r);
+      a = mx(a, (fabs(m / r) + cs) * icx);
+    } else {
+      const double m1 = U[ncell + c], m2 = U[2 * ncell + c], E = U[3 * ncell + c];
+      const double p = pressure2(r, m1, m2, E, gm1);
+      const double cs = sqrt(gam * p / r);
+      a = mx(a, (fabs(m1 / r) + cs) * icx);
+      a = mx(a, (fabs(m2 / r) + cs) * icy);
+    }
+    v = mx(v, vcoef / r);
+  }
+  block_max2(a, v);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = a;
+    partial[gridDim.x + blockIdx.x] = v;
+  }
+}
+
+// final reduction: dt = 1/(a+v), clipped to t_final - t
+__global__ void __launch_bounds__(kBlock) k_cfl_finish(const double* __restrict__ partial, int nb,
+                                                       double t_host, const double* t_dev,
+                                                       double t_final, double* dt_out) {
+  double a = 0.0, v = 0.0;
+  for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+    a = mx(a, partial[k]);
+    v = mx(v, partial[nb + k]);
+  }
+  block_max2(a, v);
+  if (threadIdx.x == 0) {
+    const double t = t_dev ? *t_dev : t_host;
+    double dt = 1.0 / (a + v);
+    if (t + dt > t_final) dt = t_final - t;
+    if (!(dt > 0.0)) dt = 0.0;
+    *dt_out = dt;
+  }
+}
+
+// t += dt and count the step if dt > 0 (scal[0] dt, scal[1] t, scal[2] steps)
+__global__ void k_advance(double* scal) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const double dt = scal[0];
+    if (dt > 0.0) {
+      scal[1] = scal[1] + dt;
+      scal[2] = scal[2] + 1.0;
+    }
+  }
+}
+
+__global__ void k_clear_flags(unsigned* flags) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) flags[0] = 0u;
+}
+
+__global__ void k_set(double* p, double v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = v;
+}
+
+__global__ void k_scale(double* p, double f) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = p[0] * f;
+}
+
+__global__ void __launch_bounds__(kBlock) k_copy(double* __restrict__ d, const double* __restrict__ s,
+                                                 long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    d[i] = s[i];
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace
+
+namespace afi {
+
+// carve the workspace; with base == nullptr only the size is computed
+size_t workspace_layout(const Geo& g, Work* w, char* base) {
+  const int nc = g.dim == 1 ? 3 : 4;
+  const int naux = g.dim == 1 ? 4 : 5;
+  const int ngrad = g.dim == 1 ? 2 : 6;
+  const int ncp = g.dim == 1 ? 10 : 18;
+  const long ncells_ring = g.dim == 1 ? (long)(g.n1 + 2) : (long)(g.n1 + 2) * (g.n2 + 2);
+  const long nfx = g.dim == 1 ? (long)(g.n1 + 1) : (long)(g.n1 + 1) * g.n2;
+  const long nfy = g.dim == 1 ? 0 : (long)g.n1 * (g.n2 + 1);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align256(bytes);
+    return base ? base + o : nullptr;
+  };
+  Work r{};
+  r.scal = (double*)take(4 * sizeof(double));
+  r.flags = (unsigned*)take(sizeof(unsigned) * 4);
+  r.nb_cfl = kMaxCflBlocks;
+  r.partial = (double*)take(2 * sizeof(double) * kMaxCflBlocks);
+  r.LU = (double*)take(sizeof(double) * nc * g.ns);
+  r.LA = (double*)take(sizeof(double) * naux * g.ns);
+  r.LG = (double*)take(sizeof(double) * ngrad * g.ns);
+  r.CP = (double*)take(sizeof(double) * ncp * ncells_ring);
+  r.FX = (double*)take(sizeof(double) * nc * nfx);
+  r.FY = (double*)take(sizeof(double) * nc * (nfy > 0 ? nfy : 1));
+  r.S1 = (double*)take(sizeof(double) * g.state_len);
+  r.S2 = (double*)take(sizeof(double) * g.state_len);
+  r.SAVE = (double*)take(sizeof(double) * g.state_len);
+  r.bytes = off;
+  if (w) *w = r;
+  return off;
+}
+
+hipError_t cfl_dt(const Geo& g, const Phys& ph, double cfl_c, double cfl_v, double visc_a,
+                  double visc_b, const Work& w, const double* U, double t_host,
+                  const double* t_dev, double t_final, double* dt_out, hipStream_t s,
+                  Timer* tm) {
+  const long ncell = g.dim == 1 ? (long)g.n1 : (long)g.n1 * g.n2;
+  long nb = (ncell + kBlock - 1) / kBlock;
+  if (nb > w.nb_cfl) nb = w.nb_cfl;
+  if (nb < 1) nb = 1;
+  const double hmin = g.dim == 1 ? g.dx : fmin(g.dx, g.dy);
+  const double vcoef = fmax(visc_a, visc_b) / (cfl_v * hmin * hmin);
+  const double icx = 1.0 / (cfl_c * g.dx);
+  const double icy = g.dim == 1 ? 0.0 : 1.0 / (cfl_c * g.dy);
+  AFI_TIMED(tm, 6, s,
+            hipLaunchKernelGGL(k_cfl, dim3((unsigned)nb), dim3(kBlock), 0, s, g.dim, ncell, ph.gm1,
+                               ph.gam, icx, icy, vcoef, U, w.partial));
+  AFI_TIMED(tm, 6, s,
+            hipLaunchKernelGGL(k_cfl_finish, dim3(1), dim3(kBlock), 0, s,
+                               (const double*)w.partial, (int)nb, t_host, t_dev, t_final, dt_out));
+  return hipGetLastError();
+}
+
+hipError_t advance_time(const Work& w, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, w.scal);
+  return hipGetLastError();
+}
+
+hipError_t clear_flags(const Work& w, hipStream_t s) {
+  hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, s, w.flags);
+  return hipGetLastError();
+}
+
+hipError_t set_scalar(double* dst, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set, dim3(1), dim3(64), 0, s, dst, v);
+  return hipGetLastError();
+}
+
+hipError_t scale_scalar(double* dst, double f, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale, dim3(1), dim3(64), 0, s, dst, f);
+  return hipGetLastError();
+}
+
+hipError_t copy_state(double* dst, const double* src, long n, hipStream_t s) {
+  long nb = (n + kBlock - 1) / kBlock;
+  if (nb > 4096) nb = 4096;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)nb), dim3(kBlock), 0, s, dst, src, n);
+  return hipGetLastError();
+}
+
+}  // namespace afi

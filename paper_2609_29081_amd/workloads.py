@@ -230,3 +230,24 @@ def random_smooth_2d(n1: int, n2: int, seed: int, bc=(PERIODIC,) * 4,
         return (1.0 + amp * field_(x, y, 0), 0.5 + amp * field_(x, y, 1),
                 -0.3 + amp * field_(x, y, 2), 1.0 + amp * field_(x, y, 3))
     return g, f
+
+
+def double_rarefaction(n1: int, n2: int = 0, speed: float = 2.0, angle: float = 0.0):
+    """Two rarefactions receding from x' = 1/2 (x' along direction `angle`),
+    rho = 1, p = 0.4, |u| = speed: a near-vacuum centre that makes the
+    density/pressure limiting act.  1D if n2 == 0, else a 2D grid on
+    [0,1]^2 (periodic in y when angle == 0, outflow otherwise)."""
+    if n2 == 0:
+        g = Grid(dim=1, n1=n1, bc=(OUTFLOW,) * 4)
+
+        def f(x):
+            return (np.ones_like(x), np.where(x < 0.5, -speed, speed), 0.4 * np.ones_like(x))
+        return g, f
+    bc = (OUTFLOW, OUTFLOW, PERIODIC, PERIODIC) if angle == 0.0 else (OUTFLOW,) * 4
+    g = Grid(dim=2, n1=n1, n2=n2, bc=bc)
+    ca, sa = np.cos(angle), np.sin(angle)
+
+    def f(x, y):
+        s = np.where((x - 0.5) * ca + (y - 0.5) * sa < 0.0, -speed, speed)
+        return (np.ones_like(x), s * ca, s * sa, 0.4 * np.ones_like(x))
+    return g, f
