@@ -149,13 +149,14 @@ af_status af_reset_flags(af_ctx* ctx, void* ws, void* stream);
  * each kernel kind below, the number of launches and their summed duration
  * in milliseconds since the previous read (arrays of AF_K_COUNT entries). */
 enum {
-  AF_K_LATTICE = 0,  /* half-lattice values, centres, auxiliaries */
-  AF_K_GRAD = 1,     /* lattice gradients                          */
-  AF_K_CELLPRE = 2,  /* per-cell low-order data                    */
-  AF_K_FACE = 3,     /* limited face fluxes                         */
-  AF_K_CELLS = 4,    /* cell-average update                         */
-  AF_K_POINTS = 5,   /* point-value update                          */
-  AF_K_CFL = 6,      /* time-step reduction                         */
+  AF_K_LATTICE = 0,  /* 1D: half-lattice values, centres, auxiliaries */
+  AF_K_GRAD = 1,     /* 1D: lattice gradients                          */
+  AF_K_CELLPRE = 2,  /* 1D: per-cell low-order data                    */
+  AF_K_FACE = 3,     /* 1D: limited face fluxes                         */
+  AF_K_CELLS = 4,    /* 1D: cell-average update                         */
+  AF_K_POINTS = 5,   /* 1D: point-value update                          */
+  AF_K_CFL = 6,      /* time-step reduction                             */
+  AF_K_STAGE2D = 7,  /* 2D: the fused stage kernel                      */
   AF_K_COUNT = 8
 };
 af_status af_timing(af_ctx* ctx, int enable);

@@ -45,7 +45,7 @@ EXPORTS = ["af_default_params", "af_init_grid", "af_destroy", "af_set_bc", "af_s
 
 # kernel kinds reported by af_timing_read
 KERNEL_KINDS = {0: "lattice", 1: "grad", 2: "cellpre", 3: "face", 4: "cells", 5: "points",
-                6: "cfl"}
+                6: "cfl", 7: "stage2d"}
 K_COUNT = 8
 
 

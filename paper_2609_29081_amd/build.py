@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libaf.so")
-SOURCES = ["af_capi.cpp", "af_common.hip", "af_kern1d.hip", "af_kern2d.hip"]
+SOURCES = ["af_capi.cpp", "af_common.hip", "af_kern1d.hip", "af_stage2d.hip"]
 ARCH = "gfx950"
 
 

@@ -140,12 +140,16 @@ size_t workspace_layout(const Geo& g, Work* w, char* base) {
   r.flags = (unsigned*)take(sizeof(unsigned) * 4);
   r.nb_cfl = kMaxCflBlocks;
   r.partial = (double*)take(2 * sizeof(double) * kMaxCflBlocks);
-  r.LU = (double*)take(sizeof(double) * nc * g.ns);
-  r.LA = (double*)take(sizeof(double) * naux * g.ns);
-  r.LG = (double*)take(sizeof(double) * ngrad * g.ns);
-  r.CP = (double*)take(sizeof(double) * ncp * ncells_ring);
-  r.FX = (double*)take(sizeof(double) * nc * nfx);
-  r.FY = (double*)take(sizeof(double) * nc * (nfy > 0 ? nfy : 1));
+  if (g.dim == 1) {
+    // the 1D stage passes its lattice, gradient, cell and face data through
+    // device memory; the 2D stage keeps them in LDS
+    r.LU = (double*)take(sizeof(double) * nc * g.ns);
+    r.LA = (double*)take(sizeof(double) * naux * g.ns);
+    r.LG = (double*)take(sizeof(double) * ngrad * g.ns);
+    r.CP = (double*)take(sizeof(double) * ncp * ncells_ring);
+    r.FX = (double*)take(sizeof(double) * nc * nfx);
+    r.FY = (double*)take(sizeof(double) * nc * (nfy > 0 ? nfy : 1));
+  }
   r.S1 = (double*)take(sizeof(double) * g.state_len);
   r.S2 = (double*)take(sizeof(double) * g.state_len);
   r.SAVE = (double*)take(sizeof(double) * g.state_len);

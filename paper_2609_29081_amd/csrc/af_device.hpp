@@ -75,7 +75,9 @@ __device__ __forceinline__ void mirror_signs(int kind, int ax, double& sx, doubl
 // (1-t) zL + t zH >= eps, for zL >= eps.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double theta_lin(double zL, double zH, double eps) {
-  return (zH < eps) ? (zL - eps) / (zL - zH) : 1.0;
+  // the division only where the limiter acts (a branch, not a select)
+  if (zH < eps) return (zL - eps) / (zL - zH);
+  return 1.0;
 }
 
 __device__ __forceinline__ double pressure2(double r, double mx, double my, double E, double gm1) {
@@ -202,6 +204,21 @@ __device__ __forceinline__ double bvisc2(int d, double rho, double p, double ux,
   const double re = p / ph.gm1;
   const double e = re / rho;
   return (sqrt(q * q + 2.0 * e * t2) + fabs(q)) / (2.0 * re);
+}
+
+// both b_x and b_y with shared terms: e = T/(gamma-1), 1/(2 rho e) =
+// (gamma-1)/(2 p); one division for the pair
+__device__ __forceinline__ void bvisc2_xy(double p, double T, double ux, double vx, double Tx,
+                                          double uy, double vy, double Ty, const Phys& ph,
+                                          double& bx, double& by) {
+  const double txx = ph.mu * ((4.0 / 3.0) * ux - (2.0 / 3.0) * vy);
+  const double tyy = ph.mu * ((4.0 / 3.0) * vy - (2.0 / 3.0) * ux);
+  const double txy = ph.mu * (uy + vx);
+  const double qx = ph.kap * Tx, qy = ph.kap * Ty;
+  const double e2 = 2.0 * T / ph.gm1;
+  const double inv = 0.5 * ph.gm1 / p;
+  bx = (sqrt(qx * qx + e2 * (txx * txx + txy * txy)) + fabs(qx)) * inv;
+  by = (sqrt(qy * qy + e2 * (txy * txy + tyy * tyy)) + fabs(qy)) * inv;
 }
 
 __device__ __forceinline__ double bvisc1(double rho, double p, double ux, double Tx,

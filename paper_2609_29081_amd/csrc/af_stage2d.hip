@@ -1,0 +1,709 @@
+// af_stage2d.hip -- one SSP-RK3 stage of the 2D compact AF method on gfx950
+// as a single fused, LDS-tiled kernel (FP64).
+//
+// A workgroup owns a tile of TX x TY cells, i.e. the half-lattice block
+// [X0, X0+2TX) x [Y0, Y0+2TY): the cell averages, x-edge, y-edge and corner
+// point values inside it.  It stages everything the stage needs for that
+// block in LDS and writes only the stage output:
+//   phase 0  lattice values on the block +- 4 half cells: ghosts as boundary
+//            images, Simpson centres scaled toward the cell average (Sec. 2.2;
+//            Remark after the pressure blend, Sec. 3.3), and (u, v, p, T, c)
+//   phase 1  D_c gradients of (u, v, T) and the viscous speeds b_x, b_y on the
+//            block +- 2 (Sec. 2.2 central operator; viscous splitting lemma)
+//   phase 2  low-order data of the cells of the tile +- 1: S, F_l, |u_l|+c,
+//            b_l, the two smoothness sensors (Sec. 3.1, Sec. 3.2)
+//   phase 3  limited face fluxes of the tile's cells: Simpson high-order
+//            flux, LLF low-order flux, theta^s, theta^rho theta^p (Sec. 3.3)
+//   phase 4  cell-average update and RK combination
+//   phase 5  point residual (biased inviscid operators with the downwind
+//            point, compact D^2, mixed terms; Sec. 2.2), point LLF and scaling
+//            limiter (Sec. 3.4), wall projection, RK combination
+#include "af_device.hpp"
+#include "af_internal.hpp"
+
+using namespace afd;
+
+namespace {
+
+// tile shape: 16 x 7 cells, 512 threads (eight wave64s, two per SIMD); the
+// lattice region then holds <= 2 sites per thread
+constexpr int TX = 16, TY = 7, NT = 512;
+// lattice region [X0-4, X0+2TX+4] x [Y0-4, Y0+2TY+4]: both edges are face
+// lines, so every centre inside has its eight neighbours inside
+constexpr int WA = 2 * TX + 9, HA = 2 * TY + 9, NA = WA * HA;
+constexpr int WG = 2 * TX + 4, HG = 2 * TY + 4, NG = WG * HG;  // block +- 2
+constexpr int WC = TX + 2, HC = TY + 2, NC = WC * HC;          // tile cells +- 1
+constexpr int NFX = TY * (TX + 1), NFY = (TY + 1) * TX;
+
+struct G2 {
+  int n1, n2, n1x, n2y;
+  long off_xe, off_ye, off_co;
+  int bc0, bc1, bc2, bc3;
+  double dx, dy;
+};
+
+G2 make_g2(const afi::Geo& g) {
+  G2 r;
+  r.n1 = g.n1;
+  r.n2 = g.n2;
+  r.n1x = g.n1x;
+  r.n2y = g.n2y;
+  r.off_xe = g.off_xe;
+  r.off_ye = g.off_ye;
+  r.off_co = g.off_co;
+  r.bc0 = g.bc[0];
+  r.bc1 = g.bc[1];
+  r.bc2 = g.bc[2];
+  r.bc3 = g.bc[3];
+  r.dx = g.dx;
+  r.dy = g.dy;
+  return r;
+}
+
+// interior point DOF (X, Y not both odd), periodic seam folded
+__device__ __forceinline__ double dof(const G2& g, const double* __restrict__ U, int X, int Y,
+                                      int k) {
+  if (X == 2 * g.n1 && g.n1x == g.n1) X = 0;
+  if (Y == 2 * g.n2 && g.n2y == g.n2) Y = 0;
+  if (Y & 1) return U[g.off_xe + ((long)k * g.n2 + (Y >> 1)) * g.n1x + (X >> 1)];
+  if (X & 1) return U[g.off_ye + ((long)k * g.n2y + (Y >> 1)) * g.n1 + (X >> 1)];
+  return U[g.off_co + ((long)k * g.n2y + (Y >> 1)) * g.n1x + (X >> 1)];
+}
+
+__device__ __forceinline__ double avg(const G2& g, const double* __restrict__ U, int i, int j,
+                                      int k) {
+  return U[((long)k * g.n2 + j) * g.n1 + i];
+}
+
+// Simpson centre value from the cell average, the sum of the four edge
+// points and the sum of the four corners (Sec. 2.2), scaled toward the
+// average with the density-then-pressure rule when the centre limiter is on
+__device__ __forceinline__ void centre_value(const Phys& ph, const double* Ub, const double* e,
+                                             const double* c, double* V) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) V[k] = (36.0 * Ub[k] - 4.0 * e[k] - c[k]) / 16.0;
+  if (ph.lim & LIM_CENTRE) {
+    if (!(Ub[0] > 0.0)) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) V[k] = Ub[k];
+    } else {
+      bool bad = false;
+      const double th = theta_pair2(Ub, V, ph.gm1, bad);
+      if (th < 1.0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) V[k] = Ub[k] + th * (V[k] - Ub[k]);
+      }
+    }
+  }
+}
+
+// conservative value at lattice site (X, Y), X in [-4, 2n1+4], from device
+// memory: ghosts are images of interior sites, centres are Simpson values
+// scaled toward the cell average
+__device__ __forceinline__ void lattice_value(const G2& g, const Phys& ph,
+                                              const double* __restrict__ U, int X, int Y,
+                                              double* V) {
+  int kx, ky;
+  const int Xi = axis_image(X, 2 * g.n1, g.bc0, g.bc1, kx);
+  const int Yi = axis_image(Y, 2 * g.n2, g.bc2, g.bc3, ky);
+  double sx = 1.0, sy = 1.0;
+  mirror_signs(kx, 0, sx, sy);
+  mirror_signs(ky, 1, sx, sy);
+  if ((Xi & 1) && (Yi & 1)) {
+    const int i = Xi >> 1, j = Yi >> 1;
+    double Ub[4], e[4], c[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      Ub[k] = avg(g, U, i, j, k);
+      e[k] = dof(g, U, Xi - 1, Yi, k) + dof(g, U, Xi + 1, Yi, k) + dof(g, U, Xi, Yi - 1, k) +
+             dof(g, U, Xi, Yi + 1, k);
+      c[k] = dof(g, U, Xi - 1, Yi - 1, k) + dof(g, U, Xi + 1, Yi - 1, k) +
+             dof(g, U, Xi - 1, Yi + 1, k) + dof(g, U, Xi + 1, Yi + 1, k);
+    }
+    centre_value(ph, Ub, e, c, V);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) V[k] = dof(g, U, Xi, Yi, k);
+  }
+  V[1] *= sx;
+  V[2] *= sy;
+}
+
+// per-cell low-order data (Sec. 3.1-3.2):
+//   o[0..3] F_x, o[4..7] F_y (total fluxes with S = central differences of
+//   Z(average)), o[8] |u|+c, o[9] |v|+c, o[10] b_x, o[11] b_y, o[12] phi1,
+//   o[13] phi2, o[14..17] the cell average; from the averages of the cell
+//   and of its four neighbours (ghost cells as boundary images)
+__device__ __forceinline__ void cell_low(const G2& g, const Phys& ph, const double* C0,
+                                         const double* Cxm, const double* Cxp, const double* Cym,
+                                         const double* Cyp, double* o) {
+  // one reciprocal density per cell
+  const double r0 = 1.0 / C0[0], rxm = 1.0 / Cxm[0], rxp = 1.0 / Cxp[0], rym = 1.0 / Cym[0],
+               ryp = 1.0 / Cyp[0];
+  auto pr = [&](const double* V, double ir) {
+    return ph.gm1 * (V[3] - 0.5 * (V[1] * V[1] + V[2] * V[2]) * ir);
+  };
+  const double p0 = pr(C0, r0), pxm = pr(Cxm, rxm), pxp = pr(Cxp, rxp), pym = pr(Cym, rym),
+               pyp = pr(Cyp, ryp);
+  const double u0 = C0[1] * r0, v0 = C0[2] * r0;
+  const double i2x = 1.0 / (2.0 * g.dx), i2y = 1.0 / (2.0 * g.dy);
+  const double ux = (Cxp[1] * rxp - Cxm[1] * rxm) * i2x;
+  const double vx = (Cxp[2] * rxp - Cxm[2] * rxm) * i2x;
+  const double Tx = (pxp * rxp - pxm * rxm) * i2x;
+  const double uy = (Cyp[1] * ryp - Cym[1] * rym) * i2y;
+  const double vy = (Cyp[2] * ryp - Cym[2] * rym) * i2y;
+  const double Ty = (pyp * ryp - pym * rym) * i2y;
+  const double c0 = sqrt(ph.gam * p0 * r0);
+  double Fv[4];
+  visc_flux2(0, u0, v0, ux, vx, Tx, uy, vy, Ty, ph, Fv);
+  o[0] = C0[1] - Fv[0];
+  o[1] = C0[1] * u0 + p0 - Fv[1];
+  o[2] = C0[2] * u0 - Fv[2];
+  o[3] = (C0[3] + p0) * u0 - Fv[3];
+  visc_flux2(1, u0, v0, ux, vx, Tx, uy, vy, Ty, ph, Fv);
+  o[4] = C0[2] - Fv[0];
+  o[5] = C0[1] * v0 - Fv[1];
+  o[6] = C0[2] * v0 + p0 - Fv[2];
+  o[7] = (C0[3] + p0) * v0 - Fv[3];
+  o[8] = fabs(u0) + c0;
+  o[9] = fabs(v0) + c0;
+  bvisc2_xy(p0, p0 * r0, ux, vx, Tx, uy, vy, Ty, ph, o[10], o[11]);
+  const double jx = fabs(pxp - 2.0 * p0 + pxm) / fabs(pxp + 2.0 * p0 + pxm);
+  const double jy = fabs(pyp - 2.0 * p0 + pym) / fabs(pyp + 2.0 * p0 + pym);
+  o[12] = mx(jx, jy);
+  const double div = ux + vy, curl = vx - uy;
+  o[13] = mx(-div / sqrt(div * div + curl * curl + kDucros), 0.0);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) o[14 + k] = C0[k];
+}
+
+// wall projection of a point value (no-slip: zero momentum; symmetry: zero
+// normal momentum; density and internal energy kept)
+__device__ __forceinline__ void project(int kind, int ax, double* V) {
+  if (kind == BC_NOSLIP) {
+    V[3] -= (V[1] * V[1] + V[2] * V[2]) / (2.0 * V[0]);
+    V[1] = 0.0;
+    V[2] = 0.0;
+  } else if (kind == BC_SYMMETRY) {
+    V[3] -= V[1 + ax] * V[1 + ax] / (2.0 * V[0]);
+    V[1 + ax] = 0.0;
+  }
+}
+
+__device__ __forceinline__ int wall_of(int bc) {
+  return (bc == BC_NOSLIP || bc == BC_SYMMETRY) ? bc : -1;
+}
+
+// LDS-resident tile data
+struct Tile {
+  double U[4][NA];   // conservative values, block +- 4
+  double A[5][NA];   // u, v, p, T, c
+  double G[6][NG];   // du/dx dv/dx dT/dx du/dy dv/dy dT/dy, block +- 2
+  double B[2][NG];   // b_x, b_y
+  double C[18][NC];  // cell low-order data, tile +- 1
+  double FX[4][NFX]; // limited x-face fluxes of the tile's cells
+  double FY[4][NFY]; // limited y-face fluxes
+};
+
+// auxiliaries (u, v, p, T, c) of LDS lattice site s
+__device__ __forceinline__ void store_aux(Tile& T, const Phys& ph, int s) {
+  const double r = T.U[0][s], m1 = T.U[1][s], m2 = T.U[2][s], E = T.U[3][s];
+  const double ir = 1.0 / r;
+  const double p = ph.gm1 * (E - 0.5 * (m1 * m1 + m2 * m2) * ir);
+  const double Tt = p * ir;
+  T.A[0][s] = m1 * ir;
+  T.A[1][s] = m2 * ir;
+  T.A[2][s] = p;
+  T.A[3][s] = Tt;
+  T.A[4][s] = sqrt(ph.gam * Tt);
+}
+
+// total flux F_d = F^c_d - F^v_d at an LDS site (a: block+-4 index, q: block+-2 index)
+__device__ __forceinline__ void site_flux(const Tile& T, const Phys& ph, int a, int q, int d,
+                                          double* F) {
+  const double m1 = T.U[1][a], m2 = T.U[2][a], E = T.U[3][a];
+  const double u = T.A[0][a], v = T.A[1][a], p = T.A[2][a];
+  double Fv[4];
+  visc_flux2(d, u, v, T.G[0][q], T.G[1][q], T.G[2][q], T.G[3][q], T.G[4][q], T.G[5][q], ph, Fv);
+  const double ud = d == 0 ? u : v;
+  F[0] = (d == 0 ? m1 : m2) - Fv[0];
+  F[1] = m1 * ud + (d == 0 ? p : 0.0) - Fv[1];
+  F[2] = m2 * ud + (d == 1 ? p : 0.0) - Fv[2];
+  F[3] = (E + p) * ud - Fv[3];
+}
+
+// low-order LLF flux along d between LDS sites (a0,q0) (minus) and (a1,q1)
+__device__ __forceinline__ void llf_pair(const Tile& T, const Phys& ph, int a0, int q0, int a1,
+                                         int q1, int d, double* F) {
+  double Fa[4], Fb[4];
+  site_flux(T, ph, a0, q0, d, Fa);
+  site_flux(T, ph, a1, q1, d, Fb);
+  const double ra = fabs(T.A[d][a0]) + T.A[4][a0];
+  const double rb = fabs(T.A[d][a1]) + T.A[4][a1];
+  const double lam = mx(ra, rb) + mx(T.B[d][q0], T.B[d][q1]);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) F[k] = 0.5 * (Fa[k] + Fb[k]) - 0.5 * lam * (T.U[k][a1] - T.U[k][a0]);
+}
+
+// raw values of the lattice region of the tile at (X0, Y0): point sites hold
+// their DOF, centre sites the cell average, ghosts as boundary images.  Each
+// thread gathers the sites tid, tid+NT, tid+2NT into registers.
+constexpr int kRawPerThread = (NA + NT - 1) / NT;
+
+__device__ __forceinline__ void load_raw(const G2& g, const double* __restrict__ Uk, int X0, int Y0,
+                                         int tid, double (&pre)[kRawPerThread][4]) {
+  const int Xlim = 2 * g.n1, Ylim = 2 * g.n2;
+#pragma unroll
+  for (int r = 0; r < kRawPerThread; ++r) {
+    const int s = tid + r * NT;
+    const int X = X0 - 4 + s % WA, Y = Y0 - 4 + s / WA;
+    if (s >= NA || X > Xlim + kMargin || Y > Ylim + kMargin) continue;
+    int kx, ky;
+    const int Xi = axis_image(X, Xlim, g.bc0, g.bc1, kx);
+    const int Yi = axis_image(Y, Ylim, g.bc2, g.bc3, ky);
+    double sx = 1.0, sy = 1.0;
+    mirror_signs(kx, 0, sx, sy);
+    mirror_signs(ky, 1, sx, sy);
+    const bool centre = (Xi & 1) && (Yi & 1);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double v = centre ? avg(g, Uk, Xi >> 1, Yi >> 1, k) : dof(g, Uk, Xi, Yi, k);
+      pre[r][k] = k == 1 ? sx * v : (k == 2 ? sy * v : v);
+    }
+  }
+}
+
+// Tiles are visited by persistent workgroups.  Workgroups are dispatched to
+// the eight XCDs round-robin by index, so the tiles are cut into eight
+// contiguous bands, one per XCD: neighbouring tiles (whose lattice regions
+// overlap) are then read through the same L2.
+struct TileIter {
+  int cur, end, step;
+  __device__ TileIter(int ntiles, int wg, int nwg) {
+    if (nwg >= 8 && nwg % 8 == 0) {
+      const int xcd = wg % 8, local = wg / 8;
+      cur = (int)((long)xcd * ntiles / 8) + local;
+      end = (int)((long)(xcd + 1) * ntiles / 8);
+      step = nwg / 8;
+    } else {
+      cur = wg;
+      end = ntiles;
+      step = nwg;
+    }
+  }
+  __device__ int get() const { return cur < end ? cur : -1; }
+  __device__ int advance() {
+    cur += step;
+    return get();
+  }
+};
+
+__global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __restrict__ Uk,
+                                              const double* __restrict__ Un,
+                                              double* __restrict__ Uout, const double* dt_dev,
+                                              double dt_host, double ca, double cb, int first,
+                                              unsigned* flags, int ntx, int ntiles) {
+  __shared__ Tile T;
+  const int tid = threadIdx.x;
+  const double dt = dt_dev ? *dt_dev : dt_host;
+  const int Xlim = 2 * g.n1, Ylim = 2 * g.n2;
+  bool nonfinite = false;
+  TileIter it(ntiles, blockIdx.x, gridDim.x);
+  int tile = it.get();
+  double pre[kRawPerThread][4];
+  if (tile >= 0) load_raw(g, Uk, 2 * TX * (tile % ntx), 2 * TY * (tile / ntx), tid, pre);
+  while (tile >= 0) {
+  const int i0 = (tile % ntx) * TX, j0 = (tile / ntx) * TY;
+  const int X0 = 2 * i0, Y0 = 2 * j0;
+  __syncthreads();  // the previous tile is done with the LDS
+
+  // ---- phase 0a: raw values of the lattice region (prefetched) ----
+#pragma unroll
+  for (int r = 0; r < kRawPerThread; ++r) {
+    const int s = tid + r * NT;
+    const int X = X0 - 4 + s % WA, Y = Y0 - 4 + s / WA;
+    if (s >= NA || X > Xlim + kMargin || Y > Ylim + kMargin) continue;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) T.U[k][s] = pre[r][k];
+  }
+  __syncthreads();
+
+  // ---- phase 2: cell low-order data (tile +- 1) from the averages held in
+  //      the centre slots; auxiliaries of the point sites ----
+  for (int s = tid; s < NC; s += NT) {
+    const int i = i0 - 1 + s % WC, j = j0 - 1 + s / WC;
+    if (i > g.n1 || j > g.n2) continue;
+    const int a = (2 * j + 1 - Y0 + 4) * WA + (2 * i + 1 - X0 + 4);
+    double C0[4], Cxm[4], Cxp[4], Cym[4], Cyp[4], o[18];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      C0[k] = T.U[k][a];
+      Cxm[k] = T.U[k][a - 2];
+      Cxp[k] = T.U[k][a + 2];
+      Cym[k] = T.U[k][a - 2 * WA];
+      Cyp[k] = T.U[k][a + 2 * WA];
+    }
+    cell_low(g, ph, C0, Cxm, Cxp, Cym, Cyp, o);
+#pragma unroll
+    for (int k = 0; k < 18; ++k) T.C[k][s] = o[k];
+  }
+  for (int s = tid; s < NA; s += NT) {
+    const int X = X0 - 4 + s % WA, Y = Y0 - 4 + s / WA;
+    if (X > Xlim + kMargin || Y > Ylim + kMargin || ((X & 1) && (Y & 1))) continue;
+    store_aux(T, ph, s);
+  }
+  __syncthreads();
+
+  // ---- phase 0b: centre values in place (Simpson + scaling) ----
+  for (int s = tid; s < NA; s += NT) {
+    const int X = X0 - 4 + s % WA, Y = Y0 - 4 + s / WA;
+    if (X > Xlim + kMargin || Y > Ylim + kMargin || !((X & 1) && (Y & 1))) continue;
+    double V[4];
+    const bool ghost_x = (X < 0 || X > Xlim) && g.bc0 != BC_PERIODIC;
+    const bool ghost_y = (Y < 0 || Y > Ylim) && g.bc2 != BC_PERIODIC;
+    if (ghost_x || ghost_y) {
+      // a centre beyond a wall or outflow side is the image of an interior one
+      lattice_value(g, ph, Uk, X, Y, V);
+    } else {
+      // periodic ghosts included: their neighbours are the wrapped values
+      double Ub[4], e[4], c[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double* z = T.U[k];
+        Ub[k] = z[s];
+        e[k] = z[s - 1] + z[s + 1] + z[s - WA] + z[s + WA];
+        c[k] = z[s - WA - 1] + z[s - WA + 1] + z[s + WA - 1] + z[s + WA + 1];
+      }
+      centre_value(ph, Ub, e, c, V);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) T.U[k][s] = V[k];
+    store_aux(T, ph, s);
+  }
+  __syncthreads();
+
+  // prefetch the next tile's raw values; the loads complete while this tile
+  // computes
+  const int next = it.advance();
+  if (next >= 0) load_raw(g, Uk, 2 * TX * (next % ntx), 2 * TY * (next / ntx), tid, pre);
+
+  // ---- phase 1: gradients and viscous speeds on the block +- 2 ----
+  {
+    const double ihx = 1.0 / (6.0 * g.dx), ihy = 1.0 / (6.0 * g.dy);
+    for (int s = tid; s < NG; s += NT) {
+      const int lx = s % WG, ly = s / WG;
+      const int X = X0 - 2 + lx, Y = Y0 - 2 + ly;
+      if (X > Xlim + 2 || Y > Ylim + 2) continue;
+      const int a = (ly + 2) * WA + (lx + 2);
+      double gr[6];
+      const int src[3] = {0, 1, 3};
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double* z = T.A[src[c]];
+        gr[c] = dc5(z[a - 2], z[a - 1], z[a + 1], z[a + 2], ihx);
+        gr[3 + c] = dc5(z[a - 2 * WA], z[a - WA], z[a + WA], z[a + 2 * WA], ihy);
+      }
+#pragma unroll
+      for (int c = 0; c < 6; ++c) T.G[c][s] = gr[c];
+      double bx, by;
+      bvisc2_xy(T.A[2][a], T.A[3][a], gr[0], gr[1], gr[2], gr[3], gr[4], gr[5], ph, bx, by);
+      T.B[0][s] = bx;
+      T.B[1][s] = by;
+    }
+  }
+  __syncthreads();
+
+  // ---- phase 3: limited face fluxes of the tile's cells ----
+  const int limc = ph.lim & (LIM_SMOOTH | LIM_PP | 16);
+  for (int s = tid; s < NFX + NFY; s += NT) {
+    const int d = s < NFX ? 0 : 1;
+    int ff, jj, i, j, X, Y;  // face (i,j) between cells a (minus) and b (plus)
+    if (d == 0) {
+      ff = s % (TX + 1);
+      jj = s / (TX + 1);
+      i = i0 + ff;
+      j = j0 + jj;
+      if (i > g.n1 || j >= g.n2) continue;
+      X = 2 * i;
+      Y = 2 * j + 1;
+    } else {
+      const int r = s - NFX;
+      ff = r % TX;
+      jj = r / TX;
+      i = i0 + ff;
+      j = j0 + jj;
+      if (i >= g.n1 || j > g.n2) continue;
+      X = 2 * i + 1;
+      Y = 2 * j;
+    }
+    const int a = (Y - Y0 + 4) * WA + (X - X0 + 4);
+    const int q = (Y - Y0 + 2) * WG + (X - X0 + 2);
+    const int sa = d == 0 ? WA : 1, sq = d == 0 ? WG : 1;  // along the face
+    double Fa[4], Fm[4], Fb[4], FH[4], F[4];
+    site_flux(T, ph, a - sa, q - sq, d, Fa);
+    site_flux(T, ph, a, q, d, Fm);
+    site_flux(T, ph, a + sa, q + sq, d, Fb);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) FH[k] = (Fa[k] + 4.0 * Fm[k] + Fb[k]) / 6.0;
+    if (!limc) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) F[k] = FH[k];
+    } else {
+      const int cbx = (j - j0 + 1) * WC + (i - i0 + 1);
+      const int cax = d == 0 ? cbx - 1 : cbx - WC;
+      const double lam = mx(T.C[8 + d][cax], T.C[8 + d][cbx]) + mx(T.C[10 + d][cax], T.C[10 + d][cbx]);
+      double FL[4], Ua[4], Ub[4], Fca[4], Fcb[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        Ua[k] = T.C[14 + k][cax];
+        Ub[k] = T.C[14 + k][cbx];
+        Fca[k] = T.C[4 * d + k][cax];
+        Fcb[k] = T.C[4 * d + k][cbx];
+        FL[k] = 0.5 * (Fca[k] + Fcb[k]) - 0.5 * lam * (Ub[k] - Ua[k]);
+      }
+      double ts = 1.0, tpp = 1.0;
+      if (ph.lim & 16) {
+        ts = 0.0;
+        tpp = 0.0;
+      } else {
+        if (ph.lim & LIM_SMOOTH)
+          ts = exp(-ph.Cs * mx(T.C[12][cax], T.C[12][cbx]) * mx(T.C[13][cax], T.C[13][cbx]));
+        if (ph.lim & LIM_PP) {
+          const double m4 = 4.0 * dt / (d == 0 ? g.dx : g.dy);
+          double ULp[4], UHp[4], ULm[4], UHm[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const double Fs = FL[k] + ts * (FH[k] - FL[k]);
+            ULp[k] = Ua[k] - m4 * (FL[k] - Fca[k]);
+            UHp[k] = Ua[k] - m4 * (Fs - Fca[k]);
+            ULm[k] = Ub[k] - m4 * (Fcb[k] - FL[k]);
+            UHm[k] = Ub[k] - m4 * (Fcb[k] - Fs);
+          }
+          tpp = 0.0;
+          bool bad = false;
+          if (!(ULp[0] > 0.0) || !(ULm[0] > 0.0)) {
+            bad = true;
+          } else {
+            const double pLp = pressure2(ULp[0], ULp[1], ULp[2], ULp[3], ph.gm1);
+            const double pLm = pressure2(ULm[0], ULm[1], ULm[2], ULm[3], ph.gm1);
+            if (!(pLp > 0.0) || !(pLm > 0.0)) bad = true;
+            const double tr = mn(theta_lin(ULp[0], UHp[0], mn(kPPEps, ULp[0])),
+                                 theta_lin(ULm[0], UHm[0], mn(kPPEps, ULm[0])));
+            double Tp[4], Tm[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              Tp[k] = ULp[k] + tr * (UHp[k] - ULp[k]);
+              Tm[k] = ULm[k] + tr * (UHm[k] - ULm[k]);
+            }
+            const double tp =
+                mn(theta_lin(pLp, pressure2(Tp[0], Tp[1], Tp[2], Tp[3], ph.gm1), mn(kPPEps, pLp)),
+                   theta_lin(pLm, pressure2(Tm[0], Tm[1], Tm[2], Tm[3], ph.gm1), mn(kPPEps, pLm)));
+            tpp = tr * tp;
+          }
+          if (bad) raise_flag(flags, FLAG_CELL_LOW);
+        }
+      }
+      const double th = ts * tpp;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) F[k] = FL[k] + th * (FH[k] - FL[k]);
+    }
+    if (d == 0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) T.FX[k][jj * (TX + 1) + ff] = F[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) T.FY[k][jj * TX + ff] = F[k];
+    }
+  }
+  __syncthreads();
+
+  // ---- phase 4: cell averages ----
+  {
+    const double mxd = dt / g.dx, myd = dt / g.dy;
+    const long nc = (long)g.n1 * g.n2;
+    for (int s = tid; s < TX * TY; s += NT) {
+      const int ii = s % TX, jj = s / TX;
+      const int i = i0 + ii, j = j0 + jj;
+      if (i >= g.n1 || j >= g.n2) continue;
+      const int c = (jj + 1) * WC + ii + 1;
+      const long gi = (long)j * g.n1 + i;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double dfx = T.FX[k][jj * (TX + 1) + ii + 1] - T.FX[k][jj * (TX + 1) + ii];
+        const double dfy = T.FY[k][(jj + 1) * TX + ii] - T.FY[k][jj * TX + ii];
+        const double fe = T.C[14 + k][c] - mxd * dfx - myd * dfy;
+        const double o = first ? fe : ca * Un[k * nc + gi] + cb * fe;
+        if (!isfinite(o)) nonfinite = true;
+        Uout[k * nc + gi] = o;
+      }
+    }
+  }
+
+  // ---- phase 5: point values (0 x-edge, 1 y-edge, 2 corner points) ----
+  for (int s = tid; s < 3 * TX * TY; s += NT) {
+    const int t = s / (TX * TY), r = s % (TX * TY);
+    const int ni = t == 1 ? g.n1 : g.n1x;
+    const int nj = t == 0 ? g.n2 : g.n2y;
+    const long np = (long)ni * nj;
+    const long off = t == 0 ? g.off_xe : (t == 1 ? g.off_ye : g.off_co);
+    {
+      const int i = i0 + r % TX, j = j0 + r / TX;
+      if (i >= ni || j >= nj) continue;
+      const int X = t == 1 ? 2 * i + 1 : 2 * i;
+      const int Y = t == 0 ? 2 * j + 1 : 2 * j;
+      const int a = (Y - Y0 + 4) * WA + (X - X0 + 4);
+      const int q = (Y - Y0 + 2) * WG + (X - X0 + 2);
+      double R[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        const int sa = d == 0 ? 1 : WA, sq = d == 0 ? 1 : WG;
+        const double h = d == 0 ? g.dx : g.dy;
+        const double i6h = 1.0 / (6.0 * h);
+        // alpha: max of |u_d| + c over the five sites of the line
+        double alpha = 0.0;
+#pragma unroll
+        for (int o = 0; o < 5; ++o) {
+          const int b = a + (o - 2) * sa;
+          alpha = mx(alpha, fabs(T.A[d][b]) + T.A[4][b]);
+        }
+        // inviscid: D+(F+) + D-(F-) = D_c(F) + alpha/(6h) * fourth difference,
+        // one component at a time (short live ranges)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          double f[5], w[5];
+#pragma unroll
+          for (int o = 0; o < 5; ++o) {
+            const int b = a + (o - 2) * sa;
+            const double ud = T.A[d][b], pb = T.A[2][b];
+            w[o] = T.U[k][b];
+            f[o] = k == 0 ? T.U[1 + d][b]
+                          : (k == 3 ? (w[o] + pb) * ud : w[o] * ud + (k == 1 + d ? pb : 0.0));
+          }
+          R[k] -= dc5(f[0], f[1], f[3], f[4], i6h) + alpha * i6h * d4(w[0], w[1], w[2], w[3], w[4]);
+        }
+        double u[5], v[5], Tt[5];
+#pragma unroll
+        for (int o = 0; o < 5; ++o) {
+          const int b = a + (o - 2) * sa;
+          u[o] = T.A[0][b];
+          v[o] = T.A[1][b];
+          Tt[o] = T.A[3][b];
+        }
+        // compact D^{(d),2}(K_dd, Z)
+        const double s4 = 4.0 / (h * h);
+        const double mu = ph.mu, m43 = (4.0 / 3.0) * ph.mu;
+        const double cu = bcol(u), cv = bcol(v), cT = bcol(Tt);
+        const double fu = bform(u, u), fv = bform(v, v);
+        if (d == 0) {
+          R[1] += s4 * m43 * cu;
+          R[2] += s4 * mu * cv;
+          R[3] += s4 * (m43 * fu + mu * fv + ph.kap * cT);
+        } else {
+          R[1] += s4 * mu * cu;
+          R[2] += s4 * m43 * cv;
+          R[3] += s4 * (mu * fu + m43 * fv + ph.kap * cT);
+        }
+        // mixed: D_c^{(d)} (K_{d,o} D_c^{(o)} Z), o the other direction
+        double m1[5], m2[5], m3[5];
+#pragma unroll
+        for (int o = 0; o < 5; ++o) {
+          if (o == 2) {
+            m1[o] = m2[o] = m3[o] = 0.0;
+            continue;
+          }
+          const int qq = q + (o - 2) * sq;
+          if (d == 0) {  // K_12 dZ/dy
+            const double uy = T.G[3][qq], vy = T.G[4][qq];
+            m1[o] = -(2.0 / 3.0) * mu * vy;
+            m2[o] = mu * uy;
+            m3[o] = mu * (v[o] * uy - (2.0 / 3.0) * u[o] * vy);
+          } else {  // K_21 dZ/dx
+            const double ux = T.G[0][qq], vx = T.G[1][qq];
+            m1[o] = mu * vx;
+            m2[o] = -(2.0 / 3.0) * mu * ux;
+            m3[o] = mu * (u[o] * vx - (2.0 / 3.0) * v[o] * ux);
+          }
+        }
+        R[1] += dc5(m1[0], m1[1], m1[3], m1[4], i6h);
+        R[2] += dc5(m2[0], m2[1], m2[3], m2[4], i6h);
+        R[3] += dc5(m3[0], m3[1], m3[3], m3[4], i6h);
+      }
+      double U0[4], UH[4], out[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        U0[k] = T.U[k][a];
+        UH[k] = U0[k] + dt * R[k];
+      }
+      if (ph.lim & LIM_POINT) {
+        double Fxp[4], Fxm[4], Fyp[4], Fym[4], UL[4];
+        llf_pair(T, ph, a, q, a + 1, q + 1, 0, Fxp);
+        llf_pair(T, ph, a - 1, q - 1, a, q, 0, Fxm);
+        llf_pair(T, ph, a, q, a + WA, q + WG, 1, Fyp);
+        llf_pair(T, ph, a - WA, q - WG, a, q, 1, Fym);
+        const double cx = 2.0 * dt / g.dx, cy = 2.0 * dt / g.dy;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) UL[k] = U0[k] - cx * (Fxp[k] - Fxm[k]) - cy * (Fyp[k] - Fym[k]);
+        bool lbad = false;
+        const double th = theta_pair2(UL, UH, ph.gm1, lbad);
+        if (lbad) raise_flag(flags, FLAG_POINT_LOW);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) out[k] = (th == 1.0) ? UH[k] : UL[k] + th * (UH[k] - UL[k]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) out[k] = UH[k];
+      }
+      if (X == 0) project(wall_of(g.bc0), 0, out);
+      if (X == Xlim) project(wall_of(g.bc1), 0, out);
+      if (Y == 0) project(wall_of(g.bc2), 1, out);
+      if (Y == Ylim) project(wall_of(g.bc3), 1, out);
+      const long gi = (long)j * ni + i;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const long idx = off + k * np + gi;
+        const double o = first ? out[k] : ca * Un[idx] + cb * out[k];
+        if (!isfinite(o)) nonfinite = true;
+        Uout[idx] = o;
+      }
+    }
+  }
+  tile = next;
+  }  // tiles
+  if (nonfinite) raise_flag(flags, FLAG_NONFINITE);
+}
+
+// compute units of the current device (one persistent workgroup each: the
+// tile's LDS footprint admits one per CU)
+int device_cus() {
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cache[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+      n = 256;
+    cache[dev] = n;
+  }
+  return cache[dev];
+}
+
+}  // namespace
+
+namespace afi {
+
+hipError_t stage2d(const Geo& geo, const Phys& ph, const Work& w, const double* Un,
+                   const double* Uk, double* Uout, const double* dt_dev, double dt_host,
+                   StageCoef sc, hipStream_t s, Timer* tm) {
+  const G2 g = make_g2(geo);
+  // tiles cover cells [0, n1) and the point columns up to index n1
+  const int ntx = g.n1 / TX + 1, nty = g.n2 / TY + 1;
+  const int ntiles = ntx * nty;
+  int nwg = device_cus();
+  if (nwg > ntiles) nwg = ntiles;
+  if (nwg >= 8) nwg -= nwg % 8;
+  AFI_TIMED(tm, 7, s,
+            hipLaunchKernelGGL(k_stage, dim3((unsigned)nwg), dim3(NT), 0, s, g, ph, Uk, Un, Uout,
+                               dt_dev, dt_host, sc.a, sc.b, sc.first, w.flags, ntx, ntiles));
+  return hipGetLastError();
+}
+
+}  // namespace afi
