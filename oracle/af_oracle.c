@@ -25,9 +25,13 @@
  *              difference of Z(average) in every direction (Sec. 3.1).
  *   R-point  : the low-order point scheme is the LLF scheme (eq. of the low
  *              face fluxes, Sec. 3.1) on the half-spaced lattice around the
- *              point: U^L = U - sum_l (2 dt/dx_l) (F^L(z,z+) - F^L(z-,z)),
- *              with S = the D_c lattice gradients; blend by Theta on density
- *              then pressure (Sec. 3.4).
+ *              point: U^L = U - sum_l (2 dt/dx_l) (F^L(z,z+) - F^L(z-,z)).
+ *              Its states are point values and, at centre sites, cell
+ *              averages: the states the positivity theorem (end of Sec. 3.4)
+ *              assumes admissible.  Its gradients S are central differences
+ *              of Z over the neighbouring sites of that lattice, as the cell
+ *              scheme's S is of Z(average).  Blend by Theta on density then
+ *              pressure (Sec. 3.4).
  *   R-bc     : ghost lattice sites are images of interior sites: mirror about
  *              the wall line (walls; no-slip flips both momenta, symmetry the
  *              normal one), zero-order copy (outflow: even ghost lines copy the
@@ -493,18 +497,36 @@ static void fluxH1(const lat1* L, int X, double* F) {
   flux_tot(c, 0, U, S, F);
 }
 
-/* low-order LLF flux between two lattice sites (reading R-point) */
+/* state of a site of the low-order point lattice (reading R-point): a point
+   site holds its point value, a centre site the cell average */
+static void lo_site1(const lat1* L, int X, double* U) {
+  for (int k = 0; k < 3; ++k) U[k] = (X & 1) ? C1(k, (X - 1) / 2) : L1(L->LU, k, X);
+}
+
+/* low-order gradient at a site of that lattice: central difference of Z
+   over its two neighbours, dx/2 away on either side */
+static void lo_grad1(const lat1* L, int X, double* S) {
+  double Um[4], Up[4], Wm[4], Wp[4], Zm[4], Zp[4];
+  lo_site1(L, X - 1, Um);
+  lo_site1(L, X + 1, Up);
+  prim(L->c, Um, Wm);
+  prim(L->c, Up, Wp);
+  zvar(L->c, Wm, Zm);
+  zvar(L->c, Wp, Zp);
+  for (int k = 0; k < 3; ++k) S[k] = (Zp[k] - Zm[k]) / L->dx;
+}
+
+/* low-order LLF flux between two neighbouring sites of the low-order point
+   lattice (reading R-point) */
 static void llf_sites1(const lat1* L, int Xa, int Xb, double* F) {
   const orc_cfg* c = L->c;
   double Ua[4], Ub[4], Sa[4], Sb[4], Wa[4], Wb[4], Fa[4], Fb[4];
-  for (int k = 0; k < 3; ++k) {
-    Ua[k] = L1(L->LU, k, Xa);
-    Ub[k] = L1(L->LU, k, Xb);
-    Sa[k] = L1(L->GZ, k, Xa);
-    Sb[k] = L1(L->GZ, k, Xb);
-    Wa[k] = L1(L->LW, k, Xa);
-    Wb[k] = L1(L->LW, k, Xb);
-  }
+  lo_site1(L, Xa, Ua);
+  lo_site1(L, Xb, Ub);
+  lo_grad1(L, Xa, Sa);
+  lo_grad1(L, Xb, Sb);
+  prim(c, Ua, Wa);
+  prim(c, Ub, Wb);
   flux_tot(c, 0, Ua, Sa, Fa);
   flux_tot(c, 0, Ub, Sb, Fb);
   double lam = dmax(rho_spec(c, 0, Wa), rho_spec(c, 0, Wb)) +
@@ -923,6 +945,33 @@ static void fluxsite2(const lat2* L, int d, int X, int Y, double* F) {
   flux_tot(L->c, d, U, S, F);
 }
 
+/* state of a site of the low-order point lattice (reading R-point): point
+   sites hold their point values, centre sites the cell averages */
+static void lo_site2(const lat2* L, int X, int Y, double* U) {
+  const int centre = (X & 1) && (Y & 1);
+  for (int k = 0; k < 4; ++k)
+    U[k] = centre ? C2(k, (X - 1) / 2, (Y - 1) / 2) : L2(L->LU, k, X, Y);
+}
+
+/* low-order gradient (x then y derivatives of Z) at a site of that lattice:
+   central differences over the neighbouring sites, half a cell away */
+static void lo_grad2(const lat2* L, int X, int Y, double* S) {
+  const orc_cfg* c = L->c;
+  double U[4][4], W[4], Z[4][4];
+  lo_site2(L, X - 1, Y, U[0]);
+  lo_site2(L, X + 1, Y, U[1]);
+  lo_site2(L, X, Y - 1, U[2]);
+  lo_site2(L, X, Y + 1, U[3]);
+  for (int m = 0; m < 4; ++m) {
+    prim(c, U[m], W);
+    zvar(c, W, Z[m]);
+  }
+  for (int k = 0; k < 4; ++k) {
+    S[k] = (Z[1][k] - Z[0][k]) / L->dx;
+    S[4 + k] = (Z[3][k] - Z[2][k]) / L->dy;
+  }
+}
+
 /* high-order face flux: Simpson average along the face (Sec. 2.2) */
 static void fluxH2(const lat2* L, int d, int X, int Y, double* F) {
   double Fa[4], Fb[4], Fm[4];
@@ -941,14 +990,12 @@ static void fluxH2(const lat2* L, int d, int X, int Y, double* F) {
 static void llf_sites2(const lat2* L, int d, int Xa, int Ya, int Xb, int Yb, double* F) {
   const orc_cfg* c = L->c;
   double Ua[4], Ub[4], Wa[4], Wb[4], Sa[8], Sb[8], Fa[4], Fb[4];
-  site2(L, Xa, Ya, Ua, Wa, NULL);
-  site2(L, Xb, Yb, Ub, Wb, NULL);
-  for (int k = 0; k < 4; ++k) {
-    Sa[k] = G2(0, k, Xa, Ya);
-    Sa[4 + k] = G2(1, k, Xa, Ya);
-    Sb[k] = G2(0, k, Xb, Yb);
-    Sb[4 + k] = G2(1, k, Xb, Yb);
-  }
+  lo_site2(L, Xa, Ya, Ua);
+  lo_site2(L, Xb, Yb, Ub);
+  prim(c, Ua, Wa);
+  prim(c, Ub, Wb);
+  lo_grad2(L, Xa, Ya, Sa);
+  lo_grad2(L, Xb, Yb, Sb);
   flux_tot(c, d, Ua, Sa, Fa);
   flux_tot(c, d, Ub, Sb, Fb);
   double lam = dmax(rho_spec(c, d, Wa), rho_spec(c, d, Wb)) +

@@ -187,25 +187,6 @@ __device__ __forceinline__ void visc_flux2(int d, double u, double v, double ux,
 
 // b_l of the viscous splitting lemma (Sec. 3.1): with rho e = p/(gamma-1),
 //   b = (sqrt(q^2 + 2 e |tau_l|^2) + |q|) / (2 rho e)
-__device__ __forceinline__ double bvisc2(int d, double rho, double p, double ux, double vx,
-                                         double Tx, double uy, double vy, double Ty,
-                                         const Phys& ph) {
-  const double txx = ph.mu * ((4.0 / 3.0) * ux - (2.0 / 3.0) * vy);
-  const double tyy = ph.mu * ((4.0 / 3.0) * vy - (2.0 / 3.0) * ux);
-  const double txy = ph.mu * (uy + vx);
-  double q, t2;
-  if (d == 0) {
-    q = ph.kap * Tx;
-    t2 = txx * txx + txy * txy;
-  } else {
-    q = ph.kap * Ty;
-    t2 = txy * txy + tyy * tyy;
-  }
-  const double re = p / ph.gm1;
-  const double e = re / rho;
-  return (sqrt(q * q + 2.0 * e * t2) + fabs(q)) / (2.0 * re);
-}
-
 // both b_x and b_y with shared terms: e = T/(gamma-1), 1/(2 rho e) =
 // (gamma-1)/(2 p); one division for the pair
 __device__ __forceinline__ void bvisc2_xy(double p, double T, double ux, double vx, double Tx,
@@ -219,6 +200,19 @@ __device__ __forceinline__ void bvisc2_xy(double p, double T, double ux, double 
   const double inv = 0.5 * ph.gm1 / p;
   bx = (sqrt(qx * qx + e2 * (txx * txx + txy * txy)) + fabs(qx)) * inv;
   by = (sqrt(qy * qy + e2 * (txy * txy + tyy * tyy)) + fabs(qy)) * inv;
+}
+
+// b_d alone, in the same form
+__device__ __forceinline__ double bvisc2_dir(int d, double p, double T, double ux, double vx,
+                                             double Tx, double uy, double vy, double Ty,
+                                             const Phys& ph) {
+  const double txx = ph.mu * ((4.0 / 3.0) * ux - (2.0 / 3.0) * vy);
+  const double tyy = ph.mu * ((4.0 / 3.0) * vy - (2.0 / 3.0) * ux);
+  const double txy = ph.mu * (uy + vx);
+  const double q = ph.kap * (d == 0 ? Tx : Ty);
+  const double t2 = d == 0 ? txx * txx + txy * txy : txy * txy + tyy * tyy;
+  const double e2 = 2.0 * T / ph.gm1;
+  return (sqrt(q * q + e2 * t2) + fabs(q)) * (0.5 * ph.gm1 / p);
 }
 
 __device__ __forceinline__ double bvisc1(double rho, double p, double ux, double Tx,

@@ -236,23 +236,25 @@ __global__ void __launch_bounds__(kBlock) k_cells1(G1 g, const double* __restric
   if (bad) raise_flag(flags, FLAG_NONFINITE);
 }
 
-__device__ __forceinline__ void llf1(const G1& g, const Phys& ph, const double* __restrict__ LU,
-                                     const double* __restrict__ LA, const double* __restrict__ LG,
-                                     int qa, int qb, double* F) {
-  double Fa[3], Fb[3];
-  site_flux1(g, ph, LU, LA, LG, qa, Fa);
-  site_flux1(g, ph, LU, LA, LG, qb, Fb);
-  const double ra = fabs(LA[qa]) + LA[3 * g.LX + qa], rb = fabs(LA[qb]) + LA[3 * g.LX + qb];
-  const double ba = bvisc1(LU[qa], LA[g.LX + qa], LG[qa], LG[g.LX + qa], ph);
-  const double bb = bvisc1(LU[qb], LA[g.LX + qb], LG[qb], LG[g.LX + qb], ph);
-  const double lam = mx(ra, rb) + mx(ba, bb);
-#pragma unroll
-  for (int k = 0; k < 3; ++k) F[k] = 0.5 * (Fa[k] + Fb[k]) - 0.5 * lam * (LU[k * g.LX + qb] - LU[k * g.LX + qa]);
+// low-order data of site o (1..3) of the five-site low-order point lattice
+// V[0..4] (point, average, point, average, point): total flux with the
+// central-difference gradient over its neighbours, |u|+c and b
+__device__ __forceinline__ void lo_site1(const Phys& ph, const double (&V)[5][3],
+                                         const double* u, const double* p, const double* T,
+                                         const double* c, int o, double ih, double* F,
+                                         double& r, double& b) {
+  const double ux = (u[o + 1] - u[o - 1]) * ih, Tx = (T[o + 1] - T[o - 1]) * ih;
+  const double tau = (4.0 / 3.0) * ph.mu * ux;
+  F[0] = V[o][1];
+  F[1] = V[o][1] * u[o] + p[o] - tau;
+  F[2] = (V[o][2] + p[o]) * u[o] - (u[o] * tau + ph.kap * Tx);
+  r = fabs(u[o]) + c[o];
+  b = bvisc1(V[o][0], p[o], ux, Tx, ph);
 }
 
 __global__ void __launch_bounds__(kBlock) k_points1(G1 g, Phys ph, const double* __restrict__ LU,
                                                     const double* __restrict__ LA,
-                                                    const double* __restrict__ LG,
+                                                    const double* __restrict__ CP,
                                                     const double* __restrict__ Un,
                                                     double* __restrict__ Uout, const double* dt_dev,
                                                     double dt_host, double ca, double cb, int first,
@@ -300,9 +302,41 @@ __global__ void __launch_bounds__(kBlock) k_points1(G1 g, Phys ph, const double*
     UH[k] = U0[k] + dt * R[k];
   }
   if (ph.lim & LIM_POINT) {
+    // low-order LLF scheme on the lattice of point values (X-2, X, X+2) and
+    // cell averages (X-1, X+1: ring cells k0 and k0+1), Sec. 3.4
+    const int nc = g.n + 2;
+    double V[5][3], lu[5], lp[5], lT[5], lc[5];
+#pragma unroll
+    for (int o = 0; o < 5; o += 2) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) V[o][k] = Us[o][k];
+      lu[o] = u[o];
+      lp[o] = p[o];
+      lT[o] = T[o];
+      lc[o] = LA[3 * g.LX + q + o - 2];
+    }
+#pragma unroll
+    for (int o = 1; o < 5; o += 2) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) V[o][k] = CP[(7 + k) * nc + k0 + (o >> 1)];
+      const double ir = 1.0 / V[o][0];
+      lu[o] = V[o][1] * ir;
+      lp[o] = pressure1(V[o][0], V[o][1], V[o][2], ph.gm1);
+      lT[o] = lp[o] * ir;
+      lc[o] = sqrt(ph.gam * lT[o]);
+    }
+    const double ih = 1.0 / g.dx;
+    double F1[3], F2[3], F3[3], r1, r2, r3, b1, b2, b3;
+    lo_site1(ph, V, lu, lp, lT, lc, 1, ih, F1, r1, b1);
+    lo_site1(ph, V, lu, lp, lT, lc, 2, ih, F2, r2, b2);
+    lo_site1(ph, V, lu, lp, lT, lc, 3, ih, F3, r3, b3);
+    const double lp23 = mx(r2, r3) + mx(b2, b3), lm12 = mx(r1, r2) + mx(b1, b2);
     double Fp[3], Fm[3], UL[3];
-    llf1(g, ph, LU, LA, LG, q, q + 1, Fp);
-    llf1(g, ph, LU, LA, LG, q - 1, q, Fm);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      Fp[k] = 0.5 * (F2[k] + F3[k]) - 0.5 * lp23 * (V[3][k] - V[2][k]);
+      Fm[k] = 0.5 * (F1[k] + F2[k]) - 0.5 * lm12 * (V[2][k] - V[1][k]);
+    }
     const double c2 = 2.0 * dt / g.dx;
 #pragma unroll
     for (int k = 0; k < 3; ++k) UL[k] = U0[k] - c2 * (Fp[k] - Fm[k]);
@@ -368,7 +402,7 @@ hipError_t stage1d(const Geo& geo, const Phys& ph, const Work& w, const double* 
                                w.flags));
   AFI_TIMED(tm, 5, s,
             hipLaunchKernelGGL(k_points1, dim3(nblk(g.np)), dim3(kBlock), 0, s, g, ph,
-                               (const double*)w.LU, (const double*)w.LA, (const double*)w.LG, Un,
+                               (const double*)w.LU, (const double*)w.LA, (const double*)w.CP, Un,
                                Uout, dt_dev, dt_host, sc.a, sc.b, sc.first, w.flags));
   return hipGetLastError();
 }

@@ -8,16 +8,18 @@
 //   phase 0  lattice values on the block +- 4 half cells: ghosts as boundary
 //            images, Simpson centres scaled toward the cell average (Sec. 2.2;
 //            Remark after the pressure blend, Sec. 3.3), and (u, v, p, T, c)
-//   phase 1  D_c gradients of (u, v, T) and the viscous speeds b_x, b_y on the
-//            block +- 2 (Sec. 2.2 central operator; viscous splitting lemma)
+//   phase 1  D_c gradients of (u, v, T) on the block +- 2 (Sec. 2.2 central
+//            operator)
 //   phase 2  low-order data of the cells of the tile +- 1: S, F_l, |u_l|+c,
-//            b_l, the two smoothness sensors (Sec. 3.1, Sec. 3.2)
+//            b_l, the two smoothness sensors, (u, v, p, T, c) of the average
+//            (Sec. 3.1, Sec. 3.2)
 //   phase 3  limited face fluxes of the tile's cells: Simpson high-order
 //            flux, LLF low-order flux, theta^s, theta^rho theta^p (Sec. 3.3)
 //   phase 4  cell-average update and RK combination
 //   phase 5  point residual (biased inviscid operators with the downwind
-//            point, compact D^2, mixed terms; Sec. 2.2), point LLF and scaling
-//            limiter (Sec. 3.4), wall projection, RK combination
+//            point, compact D^2, mixed terms; Sec. 2.2), point LLF on the
+//            lattice of point values and cell averages and the scaling limiter
+//            (Sec. 3.4), wall projection, RK combination
 #include "af_device.hpp"
 #include "af_internal.hpp"
 
@@ -132,8 +134,9 @@ __device__ __forceinline__ void lattice_value(const G2& g, const Phys& ph,
 // per-cell low-order data (Sec. 3.1-3.2):
 //   o[0..3] F_x, o[4..7] F_y (total fluxes with S = central differences of
 //   Z(average)), o[8] |u|+c, o[9] |v|+c, o[10] b_x, o[11] b_y, o[12] phi1,
-//   o[13] phi2, o[14..17] the cell average; from the averages of the cell
-//   and of its four neighbours (ghost cells as boundary images)
+//   o[13] phi2, o[14..17] the cell average, o[18..22] its (u, v, p, T, c);
+//   from the averages of the cell and of its four neighbours (ghost cells as
+//   boundary images)
 __device__ __forceinline__ void cell_low(const G2& g, const Phys& ph, const double* C0,
                                          const double* Cxm, const double* Cxp, const double* Cym,
                                          const double* Cyp, double* o) {
@@ -167,6 +170,11 @@ __device__ __forceinline__ void cell_low(const G2& g, const Phys& ph, const doub
   o[7] = (C0[3] + p0) * v0 - Fv[3];
   o[8] = fabs(u0) + c0;
   o[9] = fabs(v0) + c0;
+  o[18] = u0;
+  o[19] = v0;
+  o[20] = p0;
+  o[21] = p0 * r0;
+  o[22] = c0;
   bvisc2_xy(p0, p0 * r0, ux, vx, Tx, uy, vy, Ty, ph, o[10], o[11]);
   const double jx = fabs(pxp - 2.0 * p0 + pxm) / fabs(pxp + 2.0 * p0 + pxm);
   const double jy = fabs(pyp - 2.0 * p0 + pym) / fabs(pyp + 2.0 * p0 + pym);
@@ -199,8 +207,7 @@ struct Tile {
   double U[4][NA];   // conservative values, block +- 4
   double A[5][NA];   // u, v, p, T, c
   double G[6][NG];   // du/dx dv/dx dT/dx du/dy dv/dy dT/dy, block +- 2
-  double B[2][NG];   // b_x, b_y
-  double C[18][NC];  // cell low-order data, tile +- 1
+  double C[23][NC];  // cell low-order data, tile +- 1
   double FX[4][NFX]; // limited x-face fluxes of the tile's cells
   double FY[4][NFY]; // limited y-face fluxes
 };
@@ -232,17 +239,117 @@ __device__ __forceinline__ void site_flux(const Tile& T, const Phys& ph, int a, 
   F[3] = (E + p) * ud - Fv[3];
 }
 
-// low-order LLF flux along d between LDS sites (a0,q0) (minus) and (a1,q1)
-__device__ __forceinline__ void llf_pair(const Tile& T, const Phys& ph, int a0, int q0, int a1,
-                                         int q1, int d, double* F) {
-  double Fa[4], Fb[4];
-  site_flux(T, ph, a0, q0, d, Fa);
-  site_flux(T, ph, a1, q1, d, Fb);
-  const double ra = fabs(T.A[d][a0]) + T.A[4][a0];
-  const double rb = fabs(T.A[d][a1]) + T.A[4][a1];
-  const double lam = mx(ra, rb) + mx(T.B[d][q0], T.B[d][q1]);
+// total flux F_d = F^c_d - F^v_d of state (m1, m2, E) with velocity (u, v),
+// pressure p and gradients gr = (u_x, v_x, T_x, u_y, v_y, T_y)
+__device__ __forceinline__ void tot_flux(int d, const double* U, double u, double v, double p,
+                                         const double* gr, const Phys& ph, double* F) {
+  double Fv[4];
+  visc_flux2(d, u, v, gr[0], gr[1], gr[2], gr[3], gr[4], gr[5], ph, Fv);
+  const double ud = d == 0 ? u : v;
+  F[0] = U[1 + d] - Fv[0];
+  F[1] = U[1] * ud + (d == 0 ? p : 0.0) - Fv[1];
+  F[2] = U[2] * ud + (d == 1 ? p : 0.0) - Fv[2];
+  F[3] = (U[3] + p) * ud - Fv[3];
+}
+
+// The low-order point scheme works on the half lattice whose point sites hold
+// the point values and whose centre sites hold the cell averages (Sec. 3.4
+// with the LLF flux of Sec. 3.1).  Sites are addressed by their coordinates
+// (lx, ly) in the LDS lattice region; a centre site (both odd) reads the cell
+// data of phase 2.
+__device__ __forceinline__ int lo_cell(int lx, int ly) {
+  return ((ly - 3) >> 1) * WC + ((lx - 3) >> 1);
+}
+__device__ __forceinline__ void lo_z(const Tile& T, int lx, int ly, double& u, double& v,
+                                     double& t) {
+  if (lx & ly & 1) {
+    const int c = lo_cell(lx, ly);
+    u = T.C[18][c];
+    v = T.C[19][c];
+    t = T.C[21][c];
+  } else {
+    const int a = ly * WA + lx;
+    u = T.A[0][a];
+    v = T.A[1][a];
+    t = T.A[3][a];
+  }
+}
+// state and (u, v, p, T, c) of a site
+__device__ __forceinline__ void lo_state(const Tile& T, int lx, int ly, double* U, double* w) {
+  if (lx & ly & 1) {
+    const int c = lo_cell(lx, ly);
 #pragma unroll
-  for (int k = 0; k < 4; ++k) F[k] = 0.5 * (Fa[k] + Fb[k]) - 0.5 * lam * (T.U[k][a1] - T.U[k][a0]);
+    for (int k = 0; k < 4; ++k) U[k] = T.C[14 + k][c];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) w[k] = T.C[18 + k][c];
+  } else {
+    const int a = ly * WA + lx;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) U[k] = T.U[k][a];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) w[k] = T.A[k][a];
+  }
+}
+// low-order gradient at a site: central differences of Z = (u, v, T) over the
+// four neighbouring sites, half a cell away
+__device__ __forceinline__ void lo_grad(const Tile& T, int lx, int ly, double ihx, double ihy,
+                                        double* gr) {
+  double um, vm, tm, up, vp, tp;
+  lo_z(T, lx - 1, ly, um, vm, tm);
+  lo_z(T, lx + 1, ly, up, vp, tp);
+  gr[0] = (up - um) * ihx;
+  gr[1] = (vp - vm) * ihx;
+  gr[2] = (tp - tm) * ihx;
+  lo_z(T, lx, ly - 1, um, vm, tm);
+  lo_z(T, lx, ly + 1, up, vp, tp);
+  gr[3] = (up - um) * ihy;
+  gr[4] = (vp - vm) * ihy;
+  gr[5] = (tp - tm) * ihy;
+}
+
+// low-order point value U^L = U - sum_d (2 dt/h_d) (F^L(z, z+e_d) - F^L(z-e_d, z))
+// of the point at (lx, ly), with the LLF flux
+// F^L(a, b) = (F_a + F_b)/2 - (max(|u_d|+c) + max(b_d))/2 (U_b - U_a)
+__device__ __forceinline__ void lo_point(const Tile& T, const Phys& ph, int lx, int ly,
+                                         double dx, double dy, double dt, double* UL) {
+  const double ihx = 1.0 / dx, ihy = 1.0 / dy;
+  double U0[4], w0[5], g0[6];
+  lo_state(T, lx, ly, U0, w0);
+  lo_grad(T, lx, ly, ihx, ihy, g0);
+  double bx0, by0;
+  bvisc2_xy(w0[2], w0[3], g0[0], g0[1], g0[2], g0[3], g0[4], g0[5], ph, bx0, by0);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) UL[k] = U0[k];
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+    double F0[4];
+    tot_flux(d, U0, w0[0], w0[1], w0[2], g0, ph, F0);
+    const double r0 = fabs(w0[d]) + w0[4];
+    const double b0 = d == 0 ? bx0 : by0;
+    double Fp[4];
+    // the two neighbours one after the other (rolled: short live ranges)
+#pragma unroll 1
+    for (int sg = 1; sg >= -1; sg -= 2) {
+      const int nx = lx + (d == 0 ? sg : 0), ny = ly + (d == 1 ? sg : 0);
+      double Un[4], wn[5], gn[6], Fn[4];
+      lo_state(T, nx, ny, Un, wn);
+      lo_grad(T, nx, ny, ihx, ihy, gn);
+      tot_flux(d, Un, wn[0], wn[1], wn[2], gn, ph, Fn);
+      const double bn = bvisc2_dir(d, wn[2], wn[3], gn[0], gn[1], gn[2], gn[3], gn[4], gn[5], ph);
+      const double lam = mx(r0, fabs(wn[d]) + wn[4]) + mx(b0, bn);
+      if (sg == 1) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Fp[k] = 0.5 * (F0[k] + Fn[k]) - 0.5 * lam * (Un[k] - U0[k]);
+      } else {
+        const double c = 2.0 * dt * (d == 0 ? ihx : ihy);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const double Fm = 0.5 * (Fn[k] + F0[k]) - 0.5 * lam * (U0[k] - Un[k]);
+          UL[k] -= c * (Fp[k] - Fm);
+        }
+      }
+    }
+  }
 }
 
 // raw values of the lattice region of the tile at (X0, Y0): point sites hold
@@ -334,7 +441,7 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
     const int i = i0 - 1 + s % WC, j = j0 - 1 + s / WC;
     if (i > g.n1 || j > g.n2) continue;
     const int a = (2 * j + 1 - Y0 + 4) * WA + (2 * i + 1 - X0 + 4);
-    double C0[4], Cxm[4], Cxp[4], Cym[4], Cyp[4], o[18];
+    double C0[4], Cxm[4], Cxp[4], Cym[4], Cyp[4], o[23];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       C0[k] = T.U[k][a];
@@ -345,7 +452,7 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
     }
     cell_low(g, ph, C0, Cxm, Cxp, Cym, Cyp, o);
 #pragma unroll
-    for (int k = 0; k < 18; ++k) T.C[k][s] = o[k];
+    for (int k = 0; k < 23; ++k) T.C[k][s] = o[k];
   }
   for (int s = tid; s < NA; s += NT) {
     const int X = X0 - 4 + s % WA, Y = Y0 - 4 + s / WA;
@@ -387,7 +494,7 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
   const int next = it.advance();
   if (next >= 0) load_raw(g, Uk, 2 * TX * (next % ntx), 2 * TY * (next / ntx), tid, pre);
 
-  // ---- phase 1: gradients and viscous speeds on the block +- 2 ----
+  // ---- phase 1: gradients on the block +- 2 ----
   {
     const double ihx = 1.0 / (6.0 * g.dx), ihy = 1.0 / (6.0 * g.dy);
     for (int s = tid; s < NG; s += NT) {
@@ -405,10 +512,6 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
       }
 #pragma unroll
       for (int c = 0; c < 6; ++c) T.G[c][s] = gr[c];
-      double bx, by;
-      bvisc2_xy(T.A[2][a], T.A[3][a], gr[0], gr[1], gr[2], gr[3], gr[4], gr[5], ph, bx, by);
-      T.B[0][s] = bx;
-      T.B[1][s] = by;
     }
   }
   __syncthreads();
@@ -635,14 +738,8 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
         UH[k] = U0[k] + dt * R[k];
       }
       if (ph.lim & LIM_POINT) {
-        double Fxp[4], Fxm[4], Fyp[4], Fym[4], UL[4];
-        llf_pair(T, ph, a, q, a + 1, q + 1, 0, Fxp);
-        llf_pair(T, ph, a - 1, q - 1, a, q, 0, Fxm);
-        llf_pair(T, ph, a, q, a + WA, q + WG, 1, Fyp);
-        llf_pair(T, ph, a - WA, q - WG, a, q, 1, Fym);
-        const double cx = 2.0 * dt / g.dx, cy = 2.0 * dt / g.dy;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) UL[k] = U0[k] - cx * (Fxp[k] - Fxm[k]) - cy * (Fyp[k] - Fym[k]);
+        double UL[4];
+        lo_point(T, ph, X - X0 + 4, Y - Y0 + 4, g.dx, g.dy, dt, UL);
         bool lbad = false;
         const double th = theta_pair2(UL, UH, ph.gm1, lbad);
         if (lbad) raise_flag(flags, FLAG_POINT_LOW);
