@@ -25,8 +25,8 @@ METRIC = "cell-DOF updates/s per RK stage, 2D viscous shock tube; % peak HBM BW;
 HBM_PEAK_GBS = 8000.0
 FP64_VALU_PEAK_TFLOPS = 78.6
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-KERNEL_SOURCES = ["paper_2609_29081_amd/csrc/af_kern2d.hip", "paper_2609_29081_amd/csrc/af_device.hpp",
-                  "paper_2609_29081_amd/csrc/af_common.hip", "paper_2609_29081_amd/csrc/af_capi.cpp"]
+KERNEL_SOURCES = ["paper_2609_29081_amd/csrc/af_stage2d.hip", "paper_2609_29081_amd/csrc/af_device.hpp",
+                  "paper_2609_29081_amd/csrc/af_internal.hpp", "paper_2609_29081_amd/build.py"]
 
 
 def kernel_source_hash() -> str:

@@ -1,0 +1,131 @@
+"""HBM traffic of the fused 2D stage kernel from rocprofv3 counters.
+
+    python -m paper_2609_29081_amd.prof_traffic            # driver (GPU machine)
+    python -m paper_2609_29081_amd.prof_traffic --target   # profiled program
+
+The driver runs two counter passes (FETCH_SIZE, then WRITE_SIZE) over the
+target, which launches the stage kernel on the 1000 x 500 shock tube (the
+benchmark's launch configuration, averaged over the three RK3 stage kinds)
+and then a plain device copy of known size.  Each counter is scaled by what
+it reads for that copy (bytes moved / counter value), and the result is
+written to profiles/traffic.json (read by bench.py, keyed on a hash of the
+kernel sources so that a stale measurement is never reported) and
+profiles/stage2d_shock_tube_1000x500_traffic.md.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+COPY_BYTES = 256 * 1024 * 1024
+N1, N2 = 1000, 500
+
+
+def target(reps: int = 3) -> None:
+    sys.path.insert(0, ROOT)
+    import torch
+
+    from paper_2609_29081_amd import af
+    from paper_2609_29081_amd import workloads as W
+
+    g, f = W.shock_tube_2d(N1, N2)
+    S = af.Solver(g, mu=0.005, Pr=0.73, cfl_c=0.2, cfl_v=0.075)
+    U0 = S.to_device(W.make_state(g, f, 1.4))
+    U1 = torch.empty_like(U0)
+    U2 = torch.empty_like(U0)
+    dt = 1e-6
+    for _ in range(reps):  # stage kinds 0, 1, 2 as in one RK3 step
+        S.af_rk_stage(0, None, U0, U1, dt=dt)
+        S.af_rk_stage(1, U0, U1, U2, dt=dt)
+        S.af_rk_stage(2, U0, U2, U1, dt=dt)
+    torch.cuda.synchronize()
+    a = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print("target done", flush=True)
+
+
+def _pass(counter: str, outdir: str) -> dict:
+    cmd = ["timeout", "-s", "KILL", "120", "rocprofv3", "--pmc", counter, "--output-format", "csv",
+           "-d", outdir, "-o", "run", "--", sys.executable, "-m", "paper_2609_29081_amd.prof_traffic",
+           "--target"]
+    env = dict(os.environ, TMPDIR="/tmp",
+               PYTHONPATH=ROOT + os.pathsep + os.environ.get("PYTHONPATH", ""))
+    subprocess.run(cmd, check=True, cwd="/tmp", env=env)
+    files = glob.glob(os.path.join(outdir, "**", "*counter_collection.csv"), recursive=True)
+    vals = {"stage": [], "copy": []}
+    for fn in files:
+        for r in csv.DictReader(open(fn)):
+            name = r["Kernel_Name"]
+            v = float(r["Counter_Value"])
+            if "k_stage" in name:
+                vals["stage"].append(v)
+            elif "copyBuffer" in name or "copy" in name.lower() and "elementwise" not in name:
+                vals["copy"].append(v)
+    return vals
+
+
+def driver(outroot: str) -> None:
+    sys.path.insert(0, ROOT)
+    import bench
+
+    res = {}
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        res[c] = _pass(c, os.path.join(outroot, c.lower()))
+    fetch_kib = sum(res["FETCH_SIZE"]["stage"]) / len(res["FETCH_SIZE"]["stage"])
+    write_kib = sum(res["WRITE_SIZE"]["stage"]) / len(res["WRITE_SIZE"]["stage"])
+    copy_fetch = max(res["FETCH_SIZE"]["copy"])
+    copy_write = max(res["WRITE_SIZE"]["copy"])
+    f_scale = COPY_BYTES / copy_fetch      # bytes per counter unit, reads
+    w_scale = COPY_BYTES / copy_write      # bytes per counter unit, writes
+    fetch_b = fetch_kib * f_scale
+    write_b = write_kib * w_scale
+    out = {"kernel": "stage2d", "n1": N1, "n2": N2,
+           "kernel_source_hash": bench.kernel_source_hash(),
+           "fetch_counter_kib": fetch_kib, "write_counter_kib": write_kib,
+           "copy_fetch_counter": copy_fetch, "copy_write_counter": copy_write,
+           "fetch_scale_bytes_per_unit": f_scale, "write_scale_bytes_per_unit": w_scale,
+           "fetch_bytes": fetch_b, "write_bytes": write_b,
+           "bytes_per_launch": fetch_b + write_b,
+           "launches_averaged": len(res["FETCH_SIZE"]["stage"])}
+    prof = os.path.join(ROOT, "profiles")
+    os.makedirs(prof, exist_ok=True)
+    with open(os.path.join(prof, "traffic.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    cmdline = "python -m paper_2609_29081_amd.prof_traffic"
+    md = [f"# HBM traffic of the fused 2D stage kernel (shock tube {N1}x{N2}, FP64)", "",
+          f"Command: `{cmdline}` (two rocprofv3 passes: `--pmc FETCH_SIZE`, `--pmc WRITE_SIZE`,",
+          "each over `python -m paper_2609_29081_amd.prof_traffic --target`).", "",
+          "| quantity | value |", "|---|---|",
+          f"| stage launches averaged | {out['launches_averaged']} |",
+          f"| FETCH_SIZE per launch (counter) | {fetch_kib:.1f} |",
+          f"| WRITE_SIZE per launch (counter) | {write_kib:.1f} |",
+          f"| copy of {COPY_BYTES} B: FETCH_SIZE / WRITE_SIZE (counter) | {copy_fetch:.1f} / {copy_write:.1f} |",
+          f"| scale, bytes per counter unit (read / write) | {f_scale:.1f} / {w_scale:.1f} |",
+          f"| read bytes per launch | {fetch_b / 1e6:.1f} MB |",
+          f"| written bytes per launch | {write_b / 1e6:.1f} MB |",
+          f"| total per launch | {(fetch_b + write_b) / 1e6:.1f} MB |",
+          f"| kernel source hash | {out['kernel_source_hash']} |"]
+    with open(os.path.join(prof, "stage2d_shock_tube_1000x500_traffic.md"), "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--target", action="store_true")
+    ap.add_argument("--out", default=os.path.join(ROOT, "gpurun_out", "traffic"))
+    a = ap.parse_args()
+    if a.target:
+        target()
+    else:
+        driver(a.out)
