@@ -588,6 +588,7 @@ static int fe1(const orc_cfg* c, const double* U, double dt, double* Ufe, double
       for (int r = 0; r < 3; ++r) UL[r] = U0[r] - 2.0 * dt / dx * (Fp[r] - Fm[r]);
       int bad = 0;
       double th = theta_pair(c, UL, UH, &bad);
+      if (c->limiter & ORC_LIM_LOWONLY) th = 0.0; /* low-order point values */
       if (bad) flags |= ORC_FLAG_POINT_LOW;
       for (int r = 0; r < 3; ++r) out[r] = (th == 1.0) ? UH[r] : UL[r] + th * (UH[r] - UL[r]);
     } else {
@@ -1085,6 +1086,7 @@ static int fe2(const orc_cfg* c, const double* U, double dt, double* Ufe, double
             UL[k] = U0[k] - 2.0 * dt / dx * (Fxp[k] - Fxm[k]) - 2.0 * dt / dy * (Fyp[k] - Fym[k]);
           int bad = 0;
           double th = theta_pair(c, UL, UH, &bad);
+          if (c->limiter & ORC_LIM_LOWONLY) th = 0.0; /* low-order point values */
           if (bad) fl |= ORC_FLAG_POINT_LOW;
           for (int k = 0; k < 4; ++k) out[k] = (th == 1.0) ? UH[k] : UL[k] + th * (UH[k] - UL[k]);
         } else {

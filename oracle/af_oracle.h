@@ -37,7 +37,8 @@ enum {
   ORC_LIM_PP = 2,      /* density/pressure limiting of cell-average fluxes */
   ORC_LIM_POINT = 4,   /* scaling limiter of point values                 */
   ORC_LIM_CENTRE = 8,  /* scaling limiter of reconstructed centre values  */
-  ORC_LIM_LOWONLY = 16 /* diagnostic: use only the low-order LLF fluxes   */
+  ORC_LIM_LOWONLY = 16 /* diagnostic: low-order LLF cell fluxes and, with
+                          ORC_LIM_POINT, low-order point values          */
 };
 
 /* status flags raised by one forward-Euler stage */

@@ -205,6 +205,69 @@ def test_low_order_mode_is_rusanov_at_mu0():
     assert np.abs(g.split(out)["avg"][:, 0, :] - ref).max() < 1e-13 * np.abs(ref).max()
 
 
+def _euler_flux(V, d):
+    r, m1, m2, E = V
+    u, v = m1 / r, m2 / r
+    p = (GAMMA - 1) * (E - 0.5 * (m1 * u + m2 * v))
+    ud = u if d == 0 else v
+    F = np.array([V[1 + d], m1 * ud + (p if d == 0 else 0 * p), m2 * ud + (p if d == 1 else 0 * p),
+                  (E + p) * ud])
+    return F, np.abs(ud) + np.sqrt(GAMMA * p / r)
+
+
+def test_low_order_point_values_are_rusanov_on_the_half_lattice_1d():
+    """Sec. 3.4 at mu = 0: the low-order point update is the Rusanov scheme on
+    the half-spaced lattice whose sites alternate point value, cell average"""
+    g = W.Grid(dim=1, n1=48, bc=(W.PERIODIC,) * 4)
+    rng = np.random.default_rng(5)
+    amp = rng.uniform(-0.3, 0.3, size=4)
+
+    def f(x):
+        return (1 + amp[0] * np.sin(2 * np.pi * x) + 0.2 * np.sign(np.sin(6 * np.pi * x)),
+                0.4 + amp[1] * np.cos(4 * np.pi * x), 1.5 + amp[2] * np.sin(2 * np.pi * x) ** 2)
+    U = W.make_state(g, f, GAMMA)
+    c = O.make_cfg(g, mu=0.0, limiter=O.LIM_LOWONLY | O.LIM_POINT)
+    dt = 0.5 * O.dt(c, U)
+    out, fl = O.fe(c, U, dt)
+    P = g.split(U)
+    H = np.empty((3, 2 * g.n1))
+    H[:, 0::2] = P["pts"][:, 0, :]
+    H[:, 1::2] = P["avg"][:, 0, :]
+    ref = rusanov_1d(H, dt, g.dx / 2, W.PERIODIC)[:, 0::2]
+    got = g.split(out)["pts"][:, 0, :]
+    assert fl == 0
+    assert np.abs(got - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+def test_low_order_point_values_are_rusanov_on_the_half_lattice_2d():
+    """the 2D counterpart: a dimension-by-dimension Rusanov update on the half
+    lattice (points at edge midpoints and corners, averages at centres)"""
+    g, f = W.random_smooth_2d(12, 10, seed=4, bc=(W.PERIODIC,) * 4, amp=0.25)
+    U = W.make_state(g, f, GAMMA)
+    c = O.make_cfg(g, mu=0.0, limiter=O.LIM_LOWONLY | O.LIM_POINT)
+    dt = 0.5 * O.dt(c, U)
+    out, fl = O.fe(c, U, dt)
+    P = g.split(U)
+    H = np.empty((4, 2 * g.n2, 2 * g.n1))
+    H[:, 1::2, 1::2] = P["avg"]
+    H[:, 1::2, 0::2] = P["xe"]
+    H[:, 0::2, 1::2] = P["ye"]
+    H[:, 0::2, 0::2] = P["co"]
+    ref = H.copy()
+    for d, h, ax in ((0, g.dx / 2, 2), (1, g.dy / 2, 1)):
+        F, s = _euler_flux(H, d)
+        Hr, Fr, sr = np.roll(H, -1, axis=ax), np.roll(F, -1, axis=ax), np.roll(s, -1, axis=ax - 1)
+        Fh = 0.5 * (F + Fr) - 0.5 * np.maximum(s, sr) * (Hr - H)
+        ref -= dt / h * (Fh - np.roll(Fh, 1, axis=ax))
+    Q = g.split(out)
+    assert fl == 0
+    for name, sl in (("xe", (slice(1, None, 2), slice(0, None, 2))),
+                     ("ye", (slice(0, None, 2), slice(1, None, 2))),
+                     ("co", (slice(0, None, 2), slice(0, None, 2)))):
+        r = ref[:, sl[0], sl[1]]
+        assert np.abs(Q[name] - r).max() < 1e-13 * np.abs(r).max(), name
+
+
 def test_low_order_states_admissible_under_sufficient_cfl():
     """Prop. 3.1: dt <= dx/(2 d max lambda) keeps U^{L,+-} admissible"""
     g, f = W.leblanc_1d(200)
