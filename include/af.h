@@ -62,7 +62,11 @@ enum {
   AF_LIM_PP = 2,     /* density/pressure blend theta^rho theta^p of cell fluxes  */
   AF_LIM_POINT = 4,  /* scaling limiter of point values toward the point LLF     */
   AF_LIM_CENTRE = 8, /* scaling of Simpson centre values toward the cell average */
-  AF_LIM_ALL = 15
+  AF_LIM_ALL = 15,
+  /* diagnostic: the low-order schemes alone (blend parameters 0): LLF cell
+     fluxes (Sec. 3.1) and, together with AF_LIM_POINT, the low-order point
+     values (Sec. 3.4) */
+  AF_LIM_LOWONLY = 16
 };
 
 /* sticky status flags accumulated in the workspace by af_rk_stage */

@@ -147,7 +147,7 @@ __global__ void __launch_bounds__(kBlock) k_face1(G1 g, Phys ph, const double* _
   const double dt = dt_dev ? *dt_dev : dt_host;
   double FH[3], F[3];
   site_flux1(g, ph, LU, LA, LG, 2 * f + kMargin, FH);
-  const int limc = ph.lim & (LIM_SMOOTH | LIM_PP | 16);
+  const int limc = ph.lim & (LIM_SMOOTH | LIM_PP | LIM_LOWONLY);
   if (!limc) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) F[k] = FH[k];
@@ -165,7 +165,7 @@ __global__ void __launch_bounds__(kBlock) k_face1(G1 g, Phys ph, const double* _
       FL[k] = 0.5 * (Fa[k] + Fb[k]) - 0.5 * lam * (Ub[k] - Ua[k]);
     }
     double ts = 1.0, tpp = 1.0;
-    if (ph.lim & 16) {
+    if (ph.lim & LIM_LOWONLY) {
       ts = 0.0;
       tpp = 0.0;
     } else {
@@ -341,7 +341,8 @@ __global__ void __launch_bounds__(kBlock) k_points1(G1 g, Phys ph, const double*
 #pragma unroll
     for (int k = 0; k < 3; ++k) UL[k] = U0[k] - c2 * (Fp[k] - Fm[k]);
     bool lbad = false;
-    const double th = theta_pair1(UL, UH, ph.gm1, lbad);
+    double th = theta_pair1(UL, UH, ph.gm1, lbad);
+    if (ph.lim & LIM_LOWONLY) th = 0.0;
     if (lbad) raise_flag(flags, FLAG_POINT_LOW);
 #pragma unroll
     for (int k = 0; k < 3; ++k) out[k] = (th == 1.0) ? UH[k] : UL[k] + th * (UH[k] - UL[k]);

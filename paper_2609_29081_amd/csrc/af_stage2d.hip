@@ -517,7 +517,7 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
   __syncthreads();
 
   // ---- phase 3: limited face fluxes of the tile's cells ----
-  const int limc = ph.lim & (LIM_SMOOTH | LIM_PP | 16);
+  const int limc = ph.lim & (LIM_SMOOTH | LIM_PP | LIM_LOWONLY);
   for (int s = tid; s < NFX + NFY; s += NT) {
     const int d = s < NFX ? 0 : 1;
     int ff, jj, i, j, X, Y;  // face (i,j) between cells a (minus) and b (plus)
@@ -565,7 +565,7 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
         FL[k] = 0.5 * (Fca[k] + Fcb[k]) - 0.5 * lam * (Ub[k] - Ua[k]);
       }
       double ts = 1.0, tpp = 1.0;
-      if (ph.lim & 16) {
+      if (ph.lim & LIM_LOWONLY) {
         ts = 0.0;
         tpp = 0.0;
       } else {
@@ -741,7 +741,8 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
         double UL[4];
         lo_point(T, ph, X - X0 + 4, Y - Y0 + 4, g.dx, g.dy, dt, UL);
         bool lbad = false;
-        const double th = theta_pair2(UL, UH, ph.gm1, lbad);
+        double th = theta_pair2(UL, UH, ph.gm1, lbad);
+        if (ph.lim & LIM_LOWONLY) th = 0.0;
         if (lbad) raise_flag(flags, FLAG_POINT_LOW);
 #pragma unroll
         for (int k = 0; k < 4; ++k) out[k] = (th == 1.0) ? UH[k] : UL[k] + th * (UH[k] - UL[k]);

@@ -7,10 +7,11 @@ The driver runs two counter passes (FETCH_SIZE, then WRITE_SIZE) over the
 target, which launches the stage kernel on the 1000 x 500 shock tube (the
 benchmark's launch configuration, averaged over the three RK3 stage kinds)
 and then a plain device copy of known size.  Each counter is scaled by what
-it reads for that copy (bytes moved / counter value), and the result is
-written to profiles/traffic.json (read by bench.py, keyed on a hash of the
-kernel sources so that a stale measurement is never reported) and
-profiles/stage2d_shock_tube_1000x500_traffic.md.
+it reads for that copy (bytes moved / counter value).  The driver writes
+traffic.json and stage2d_shock_tube_1000x500_traffic.md into its output
+folder (--out); copied into profiles/, traffic.json is what bench.py reports
+as the measured traffic, as long as its hash of the kernel sources still
+matches (a stale measurement is never reported).
 """
 from __future__ import annotations
 
@@ -97,23 +98,27 @@ def driver(outroot: str) -> None:
            "fetch_bytes": fetch_b, "write_bytes": write_b,
            "bytes_per_launch": fetch_b + write_b,
            "launches_averaged": len(res["FETCH_SIZE"]["stage"])}
-    prof = os.path.join(ROOT, "profiles")
+    prof = outroot
     os.makedirs(prof, exist_ok=True)
     with open(os.path.join(prof, "traffic.json"), "w") as fh:
         json.dump(out, fh, indent=1)
     cmdline = "python -m paper_2609_29081_amd.prof_traffic"
+    alg = 8.0 * 8.0 / 3.0 * (4 * (N1 * N2 + (N1 + 1) * N2 + N1 * (N2 + 1) + (N1 + 1) * (N2 + 1)))
     md = [f"# HBM traffic of the fused 2D stage kernel (shock tube {N1}x{N2}, FP64)", "",
-          f"Command: `{cmdline}` (two rocprofv3 passes: `--pmc FETCH_SIZE`, `--pmc WRITE_SIZE`,",
-          "each over `python -m paper_2609_29081_amd.prof_traffic --target`).", "",
+          f"Command: `{cmdline}` (two rocprofv3 passes, `--pmc FETCH_SIZE`",
+          "then `--pmc WRITE_SIZE`, each over `python -m paper_2609_29081_amd.prof_traffic --target`:",
+          "three RK3 steps' worth of stage launches, then a 256 MiB device copy for calibration).", "",
           "| quantity | value |", "|---|---|",
           f"| stage launches averaged | {out['launches_averaged']} |",
-          f"| FETCH_SIZE per launch (counter) | {fetch_kib:.1f} |",
-          f"| WRITE_SIZE per launch (counter) | {write_kib:.1f} |",
+          f"| FETCH_SIZE per launch (counter, KiB) | {fetch_kib:.1f} |",
+          f"| WRITE_SIZE per launch (counter, KiB) | {write_kib:.1f} |",
           f"| copy of {COPY_BYTES} B: FETCH_SIZE / WRITE_SIZE (counter) | {copy_fetch:.1f} / {copy_write:.1f} |",
           f"| scale, bytes per counter unit (read / write) | {f_scale:.1f} / {w_scale:.1f} |",
           f"| read bytes per launch | {fetch_b / 1e6:.1f} MB |",
           f"| written bytes per launch | {write_b / 1e6:.1f} MB |",
           f"| total per launch | {(fetch_b + write_b) / 1e6:.1f} MB |",
+          "| algorithmic bytes per launch (mean of the 3 stages: 5/3 states read, 1 written) | "
+          f"{alg / 1e6:.1f} MB |",
           f"| kernel source hash | {out['kernel_source_hash']} |"]
     with open(os.path.join(prof, "stage2d_shock_tube_1000x500_traffic.md"), "w") as fh:
         fh.write("\n".join(md) + "\n")

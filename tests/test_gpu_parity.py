@@ -135,7 +135,8 @@ def test_stage_1d_density_pressure_limiting_active():
 
 
 @pytest.mark.parametrize("limiter", [0, O.LIM_SMOOTH, O.LIM_PP, O.LIM_POINT, O.LIM_CENTRE,
-                                     O.LIM_LOWONLY, O.LIM_LOWONLY | O.LIM_PP])
+                                     O.LIM_LOWONLY, O.LIM_LOWONLY | O.LIM_PP,
+                                     O.LIM_LOWONLY | O.LIM_POINT])
 def test_stage_2d_limiter_switches(limiter):
     """every switch on a mild shock tube (density ratio 2.5), where even the
     unlimited scheme keeps every state admissible"""
