@@ -75,7 +75,8 @@ def main() -> int:
     ap.add_argument("--n2", type=int, default=500)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget of the CPU-oracle baseline sample (0 disables it)")
-    ap.add_argument("--timing-steps", type=int, default=10)
+    ap.add_argument("--roofline-reps", type=int, default=10,
+                    help="repetitions of the three stage kinds timed for the roofline")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -131,17 +132,24 @@ def main() -> int:
     stage_bytes = 8.0 * g.state_len * 8.0 / 3.0     # mean over the 3 stages: (2+3+3)/3 states
     stage_gbs = stage_bytes / (stage_ms * 1e-3) / 1e9
 
-    # per-kernel durations, measured live with HIP events on the launch stream
+    # RK3 attempts per accepted step over the same window (a rejected attempt
+    # is redone with dt/2; its stages stop at the first flag): launch counts
     U.copy_(dev_U0)
     torch.cuda.synchronize()
     S.af_timing(True)
     S.af_timing_read()
-    st, _, _ = S.af_run(U, 0.0, 1e30, args.timing_steps, check_every=1)
+    st, _, _ = S.af_run(U, 0.0, 1e30, K, check_every=1)
+    kw_ = S.af_timing_read()
+    stage_kind = "stage2d" if "stage2d" in kw_ else "lattice"
+    attempts_per_step = kw_[stage_kind][0] / (3.0 * K)
+    # per-kernel durations of complete stage launches (the three RK3 stage
+    # kinds from the initial state at its CFL dt), measured live with HIP
+    # events on the launch stream
+    from paper_2609_29081_amd.prof_counters import stage_sequence
+    S.af_timing_read()
+    stage_sequence(S, dev_U0, args.roofline_reps)
     kt = S.af_timing_read()
     S.af_timing(False)
-    # RK3 attempts per accepted step (a rejected attempt is redone with dt/2)
-    stage_kind = "stage2d" if "stage2d" in kt else "lattice"
-    attempts_per_step = kt[stage_kind][0] / (3.0 * args.timing_steps)
     alg = algorithmic_bytes(g)
     kernels = {}
     for name, (n, ms) in kt.items():
@@ -156,17 +164,30 @@ def main() -> int:
     dom = max(kt.items(), key=lambda kv: kv[1][1])[0]
     dom_avg_s = kt[dom][1] / kt[dom][0] * 1e-3
     achieved = alg[dom] / dom_avg_s / 1e9
-    traffic = None
+    traffic = flops = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fh:
             tr = json.load(fh)
         if tr.get("kernel_source_hash") == kernel_source_hash() and tr.get("kernel") == dom \
                 and tr.get("n1") == g.n1 and tr.get("n2") == g.n2:
             traffic = tr.get("bytes_per_launch")
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "alg_bytes_per_launch": alg[dom],
-                "avg_launch_us": round(dom_avg_s * 1e6, 3)}
+            flops = tr.get("fp64_flops_per_launch")
+    hbm = {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": alg[dom]}
+    if flops:
+        # the stage executes ~20 FP64 flops per algorithmic byte, twice the
+        # FP64 ridge: the FP64 VALU is the binding roof
+        tf = flops / dom_avg_s / 1e12
+        roofline = {"bound": "alu", "kernel": dom, "achieved": round(tf, 2),
+                    "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(tf / FP64_VALU_PEAK_TFLOPS, 4), "traffic": traffic,
+                    "flops_per_launch": flops,
+                    "flops_kind": "executed FP64 flops (rocprofv3 counters, 64 lanes per wave "
+                                  "instruction), an upper bound on the algorithmic count",
+                    "avg_launch_us": round(dom_avg_s * 1e6, 3), "hbm": hbm}
+    else:
+        roofline = dict({"bound": "hbm", "kernel": dom, "traffic": traffic,
+                         "avg_launch_us": round(dom_avg_s * 1e6, 3)}, **hbm)
 
     # CPU baseline: the FP64 oracle on the host cores, first steps of the same
     # workload, and the L1 difference of the GPU after the same steps
@@ -209,6 +230,7 @@ def main() -> int:
         "roofline": roofline,
         "kernels": kernels,
         "rk3_attempts_per_step": round(attempts_per_step, 3),
+        "stage_launches_per_s": kw_[stage_kind][0] / sec,
         "cpu_baseline": cpu,
         "l1_err_vs_oracle": l1,
         "linf_rel_vs_oracle": linf if cpu else None,

@@ -134,14 +134,18 @@ afd::Phys physics(const af_params& p) {
   return ph;
 }
 
-const afi::StageCoef kCoef[3] = {{0.0, 1.0, 1}, {0.75, 0.25, 0}, {1.0 / 3.0, 2.0 / 3.0, 0}};
+const afi::StageCoef kCoef[3] = {{0.0, 1.0, 1, 0}, {0.75, 0.25, 0, 0}, {1.0 / 3.0, 2.0 / 3.0, 0, 0}};
 
+// in_step: the stage is part of a step attempt (af_step, af_run), whose
+// output is discarded once a flag is raised, so it may stop early
 hipError_t launch_stage(const afi::Geo& g, const afd::Phys& ph, const afi::Work& w, int k,
                         const double* Un, const double* Uk, double* Uout, const double* dt_dev,
-                        double dt_host, hipStream_t s, afi::Timer* tm) {
+                        double dt_host, hipStream_t s, afi::Timer* tm, bool in_step = true) {
   if (!Un) Un = Uk;
-  return g.dim == 1 ? afi::stage1d(g, ph, w, Un, Uk, Uout, dt_dev, dt_host, kCoef[k], s, tm)
-                    : afi::stage2d(g, ph, w, Un, Uk, Uout, dt_dev, dt_host, kCoef[k], s, tm);
+  afi::StageCoef sc = kCoef[k];
+  sc.skip_flagged = in_step ? 1 : 0;
+  return g.dim == 1 ? afi::stage1d(g, ph, w, Un, Uk, Uout, dt_dev, dt_host, sc, s, tm)
+                    : afi::stage2d(g, ph, w, Un, Uk, Uout, dt_dev, dt_host, sc, s, tm);
 }
 
 hipError_t launch_cfl(const af_ctx* c, const afi::Geo& g, const afi::Work& w, const double* U,
@@ -294,7 +298,7 @@ af_status af_rk_stage(af_ctx* c, int k, const double* dt_dev, double dt_host, co
   afi::Work w;
   afi::workspace_layout(g, &w, (char*)ws);
   hipError_t e = launch_stage(g, physics(c->p), w, k, Un, Uk, Uout, dt_dev, dt_host,
-                              (hipStream_t)stream, c->timer);
+                              (hipStream_t)stream, c->timer, false);
   if (e != hipSuccess) return hip_fail(e, "af_rk_stage launch");
   return AF_OK;
 }

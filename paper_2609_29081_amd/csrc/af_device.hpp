@@ -229,4 +229,10 @@ __device__ __forceinline__ void raise_flag(unsigned* flags, unsigned f) {
   atomicOr(flags, f);
 }
 
+// current value of the flag word, as other workgroups of a running kernel
+// may have raised it (device-coherent load)
+__device__ __forceinline__ unsigned peek_flags(unsigned* flags) {
+  return __hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 }  // namespace afd

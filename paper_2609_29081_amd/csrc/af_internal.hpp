@@ -45,6 +45,9 @@ struct Work {
 struct StageCoef {
   double a, b;
   int first;  // 1: Uout = FE(Uk)
+  // 1: the stage belongs to a step attempt and stops as soon as the attempt's
+  // flag word is set (the attempt is rejected, so its output is never used)
+  int skip_flagged;
 };
 
 size_t workspace_layout(const Geo& g, Work* w, char* base);

@@ -17,7 +17,15 @@ struct G1 {
   long off_pts;
   int bc0, bc1;
   double dx;
+  // inside a step attempt: stop once the attempt's flag word is set (it is
+  // rejected and the stage output is never read)
+  int skip_flagged;
+  unsigned* fl;
 };
+
+__device__ __forceinline__ bool rejected(const G1& g) {
+  return g.skip_flagged && peek_flags(g.fl) != 0u;
+}
 
 __device__ __forceinline__ double pt(const G1& g, const double* __restrict__ U, int X, int k) {
   if (X == 2 * g.n && g.np == g.n) X = 0;
@@ -39,7 +47,7 @@ __global__ void __launch_bounds__(kBlock) k_lattice1(G1 g, Phys ph, const double
                                                      double* __restrict__ LU,
                                                      double* __restrict__ LA) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= g.LX) return;
+  if (t >= g.LX || rejected(g)) return;
   const int X = t - kMargin;
   int kind;
   const int Xi = axis_image(X, 2 * g.n, g.bc0, g.bc1, kind);
@@ -84,7 +92,7 @@ __global__ void __launch_bounds__(kBlock) k_lattice1(G1 g, Phys ph, const double
 __global__ void __launch_bounds__(kBlock) k_grad1(G1 g, const double* __restrict__ LA,
                                                   double* __restrict__ LG) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 2 * g.n + 5) return;
+  if (t >= 2 * g.n + 5 || rejected(g)) return;
   const int q = t - 2 + kMargin;
   const double i6 = 1.0 / (6.0 * g.dx);
   const double* u = LA;
@@ -99,7 +107,7 @@ __global__ void __launch_bounds__(kBlock) k_cellpre1(G1 g, Phys ph, const double
                                                      double* __restrict__ CP) {
   const int nc = g.n + 2;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nc) return;
+  if (t >= nc || rejected(g)) return;
   const int i = t - 1;
   double C0[3], Cm[3], Cp[3];
   cell_image1(g, U, i, C0);
@@ -143,7 +151,7 @@ __global__ void __launch_bounds__(kBlock) k_face1(G1 g, Phys ph, const double* _
                                                   double dt_host, unsigned* flags) {
   const int nf = g.n + 1;
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= nf) return;
+  if (f >= nf || rejected(g)) return;
   const double dt = dt_dev ? *dt_dev : dt_host;
   double FH[3], F[3];
   site_flux1(g, ph, LU, LA, LG, 2 * f + kMargin, FH);
@@ -221,7 +229,7 @@ __global__ void __launch_bounds__(kBlock) k_cells1(G1 g, const double* __restric
                                                    const double* dt_dev, double dt_host, double ca,
                                                    double cb, int first, unsigned* flags) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.n) return;
+  if (i >= g.n || rejected(g)) return;
   const double dt = dt_dev ? *dt_dev : dt_host;
   const double m = dt / g.dx;
   const int nf = g.n + 1;
@@ -260,7 +268,7 @@ __global__ void __launch_bounds__(kBlock) k_points1(G1 g, Phys ph, const double*
                                                     double dt_host, double ca, double cb, int first,
                                                     unsigned* flags) {
   const int k0 = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k0 >= g.np) return;
+  if (k0 >= g.np || rejected(g)) return;
   const int X = 2 * k0;
   const int q = X + kMargin;
   const double dt = dt_dev ? *dt_dev : dt_host;
@@ -384,6 +392,8 @@ hipError_t stage1d(const Geo& geo, const Phys& ph, const Work& w, const double* 
   g.bc0 = geo.bc[0];
   g.bc1 = geo.bc[1];
   g.dx = geo.dx;
+  g.skip_flagged = sc.skip_flagged;
+  g.fl = w.flags;
   AFI_TIMED(tm, 0, s,
             hipLaunchKernelGGL(k_lattice1, dim3(nblk(g.LX)), dim3(kBlock), 0, s, g, ph, Uk, w.LU,
                                w.LA));

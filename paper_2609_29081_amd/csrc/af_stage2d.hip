@@ -409,8 +409,10 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
                                               const double* __restrict__ Un,
                                               double* __restrict__ Uout, const double* dt_dev,
                                               double dt_host, double ca, double cb, int first,
-                                              unsigned* flags, int ntx, int ntiles) {
+                                              int skip_flagged, unsigned* flags, int ntx,
+                                              int ntiles) {
   __shared__ Tile T;
+  __shared__ unsigned stop;  // workgroup-uniform copy of the flag word
   const int tid = threadIdx.x;
   const double dt = dt_dev ? *dt_dev : dt_host;
   const int Xlim = 2 * g.n1, Ylim = 2 * g.n2;
@@ -422,7 +424,11 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
   while (tile >= 0) {
   const int i0 = (tile % ntx) * TX, j0 = (tile / ntx) * TY;
   const int X0 = 2 * i0, Y0 = 2 * j0;
-  __syncthreads();  // the previous tile is done with the LDS
+  // inside a step attempt, stop once any workgroup has flagged the attempt:
+  // it is rejected and this output is never read
+  if (tid == 0) stop = skip_flagged ? peek_flags(flags) : 0u;
+  __syncthreads();  // the previous tile is done with the LDS; stop is visible
+  if (stop) break;
 
   // ---- phase 0a: raw values of the lattice region (prefetched) ----
 #pragma unroll
@@ -800,7 +806,8 @@ hipError_t stage2d(const Geo& geo, const Phys& ph, const Work& w, const double* 
   if (nwg >= 8) nwg -= nwg % 8;
   AFI_TIMED(tm, 7, s,
             hipLaunchKernelGGL(k_stage, dim3((unsigned)nwg), dim3(NT), 0, s, g, ph, Uk, Un, Uout,
-                               dt_dev, dt_host, sc.a, sc.b, sc.first, w.flags, ntx, ntiles));
+                               dt_dev, dt_host, sc.a, sc.b, sc.first, sc.skip_flagged, w.flags,
+                               ntx, ntiles));
   return hipGetLastError();
 }
 

@@ -1,17 +1,20 @@
-"""HBM traffic of the fused 2D stage kernel from rocprofv3 counters.
+"""HBM traffic and FP64 instruction counts of the fused 2D stage kernel
+from rocprofv3 counters.
 
-    python -m paper_2609_29081_amd.prof_traffic            # driver (GPU machine)
-    python -m paper_2609_29081_amd.prof_traffic --target   # profiled program
+    python -m paper_2609_29081_amd.prof_counters            # driver (GPU machine)
+    python -m paper_2609_29081_amd.prof_counters --target   # profiled program
 
-The driver runs two counter passes (FETCH_SIZE, then WRITE_SIZE) over the
-target, which launches the stage kernel on the 1000 x 500 shock tube (the
-benchmark's launch configuration, averaged over the three RK3 stage kinds)
+The driver runs three counter passes (FETCH_SIZE; WRITE_SIZE; the FP64 and
+LDS instruction counters) over the target, which launches the stage kernel on the 1000 x 500 shock tube (the
+benchmark's launch configuration, averaged over the three RK3 stage kinds;
+the same launch sequence as the roofline pass of bench.py)
 and then a plain device copy of known size.  Each counter is scaled by what
-it reads for that copy (bytes moved / counter value).  The driver writes
-traffic.json and stage2d_shock_tube_1000x500_traffic.md into its output
+it reads for that copy (bytes moved / counter value).  Executed FP64 flops
+count 64 lanes per wave instruction (2 per FMA).  The driver writes
+traffic.json and stage2d_shock_tube_1000x500_counters.md into its output
 folder (--out); copied into profiles/, traffic.json is what bench.py reports
-as the measured traffic, as long as its hash of the kernel sources still
-matches (a stale measurement is never reported).
+as the measured traffic and executed flops, as long as its hash of the
+kernel sources still matches (a stale measurement is never reported).
 """
 from __future__ import annotations
 
@@ -28,6 +31,20 @@ COPY_BYTES = 256 * 1024 * 1024
 N1, N2 = 1000, 500
 
 
+def stage_sequence(S, U0, reps: int) -> None:
+    """reps x the three RK3 stage kinds from U0 at its CFL dt, each launch a
+    complete stage (af_rk_stage never stops early); the launch sequence
+    whose mean duration bench.py reports in its roofline"""
+    import torch
+    U1 = torch.empty_like(U0)
+    U2 = torch.empty_like(U0)
+    dt_dev = S.af_cfl_dt(U0)
+    for _ in range(reps):
+        S.af_rk_stage(0, None, U0, U1, dt_dev=dt_dev)
+        S.af_rk_stage(1, U0, U1, U2, dt_dev=dt_dev)
+        S.af_rk_stage(2, U0, U2, U1, dt_dev=dt_dev)
+
+
 def target(reps: int = 3) -> None:
     sys.path.insert(0, ROOT)
     import torch
@@ -38,13 +55,7 @@ def target(reps: int = 3) -> None:
     g, f = W.shock_tube_2d(N1, N2)
     S = af.Solver(g, mu=0.005, Pr=0.73, cfl_c=0.2, cfl_v=0.075)
     U0 = S.to_device(W.make_state(g, f, 1.4))
-    U1 = torch.empty_like(U0)
-    U2 = torch.empty_like(U0)
-    dt = 1e-6
-    for _ in range(reps):  # stage kinds 0, 1, 2 as in one RK3 step
-        S.af_rk_stage(0, None, U0, U1, dt=dt)
-        S.af_rk_stage(1, U0, U1, U2, dt=dt)
-        S.af_rk_stage(2, U0, U2, U1, dt=dt)
+    stage_sequence(S, U0, reps)
     torch.cuda.synchronize()
     a = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
@@ -55,23 +66,31 @@ def target(reps: int = 3) -> None:
     print("target done", flush=True)
 
 
-def _pass(counter: str, outdir: str) -> dict:
-    cmd = ["timeout", "-s", "KILL", "120", "rocprofv3", "--pmc", counter, "--output-format", "csv",
-           "-d", outdir, "-o", "run", "--", sys.executable, "-m", "paper_2609_29081_amd.prof_traffic",
-           "--target"]
+FP64_COUNTERS = ["SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_ADD_F64",
+                 "SQ_INSTS_VALU_TRANS_F64", "SQ_INSTS_VALU", "SQ_INSTS_LDS"]
+
+
+def _pass(counters: list, outdir: str) -> dict:
+    """one rocprofv3 run collecting `counters`; returns
+    {counter: {"stage": [per launch], "copy": [per launch]}}"""
+    cmd = ["timeout", "-s", "KILL", "120", "rocprofv3", "--pmc", " ".join(counters),
+           "--output-format", "csv", "-d", outdir, "-o", "run", "--", sys.executable, "-m",
+           "paper_2609_29081_amd.prof_counters", "--target"]
     env = dict(os.environ, TMPDIR="/tmp",
                PYTHONPATH=ROOT + os.pathsep + os.environ.get("PYTHONPATH", ""))
     subprocess.run(cmd, check=True, cwd="/tmp", env=env)
     files = glob.glob(os.path.join(outdir, "**", "*counter_collection.csv"), recursive=True)
-    vals = {"stage": [], "copy": []}
+    vals = {c: {"stage": [], "copy": []} for c in counters}
     for fn in files:
         for r in csv.DictReader(open(fn)):
-            name = r["Kernel_Name"]
+            name, cname = r["Kernel_Name"], r["Counter_Name"]
+            if cname not in vals:
+                continue
             v = float(r["Counter_Value"])
             if "k_stage" in name:
-                vals["stage"].append(v)
-            elif "copyBuffer" in name or "copy" in name.lower() and "elementwise" not in name:
-                vals["copy"].append(v)
+                vals[cname]["stage"].append(v)
+            elif "copyBuffer" in name:
+                vals[cname]["copy"].append(v)
     return vals
 
 
@@ -81,7 +100,11 @@ def driver(outroot: str) -> None:
 
     res = {}
     for c in ("FETCH_SIZE", "WRITE_SIZE"):
-        res[c] = _pass(c, os.path.join(outroot, c.lower()))
+        res[c] = _pass([c], os.path.join(outroot, c.lower()))[c]
+    isa = _pass(FP64_COUNTERS, os.path.join(outroot, "fp64"))
+    per = {c: sum(isa[c]["stage"]) / len(isa[c]["stage"]) for c in FP64_COUNTERS}
+    flops = 64.0 * (2.0 * per["SQ_INSTS_VALU_FMA_F64"] + per["SQ_INSTS_VALU_MUL_F64"]
+                    + per["SQ_INSTS_VALU_ADD_F64"])
     fetch_kib = sum(res["FETCH_SIZE"]["stage"]) / len(res["FETCH_SIZE"]["stage"])
     write_kib = sum(res["WRITE_SIZE"]["stage"]) / len(res["WRITE_SIZE"]["stage"])
     copy_fetch = max(res["FETCH_SIZE"]["copy"])
@@ -97,17 +120,21 @@ def driver(outroot: str) -> None:
            "fetch_scale_bytes_per_unit": f_scale, "write_scale_bytes_per_unit": w_scale,
            "fetch_bytes": fetch_b, "write_bytes": write_b,
            "bytes_per_launch": fetch_b + write_b,
-           "launches_averaged": len(res["FETCH_SIZE"]["stage"])}
+           "launches_averaged": len(res["FETCH_SIZE"]["stage"]),
+           "instructions_per_launch": per,
+           "fp64_flops_per_launch": flops}
     prof = outroot
     os.makedirs(prof, exist_ok=True)
     with open(os.path.join(prof, "traffic.json"), "w") as fh:
         json.dump(out, fh, indent=1)
-    cmdline = "python -m paper_2609_29081_amd.prof_traffic"
+    cmdline = "python -m paper_2609_29081_amd.prof_counters"
     alg = 8.0 * 8.0 / 3.0 * (4 * (N1 * N2 + (N1 + 1) * N2 + N1 * (N2 + 1) + (N1 + 1) * (N2 + 1)))
-    md = [f"# HBM traffic of the fused 2D stage kernel (shock tube {N1}x{N2}, FP64)", "",
-          f"Command: `{cmdline}` (two rocprofv3 passes, `--pmc FETCH_SIZE`",
-          "then `--pmc WRITE_SIZE`, each over `python -m paper_2609_29081_amd.prof_traffic --target`:",
-          "three RK3 steps' worth of stage launches, then a 256 MiB device copy for calibration).", "",
+    md = [f"# Counters of the fused 2D stage kernel (shock tube {N1}x{N2}, FP64)", "",
+          f"Command: `{cmdline}` (three rocprofv3 passes, `--pmc FETCH_SIZE`,",
+          f"`--pmc WRITE_SIZE`, `--pmc {' '.join(FP64_COUNTERS)}`, each over",
+          "`python -m paper_2609_29081_amd.prof_counters --target`: three RK3 steps' worth of",
+          "complete stage launches at the CFL dt of the initial state, then a 256 MiB device copy",
+          "for calibration).", "",
           "| quantity | value |", "|---|---|",
           f"| stage launches averaged | {out['launches_averaged']} |",
           f"| FETCH_SIZE per launch (counter, KiB) | {fetch_kib:.1f} |",
@@ -120,7 +147,10 @@ def driver(outroot: str) -> None:
           "| algorithmic bytes per launch (mean of the 3 stages: 5/3 states read, 1 written) | "
           f"{alg / 1e6:.1f} MB |",
           f"| kernel source hash | {out['kernel_source_hash']} |"]
-    with open(os.path.join(prof, "stage2d_shock_tube_1000x500_traffic.md"), "w") as fh:
+    md += ["", "| instruction counter (per launch, wave instructions) | value |", "|---|---|"]
+    md += [f"| {c} | {per[c]:.4g} |" for c in FP64_COUNTERS]
+    md += [f"| executed FP64 flops per launch (64 lanes x (2 FMA + MUL + ADD)) | {flops:.4g} |"]
+    with open(os.path.join(prof, "stage2d_shock_tube_1000x500_counters.md"), "w") as fh:
         fh.write("\n".join(md) + "\n")
     print(json.dumps(out))
 
