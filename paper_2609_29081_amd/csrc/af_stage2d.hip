@@ -36,10 +36,13 @@ constexpr int WA = 2 * TX + 9, HA = 2 * TY + 9, NA = WA * HA;
 constexpr int WG = 2 * TX + 4, HG = 2 * TY + 4, NG = WG * HG;  // block +- 2
 constexpr int WC = TX + 2, HC = TY + 2, NC = WC * HC;          // tile cells +- 1
 constexpr int NFX = TY * (TX + 1), NFY = (TY + 1) * TX;
+constexpr int NCEN = (TX + 4) * (TY + 4);  // centre sites of the lattice region
+static_assert(NCEN <= NT / 2, "one centre per thread of the upper half");
 
 struct G2 {
   int n1, n2, n1x, n2y;
   long off_xe, off_ye, off_co;
+  int st_avg, st_xe, st_ye, st_co;  // distance between component planes
   int bc0, bc1, bc2, bc3;
   double dx, dy;
 };
@@ -53,6 +56,10 @@ G2 make_g2(const afi::Geo& g) {
   r.off_xe = g.off_xe;
   r.off_ye = g.off_ye;
   r.off_co = g.off_co;
+  r.st_avg = g.n1 * g.n2;
+  r.st_xe = g.n2 * g.n1x;
+  r.st_ye = g.n2y * g.n1;
+  r.st_co = g.n2y * g.n1x;
   r.bc0 = g.bc[0];
   r.bc1 = g.bc[1];
   r.bc2 = g.bc[2];
@@ -62,29 +69,44 @@ G2 make_g2(const afi::Geo& g) {
   return r;
 }
 
-// interior point DOF (X, Y not both odd), periodic seam folded
-__device__ __forceinline__ double dof(const G2& g, const double* __restrict__ U, int X, int Y,
-                                      int k) {
+// offset of interior lattice site (X, Y) in a state (its first component;
+// centre sites hold the cell average, the periodic seam is folded) and the
+// distance between its component planes.  Plane indices fit 32 bits (the
+// grid size is bounded at init).
+__device__ __forceinline__ void site_ofs(const G2& g, int X, int Y, long& o, int& st) {
   if (X == 2 * g.n1 && g.n1x == g.n1) X = 0;
   if (Y == 2 * g.n2 && g.n2y == g.n2) Y = 0;
-  if (Y & 1) return U[g.off_xe + ((long)k * g.n2 + (Y >> 1)) * g.n1x + (X >> 1)];
-  if (X & 1) return U[g.off_ye + ((long)k * g.n2y + (Y >> 1)) * g.n1 + (X >> 1)];
-  return U[g.off_co + ((long)k * g.n2y + (Y >> 1)) * g.n1x + (X >> 1)];
+  const bool xo = X & 1, yo = Y & 1;
+  const int ncol = xo ? g.n1 : g.n1x;
+  const long base = xo ? (yo ? 0L : g.off_ye) : (yo ? g.off_xe : g.off_co);
+  st = xo ? (yo ? g.st_avg : g.st_ye) : (yo ? g.st_xe : g.st_co);
+  o = base + (long)((Y >> 1) * ncol + (X >> 1));
 }
 
-__device__ __forceinline__ double avg(const G2& g, const double* __restrict__ U, int i, int j,
-                                      int k) {
-  return U[((long)k * g.n2 + j) * g.n1 + i];
+// (u, v, p, T, c) of state V, given 1/rho
+__device__ __forceinline__ void aux_of(const Phys& ph, const double* V, double ir, double* w) {
+  const double p = ph.gm1 * (V[3] - 0.5 * (V[1] * V[1] + V[2] * V[2]) * ir);
+  w[0] = V[1] * ir;
+  w[1] = V[2] * ir;
+  w[2] = p;
+  w[3] = p * ir;
+  w[4] = sqrt(ph.gam * w[3]);
 }
 
 // Simpson centre value from the cell average, the sum of the four edge
 // points and the sum of the four corners (Sec. 2.2), scaled toward the
-// average with the density-then-pressure rule when the centre limiter is on
+// average with the density-then-pressure rule when the centre limiter is on,
+// and its (u, v, p, T, c).  A centre whose density and pressure are already
+// at least eps keeps its value: the rule's parameter is 1 there (the rule is
+// continuous at that threshold, so only round-off separates the two
+// evaluations of the test)
 __device__ __forceinline__ void centre_value(const Phys& ph, const double* Ub, const double* e,
-                                             const double* c, double* V) {
+                                             const double* c, double* V, double* w) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) V[k] = (36.0 * Ub[k] - 4.0 * e[k] - c[k]) / 16.0;
-  if (ph.lim & LIM_CENTRE) {
+  double ir = 1.0 / V[0];
+  const double p = ph.gm1 * (V[3] - 0.5 * (V[1] * V[1] + V[2] * V[2]) * ir);
+  if ((ph.lim & LIM_CENTRE) && !(Ub[0] > 0.0 && V[0] >= kPPEps && p >= kPPEps)) {
     if (!(Ub[0] > 0.0)) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) V[k] = Ub[k];
@@ -96,7 +118,9 @@ __device__ __forceinline__ void centre_value(const Phys& ph, const double* Ub, c
         for (int k = 0; k < 4; ++k) V[k] = Ub[k] + th * (V[k] - Ub[k]);
       }
     }
+    ir = 1.0 / V[0];
   }
+  aux_of(ph, V, ir, w);
 }
 
 // conservative value at lattice site (X, Y), X in [-4, 2n1+4], from device
@@ -104,31 +128,44 @@ __device__ __forceinline__ void centre_value(const Phys& ph, const double* Ub, c
 // scaled toward the cell average
 __device__ __forceinline__ void lattice_value(const G2& g, const Phys& ph,
                                               const double* __restrict__ U, int X, int Y,
-                                              double* V) {
+                                              double* V, double* aux) {
   int kx, ky;
   const int Xi = axis_image(X, 2 * g.n1, g.bc0, g.bc1, kx);
   const int Yi = axis_image(Y, 2 * g.n2, g.bc2, g.bc3, ky);
   double sx = 1.0, sy = 1.0;
   mirror_signs(kx, 0, sx, sy);
   mirror_signs(ky, 1, sx, sy);
+  auto load4 = [&](int X, int Y, double* W) {
+    long o;
+    int st;
+    site_ofs(g, X, Y, o, st);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) W[k] = U[o + (long)k * st];
+  };
   if ((Xi & 1) && (Yi & 1)) {
-    const int i = Xi >> 1, j = Yi >> 1;
-    double Ub[4], e[4], c[4];
+    double Ub[4], e[4] = {0.0, 0.0, 0.0, 0.0}, c[4] = {0.0, 0.0, 0.0, 0.0}, W[4];
+    load4(Xi, Yi, Ub);
+    // same summation order as the in-LDS path: (-x) + (+x) + (-y) + (+y)
+    const int ex[4] = {-1, 1, 0, 0}, ey[4] = {0, 0, -1, 1};
+    const int cx[4] = {-1, 1, -1, 1}, cy[4] = {-1, -1, 1, 1};
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      Ub[k] = avg(g, U, i, j, k);
-      e[k] = dof(g, U, Xi - 1, Yi, k) + dof(g, U, Xi + 1, Yi, k) + dof(g, U, Xi, Yi - 1, k) +
-             dof(g, U, Xi, Yi + 1, k);
-      c[k] = dof(g, U, Xi - 1, Yi - 1, k) + dof(g, U, Xi + 1, Yi - 1, k) +
-             dof(g, U, Xi - 1, Yi + 1, k) + dof(g, U, Xi + 1, Yi + 1, k);
+    for (int n = 0; n < 4; ++n) {
+      load4(Xi + ex[n], Yi + ey[n], W);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) e[k] += W[k];
+      load4(Xi + cx[n], Yi + cy[n], W);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) c[k] += W[k];
     }
-    centre_value(ph, Ub, e, c, V);
+    centre_value(ph, Ub, e, c, V, aux);
   } else {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) V[k] = dof(g, U, Xi, Yi, k);
+    load4(Xi, Yi, V);
+    aux_of(ph, V, 1.0 / V[0], aux);
   }
   V[1] *= sx;
   V[2] *= sy;
+  aux[0] *= sx;
+  aux[1] *= sy;
 }
 
 // per-cell low-order data (Sec. 3.1-3.2):
@@ -208,6 +245,7 @@ struct Tile {
   double A[5][NA];   // u, v, p, T, c
   double G[6][NG];   // du/dx dv/dx dT/dx du/dy dv/dy dT/dy, block +- 2
   double C[23][NC];  // cell low-order data, tile +- 1
+  double CV[9][NCEN];  // centre values and their (u, v, p, T, c), staged
   double FX[4][NFX]; // limited x-face fluxes of the tile's cells
   double FY[4][NFY]; // limited y-face fluxes
 };
@@ -371,10 +409,13 @@ __device__ __forceinline__ void load_raw(const G2& g, const double* __restrict__
     double sx = 1.0, sy = 1.0;
     mirror_signs(kx, 0, sx, sy);
     mirror_signs(ky, 1, sx, sy);
-    const bool centre = (Xi & 1) && (Yi & 1);
+    long o;
+    int st;
+    site_ofs(g, Xi, Yi, o, st);
+    const double* src = Uk + o;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const double v = centre ? avg(g, Uk, Xi >> 1, Yi >> 1, k) : dof(g, Uk, Xi, Yi, k);
+      const double v = src[(long)k * st];
       pre[r][k] = k == 1 ? sx * v : (k == 2 ? sy * v : v);
     }
   }
@@ -441,8 +482,42 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
   }
   __syncthreads();
 
-  // ---- phase 2: cell low-order data (tile +- 1) from the averages held in
-  //      the centre slots; auxiliaries of the point sites ----
+  // ---- phase 2: centre values (Simpson + scaling; waves 4-7, one centre per
+  //      thread, staged until the cells have read the averages in the centre
+  //      slots), cell low-order data of the tile +- 1 (waves 0-2),
+  //      auxiliaries of the point sites (all) ----
+  const int cidx = tid - NT / 2;  // this thread's centre, if in [0, NCEN)
+  int cs = -1;                    // its LDS lattice slot
+  if (cidx >= 0 && cidx < NCEN) {
+    const int X = X0 - 3 + 2 * (cidx % (TX + 4)), Y = Y0 - 3 + 2 * (cidx / (TX + 4));
+    if (X <= Xlim + kMargin && Y <= Ylim + kMargin) {
+      cs = (Y - Y0 + 4) * WA + (X - X0 + 4);
+      double cV[4], cw[5];
+      {
+        const bool ghost_x = (X < 0 || X > Xlim) && g.bc0 != BC_PERIODIC;
+        const bool ghost_y = (Y < 0 || Y > Ylim) && g.bc2 != BC_PERIODIC;
+        if (ghost_x || ghost_y) {
+          // a centre beyond a wall or outflow side is the image of an interior one
+          lattice_value(g, ph, Uk, X, Y, cV, cw);
+        } else {
+          // periodic ghosts included: their neighbours are the wrapped values
+          double Ub[4], e[4], cc[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const double* z = T.U[k];
+            Ub[k] = z[cs];
+            e[k] = z[cs - 1] + z[cs + 1] + z[cs - WA] + z[cs + WA];
+            cc[k] = z[cs - WA - 1] + z[cs - WA + 1] + z[cs + WA - 1] + z[cs + WA + 1];
+          }
+          centre_value(ph, Ub, e, cc, cV, cw);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) T.CV[k][cidx] = cV[k];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) T.CV[4 + k][cidx] = cw[k];
+    }
+  }
   for (int s = tid; s < NC; s += NT) {
     const int i = i0 - 1 + s % WC, j = j0 - 1 + s / WC;
     if (i > g.n1 || j > g.n2) continue;
@@ -466,32 +541,11 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
     store_aux(T, ph, s);
   }
   __syncthreads();
-
-  // ---- phase 0b: centre values in place (Simpson + scaling) ----
-  for (int s = tid; s < NA; s += NT) {
-    const int X = X0 - 4 + s % WA, Y = Y0 - 4 + s / WA;
-    if (X > Xlim + kMargin || Y > Ylim + kMargin || !((X & 1) && (Y & 1))) continue;
-    double V[4];
-    const bool ghost_x = (X < 0 || X > Xlim) && g.bc0 != BC_PERIODIC;
-    const bool ghost_y = (Y < 0 || Y > Ylim) && g.bc2 != BC_PERIODIC;
-    if (ghost_x || ghost_y) {
-      // a centre beyond a wall or outflow side is the image of an interior one
-      lattice_value(g, ph, Uk, X, Y, V);
-    } else {
-      // periodic ghosts included: their neighbours are the wrapped values
-      double Ub[4], e[4], c[4];
+  if (cs >= 0) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const double* z = T.U[k];
-        Ub[k] = z[s];
-        e[k] = z[s - 1] + z[s + 1] + z[s - WA] + z[s + WA];
-        c[k] = z[s - WA - 1] + z[s - WA + 1] + z[s + WA - 1] + z[s + WA + 1];
-      }
-      centre_value(ph, Ub, e, c, V);
-    }
+    for (int k = 0; k < 4; ++k) T.U[k][cs] = T.CV[k][cidx];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) T.U[k][s] = V[k];
-    store_aux(T, ph, s);
+    for (int k = 0; k < 5; ++k) T.A[k][cs] = T.CV[4 + k][cidx];
   }
   __syncthreads();
 
