@@ -57,17 +57,17 @@ __device__ __forceinline__ int axis_image(int X, int twon, int lo, int hi, int& 
   return X;
 }
 
-// momentum sign flips of a mirror across a wall normal to axis ax (0 x, 1 y)
-__device__ __forceinline__ void mirror_signs(int kind, int ax, double& sx, double& sy) {
-  if (kind == BC_NOSLIP) {
-    sx = -sx;
-    sy = -sy;
-  } else if (kind == BC_SYMMETRY) {
-    if (ax == 0)
-      sx = -sx;
-    else
-      sy = -sy;
-  }
+// momentum signs (sx, sy) of the image of a site reached across the wall
+// kinds kx (normal x) and ky (normal y), -1 when none was crossed: a no-slip
+// wall flips both momenta, a symmetry line the normal one.  Plain integer
+// parity, so the result stays in registers.
+struct Signs {
+  double sx, sy;
+};
+__device__ __forceinline__ Signs image_signs(int kx, int ky) {
+  const int fx = (kx == BC_NOSLIP || kx == BC_SYMMETRY) ^ (ky == BC_NOSLIP);
+  const int fy = (kx == BC_NOSLIP) ^ (ky == BC_NOSLIP || ky == BC_SYMMETRY);
+  return Signs{fx ? -1.0 : 1.0, fy ? -1.0 : 1.0};
 }
 
 // ---------------------------------------------------------------------------

@@ -37,6 +37,8 @@ constexpr int WG = 2 * TX + 4, HG = 2 * TY + 4, NG = WG * HG;  // block +- 2
 constexpr int WC = TX + 2, HC = TY + 2, NC = WC * HC;          // tile cells +- 1
 constexpr int NFX = TY * (TX + 1), NFY = (TY + 1) * TX;
 constexpr int NCEN = (TX + 4) * (TY + 4);  // centre sites of the lattice region
+constexpr int NPT = 3 * TX * TY;           // point DOF sites of a tile
+constexpr int kStage = 9 * NCEN > 4 * NPT ? 9 * NCEN : 4 * NPT;
 static_assert(NCEN <= NT / 2, "one centre per thread of the upper half");
 
 struct G2 {
@@ -132,9 +134,8 @@ __device__ __forceinline__ void lattice_value(const G2& g, const Phys& ph,
   int kx, ky;
   const int Xi = axis_image(X, 2 * g.n1, g.bc0, g.bc1, kx);
   const int Yi = axis_image(Y, 2 * g.n2, g.bc2, g.bc3, ky);
-  double sx = 1.0, sy = 1.0;
-  mirror_signs(kx, 0, sx, sy);
-  mirror_signs(ky, 1, sx, sy);
+  const Signs sg = image_signs(kx, ky);
+  const double sx = sg.sx, sy = sg.sy;
   auto load4 = [&](int X, int Y, double* W) {
     long o;
     int st;
@@ -245,7 +246,9 @@ struct Tile {
   double A[5][NA];   // u, v, p, T, c
   double G[6][NG];   // du/dx dv/dx dT/dx du/dy dv/dy dT/dy, block +- 2
   double C[23][NC];  // cell low-order data, tile +- 1
-  double CV[9][NCEN];  // centre values and their (u, v, p, T, c), staged
+  // staging: centre values and their (u, v, p, T, c) in phase 2, low-order
+  // point values in phase 5
+  double STG[kStage];
   double FX[4][NFX]; // limited x-face fluxes of the tile's cells
   double FY[4][NFY]; // limited y-face fluxes
 };
@@ -406,9 +409,8 @@ __device__ __forceinline__ void load_raw(const G2& g, const double* __restrict__
     int kx, ky;
     const int Xi = axis_image(X, Xlim, g.bc0, g.bc1, kx);
     const int Yi = axis_image(Y, Ylim, g.bc2, g.bc3, ky);
-    double sx = 1.0, sy = 1.0;
-    mirror_signs(kx, 0, sx, sy);
-    mirror_signs(ky, 1, sx, sy);
+    const Signs sg = image_signs(kx, ky);
+    const double sx = sg.sx, sy = sg.sy;
     long o;
     int st;
     site_ofs(g, Xi, Yi, o, st);
@@ -513,9 +515,9 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
         }
       }
 #pragma unroll
-      for (int k = 0; k < 4; ++k) T.CV[k][cidx] = cV[k];
+      for (int k = 0; k < 4; ++k) T.STG[k * NCEN + cidx] = cV[k];
 #pragma unroll
-      for (int k = 0; k < 5; ++k) T.CV[4 + k][cidx] = cw[k];
+      for (int k = 0; k < 5; ++k) T.STG[(4 + k) * NCEN + cidx] = cw[k];
     }
   }
   for (int s = tid; s < NC; s += NT) {
@@ -543,9 +545,9 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
   __syncthreads();
   if (cs >= 0) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) T.U[k][cs] = T.CV[k][cidx];
+    for (int k = 0; k < 4; ++k) T.U[k][cs] = T.STG[k * NCEN + cidx];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) T.A[k][cs] = T.CV[4 + k][cidx];
+    for (int k = 0; k < 5; ++k) T.A[k][cs] = T.STG[(4 + k) * NCEN + cidx];
   }
   __syncthreads();
 
@@ -702,8 +704,24 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
     }
   }
 
+  // ---- phase 5a: low-order point values (Sec. 3.4), staged in LDS ----
+  if (ph.lim & LIM_POINT) {
+    for (int s = tid; s < NPT; s += NT) {
+      const int t = s / (TX * TY), r = s % (TX * TY);
+      const int i = i0 + r % TX, j = j0 + r / TX;
+      if (i >= (t == 1 ? g.n1 : g.n1x) || j >= (t == 0 ? g.n2 : g.n2y)) continue;
+      const int X = t == 1 ? 2 * i + 1 : 2 * i;
+      const int Y = t == 0 ? 2 * j + 1 : 2 * j;
+      double UL[4];
+      lo_point(T, ph, X - X0 + 4, Y - Y0 + 4, g.dx, g.dy, dt, UL);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) T.STG[k * NPT + s] = UL[k];
+    }
+    __syncthreads();
+  }
+
   // ---- phase 5: point values (0 x-edge, 1 y-edge, 2 corner points) ----
-  for (int s = tid; s < 3 * TX * TY; s += NT) {
+  for (int s = tid; s < NPT; s += NT) {
     const int t = s / (TX * TY), r = s % (TX * TY);
     const int ni = t == 1 ? g.n1 : g.n1x;
     const int nj = t == 0 ? g.n2 : g.n2y;
@@ -799,7 +817,8 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
       }
       if (ph.lim & LIM_POINT) {
         double UL[4];
-        lo_point(T, ph, X - X0 + 4, Y - Y0 + 4, g.dx, g.dy, dt, UL);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) UL[k] = T.STG[k * NPT + s];
         bool lbad = false;
         double th = theta_pair2(UL, UH, ph.gm1, lbad);
         if (ph.lim & LIM_LOWONLY) th = 0.0;
