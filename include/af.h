@@ -104,9 +104,24 @@ void af_destroy(af_ctx* ctx);
  * both sides before any compute call (checked there: AF_E_ARG). */
 af_status af_set_bc(af_ctx* ctx, int side, int kind);
 
-/* Number of doubles in one state buffer, and bytes of the workspace. */
+/* Number of doubles in one state buffer, its size in bytes, and the bytes of
+ * the workspace (0 for a NULL or inconsistent context). */
 size_t af_state_len(const af_ctx* ctx);
+size_t af_state_bytes(const af_ctx* ctx);
 size_t af_workspace_bytes(const af_ctx* ctx);
+
+/* Copy a whole state between a host buffer (af_state_len doubles, in the
+ * layout above) and a device state buffer, on `stream`; synchronous (the
+ * call returns when the copy is done).  AF_E_ARG for NULL pointers. */
+af_status af_set_state(af_ctx* ctx, double* U_dev, const double* U_host, void* stream);
+af_status af_get_state(af_ctx* ctx, const double* U_dev, double* U_host, void* stream);
+
+/* Number of DOF sites (cell averages and point values) of the device state
+ * U whose density or pressure p = (gamma-1)(E - |rho u|^2/(2 rho)) is not
+ * positive, NaN included: the admissible set of Sec. 3 (synchronous; uses
+ * the workspace).  *count receives the number. */
+af_status af_check_admissible(af_ctx* ctx, const double* U, void* ws, void* stream,
+                              long* count);
 
 /* One SSP-RK3 stage (Shu-Osher form), asynchronous on `stream`:
  *   Uout = a_k Un + b_k FE(Uk, dt),  (a,b) = (0,1), (3/4,1/4), (1/3,2/3)

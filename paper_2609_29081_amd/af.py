@@ -40,7 +40,8 @@ class Params(C.Structure):
 _lib = None
 
 EXPORTS = ["af_default_params", "af_init_grid", "af_destroy", "af_set_bc", "af_state_len",
-           "af_workspace_bytes", "af_rk_stage", "af_cfl_dt", "af_step", "af_run",
+           "af_state_bytes", "af_workspace_bytes", "af_set_state", "af_get_state",
+           "af_check_admissible", "af_rk_stage", "af_cfl_dt", "af_step", "af_run",
            "af_read_flags", "af_reset_flags", "af_timing", "af_timing_read", "af_last_error"]
 
 # kernel kinds reported by af_timing_read
@@ -67,6 +68,11 @@ def lib():
         L.af_state_len.restype = C.c_size_t
         L.af_workspace_bytes.argtypes = [vp]
         L.af_workspace_bytes.restype = C.c_size_t
+        L.af_state_bytes.argtypes = [vp]
+        L.af_state_bytes.restype = C.c_size_t
+        L.af_set_state.argtypes = [vp, vp, vp, vp]
+        L.af_get_state.argtypes = [vp, vp, vp, vp]
+        L.af_check_admissible.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_long)]
         L.af_rk_stage.argtypes = [vp, ip, vp, C.c_double, vp, vp, vp, vp, vp]
         L.af_cfl_dt.argtypes = [vp, vp, C.c_double, C.c_double, vp, vp, vp]
         L.af_step.argtypes = [vp, vp, vp, vp, C.c_double, C.c_double, C.c_double, dp,
@@ -180,6 +186,30 @@ class Solver:
 
     def af_reset_flags(self, stream=None):
         _check(lib().af_reset_flags(self.ctx, _ptr(self.ws), _stream(stream)))
+
+    def af_set_state(self, U_dev, U_host, stream=None):
+        """copy a host state (numpy float64, af_state_len values) to a device state"""
+        import numpy as np
+        h = np.ascontiguousarray(U_host, dtype=np.float64)
+        if h.size != self.state_len:
+            raise ValueError(f"host state has {h.size} values, expected {self.state_len}")
+        _check(lib().af_set_state(self.ctx, _ptr(U_dev), h.ctypes.data_as(C.c_void_p),
+                                  _stream(stream)))
+
+    def af_get_state(self, U_dev, stream=None):
+        """copy a device state to a new host array"""
+        import numpy as np
+        h = np.empty(self.state_len, dtype=np.float64)
+        _check(lib().af_get_state(self.ctx, _ptr(U_dev), h.ctypes.data_as(C.c_void_p),
+                                  _stream(stream)))
+        return h
+
+    def af_check_admissible(self, U, stream=None) -> int:
+        """number of DOF sites of U with non-positive density or pressure"""
+        n = C.c_long()
+        _check(lib().af_check_admissible(self.ctx, _ptr(U), _ptr(self.ws), _stream(stream),
+                                         C.byref(n)))
+        return n.value
 
     def af_timing(self, enable: bool):
         _check(lib().af_timing(self.ctx, 1 if enable else 0))

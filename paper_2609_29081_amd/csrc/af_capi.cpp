@@ -280,6 +280,39 @@ size_t af_state_len(const af_ctx* c) {
   return (size_t)g.state_len;
 }
 
+size_t af_state_bytes(const af_ctx* c) { return af_state_len(c) * sizeof(double); }
+
+af_status af_set_state(af_ctx* c, double* U_dev, const double* U_host, void* stream) {
+  if (!c || !U_dev || !U_host) return fail(AF_E_ARG, "af_set_state: NULL argument");
+  const hipStream_t s = (hipStream_t)stream;
+  AF_HIP(hipMemcpyAsync(U_dev, U_host, af_state_bytes(c), hipMemcpyHostToDevice, s));
+  AF_HIP(hipStreamSynchronize(s));
+  return AF_OK;
+}
+
+af_status af_get_state(af_ctx* c, const double* U_dev, double* U_host, void* stream) {
+  if (!c || !U_dev || !U_host) return fail(AF_E_ARG, "af_get_state: NULL argument");
+  const hipStream_t s = (hipStream_t)stream;
+  AF_HIP(hipMemcpyAsync(U_host, U_dev, af_state_bytes(c), hipMemcpyDeviceToHost, s));
+  AF_HIP(hipStreamSynchronize(s));
+  return AF_OK;
+}
+
+af_status af_check_admissible(af_ctx* c, const double* U, void* ws, void* stream, long* count) {
+  if (!c || !U || !ws || !count) return fail(AF_E_ARG, "af_check_admissible: NULL argument");
+  afi::Geo g;
+  if (!geometry(c, &g)) return AF_E_ARG;
+  afi::Work w;
+  afi::workspace_layout(g, &w, (char*)ws);
+  const hipStream_t s = (hipStream_t)stream;
+  AF_HIP(afi::count_inadmissible(g, c->p.gamma - 1.0, w, U, s));
+  unsigned long long n = 0;
+  AF_HIP(hipMemcpyAsync(&n, w.count, sizeof(n), hipMemcpyDeviceToHost, s));
+  AF_HIP(hipStreamSynchronize(s));
+  *count = (long)n;
+  return AF_OK;
+}
+
 size_t af_workspace_bytes(const af_ctx* c) {
   afi::Geo g;
   if (!c || !geometry(c, &g)) return 0;

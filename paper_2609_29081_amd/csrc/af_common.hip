@@ -96,6 +96,39 @@ __global__ void k_advance(double* scal) {
   }
 }
 
+// sites of one DOF array (len sites, component planes len apart, nc
+// components) whose density or pressure is not positive
+__global__ void __launch_bounds__(kBlock) k_inadmissible(int nc, const double* __restrict__ U,
+                                                         long len, double gm1,
+                                                         unsigned long long* count) {
+  __shared__ unsigned long long part[kBlock / 64];
+  unsigned long long c = 0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < len;
+       i += (long)gridDim.x * blockDim.x) {
+    const double r = U[i];
+    double kin = 0.0;
+    for (int k = 1; k < nc - 1; ++k) {
+      const double m = U[k * len + i];
+      kin += m * m;
+    }
+    const double p = gm1 * (U[(nc - 1) * len + i] - 0.5 * kin / r);
+    if (!(r > 0.0) || !(p > 0.0)) ++c;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int k = 0; k < kBlock / 64; ++k) t += part[k];
+    if (t) atomicAdd(count, t);
+  }
+}
+
+__global__ void k_zero_count(unsigned long long* count) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) count[0] = 0ull;
+}
+
 __global__ void k_clear_flags(unsigned* flags) {
   if (threadIdx.x == 0 && blockIdx.x == 0) flags[0] = 0u;
 }
@@ -138,6 +171,7 @@ size_t workspace_layout(const Geo& g, Work* w, char* base) {
   Work r{};
   r.scal = (double*)take(4 * sizeof(double));
   r.flags = (unsigned*)take(sizeof(unsigned) * 4);
+  r.count = (unsigned long long*)take(sizeof(unsigned long long));
   r.nb_cfl = kMaxCflBlocks;
   r.partial = (double*)take(2 * sizeof(double) * kMaxCflBlocks);
   if (g.dim == 1) {
@@ -196,6 +230,38 @@ hipError_t set_scalar(double* dst, double v, hipStream_t s) {
 
 hipError_t scale_scalar(double* dst, double f, hipStream_t s) {
   hipLaunchKernelGGL(k_scale, dim3(1), dim3(64), 0, s, dst, f);
+  return hipGetLastError();
+}
+
+hipError_t count_inadmissible(const Geo& g, double gm1, const Work& w, const double* U,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(64), 0, s, w.count);
+  const int nc = g.dim == 1 ? 3 : 4;
+  long off[4], len[4];
+  int na;
+  if (g.dim == 1) {
+    na = 2;
+    off[0] = 0;
+    len[0] = g.n1;
+    off[1] = g.off_pts;
+    len[1] = g.n1x;
+  } else {
+    na = 4;
+    off[0] = 0;
+    len[0] = (long)g.n1 * g.n2;
+    off[1] = g.off_xe;
+    len[1] = (long)g.n2 * g.n1x;
+    off[2] = g.off_ye;
+    len[2] = (long)g.n2y * g.n1;
+    off[3] = g.off_co;
+    len[3] = (long)g.n2y * g.n1x;
+  }
+  for (int a = 0; a < na; ++a) {
+    long nb = (len[a] + kBlock - 1) / kBlock;
+    if (nb > 2048) nb = 2048;
+    hipLaunchKernelGGL(k_inadmissible, dim3((unsigned)nb), dim3(kBlock), 0, s, nc, U + off[a],
+                       len[a], gm1, w.count);
+  }
   return hipGetLastError();
 }
 

@@ -27,6 +27,7 @@ struct Geo {
 struct Work {
   double* scal;      // [0] dt  [1] t  [2] steps taken  [3] spare
   unsigned* flags;   // sticky flag word
+  unsigned long long* count;  // result of the admissibility count
   double* partial;   // CFL partial maxima [2][nb_cfl]
   int nb_cfl;
   double* LU;        // lattice conservative values  [ncomp][ns]
@@ -82,5 +83,9 @@ hipError_t clear_flags(const Work& w, hipStream_t s);
 hipError_t copy_state(double* dst, const double* src, long n, hipStream_t s);
 hipError_t set_scalar(double* dst, double v, hipStream_t s);
 hipError_t scale_scalar(double* dst, double f, hipStream_t s);
+// number of DOF sites of state U whose density or pressure is not positive
+// (NaN included), into *w.count (asynchronous)
+hipError_t count_inadmissible(const Geo& g, double gm1, const Work& w, const double* U,
+                              hipStream_t s);
 
 }  // namespace afi

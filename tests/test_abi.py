@@ -62,6 +62,7 @@ def test_sizes_match_the_documented_layout():
         for side in range(2 if grid.dim == 1 else 4):
             assert af.lib().af_set_bc(h, side, grid.bc[side]) == af.AF_OK
         assert af.lib().af_state_len(h) == grid.state_len
+        assert af.lib().af_state_bytes(h) == 8 * grid.state_len
         assert af.lib().af_workspace_bytes(h) > 8 * grid.state_len
         af.lib().af_destroy(h)
 
