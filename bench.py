@@ -75,6 +75,8 @@ def main() -> int:
     ap.add_argument("--n2", type=int, default=500)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget of the CPU-oracle baseline sample (0 disables it)")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision form")
     ap.add_argument("--roofline-reps", type=int, default=10,
                     help="repetitions of the three stage kinds timed for the roofline")
     args = ap.parse_args()
@@ -214,6 +216,55 @@ def main() -> int:
         l1 = float(np.abs(Pg["avg"][0] - Pc["avg"][0]).sum() * g.dx * g.dy)
         linf = max(float(np.abs(Pg[n][k] - Pc[n][k]).max() / np.abs(Pc[n][k]).max())
                    for n in Pg for k in range(4))
+    # the mixed-precision form (FP32 stencils, FP64 blends and updates): the
+    # same K steps from t = 0, timed the same way, and its difference from
+    # the FP64 form over fixed-dt steps (no halving, equal times)
+    forms = {"fp64": {"value": value, "ms_per_step": gpu_ms / K,
+                      "stage_us": round(dom_avg_s * 1e6, 1)}}
+    if not args.no_mixed:
+        Sm = af.Solver(g, precision=af.PREC_MIXED, **kw)
+        Um = dev_U0.clone()
+        if Wm > 0:
+            Sm.af_run(Um, 0.0, 1e30, Wm, check_every=1)
+        Um.copy_(dev_U0)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        stm, nm, _ = Sm.af_run(Um, 0.0, 1e30, K, check_every=1)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if stm != af.AF_OK or nm != K:
+            raise RuntimeError(f"mixed run failed: status {stm}, {nm}/{K} steps")
+        ms_m = e0.elapsed_time(e1)
+        Sm.af_timing(True)
+        Sm.af_timing_read()
+        stage_sequence(Sm, dev_U0, args.roofline_reps)
+        km = Sm.af_timing_read()
+        Sm.af_timing(False)
+        dt_fix = 0.125 * float(S.af_cfl_dt(dev_U0).item())
+        A, B = dev_U0.clone(), dev_U0.clone()
+        for n_ in range(10):
+            S.af_step(A, dt_fix, n_ * dt_fix)
+            Sm.af_step(B, dt_fix, n_ * dt_fix)
+        a_, b_ = A.cpu().numpy(), B.cpu().numpy()
+        stage_s_m = km["stage2d"][1] / km["stage2d"][0] * 1e-3
+        forms["mixed"] = {"value": dof_sites * 3 * K / (ms_m / 1e3), "ms_per_step": ms_m / K,
+                          "stage_us": round(stage_s_m * 1e6, 1),
+                          "hbm_alg_GBs": round(alg["stage2d"] / stage_s_m / 1e9, 1),
+                          "l1_rel_vs_fp64": float(np.abs(b_ - a_).sum() / np.abs(a_).sum()),
+                          "l1_rel_vs_fp64_steps": f"10 steps of dt = CFL dt / 8 from t = 0"}
+        mfile = os.path.join(ROOT, "profiles", "traffic_mixed.json")
+        if os.path.exists(mfile):
+            with open(mfile) as fh:
+                trm = json.load(fh)
+            if trm.get("kernel_source_hash") == kernel_source_hash() and trm.get("n1") == g.n1 \
+                    and trm.get("n2") == g.n2:
+                f32, f64 = trm["fp32_flops_per_launch"], trm["fp64_flops_per_launch"]
+                forms["mixed"].update({
+                    "traffic": trm["bytes_per_launch"],
+                    "executed_TFLOPs": {"fp32": round(f32 / stage_s_m / 1e12, 2),
+                                        "fp64": round(f64 / stage_s_m / 1e12, 2)}})
     out = {
         "metric": METRIC, "value": value, "unit": "DOF-updates/s", "n_gpus": 1, "steps": K,
         "warmup": Wm, "ms_per_step": gpu_ms / K, "higher_is_better": True, "scaling": "weak",
@@ -228,6 +279,7 @@ def main() -> int:
         "stage_hbm": {"alg_bytes": stage_bytes, "GBs": round(stage_gbs, 1),
                       "frac": round(stage_gbs / HBM_PEAK_GBS, 4)},
         "roofline": roofline,
+        "forms": forms,
         "kernels": kernels,
         "rk3_attempts_per_step": round(attempts_per_step, 3),
         "stage_launches_per_s": kw_[stage_kind][0] / sec,

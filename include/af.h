@@ -87,12 +87,20 @@ typedef struct af_params {
   double Cs;            /* smoothness-limiter strength (paper: 1), >= 0           */
   int limiter;          /* AF_LIM_* bits                                          */
   int max_halvings;     /* retries of a step with halved dt (>= 0)               */
+  int precision;        /* AF_PREC_FP64, or AF_PREC_MIXED (2D only)               */
 } af_params;
+
+/* arithmetic of the 2D stage.  AF_PREC_MIXED: the stencils, fluxes and
+ * residuals run in FP32; the density/pressure blends (Theta rule, Sec. 3.3
+ * and 3.4), the cell-average update and the point-value update run in FP64
+ * on FP64 data.  The state stays FP64 in both; results differ from the FP64
+ * stage by the FP32 rounding of the fluxes and residuals. */
+enum { AF_PREC_FP64 = 0, AF_PREC_MIXED = 1 };
 
 typedef struct af_ctx af_ctx;
 
 /* Fill p with defaults: 2D 64x64 on [0,1]^2, gamma 1.4, mu 1e-3, Pr 0.72,
- * cfl_c 0.2, cfl_v 0.075, Cs 1, all limiters, max_halvings 40. */
+ * cfl_c 0.2, cfl_v 0.075, Cs 1, all limiters, max_halvings 40, FP64. */
 af_status af_default_params(af_params* p);
 
 /* Validate p and create a context (host memory only; no device work).

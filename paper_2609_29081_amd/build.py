@@ -8,7 +8,16 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libaf.so")
-SOURCES = ["af_capi.cpp", "af_common.hip", "af_kern1d.hip", "af_stage2d.hip"]
+# (source, object, extra flags): the 2D stage is compiled twice, as the FP64
+# stage (16 x 7 tiles) and as the mixed-precision stage (FP32 stencils, whose
+# smaller LDS footprint admits 16 x 10 tiles)
+SOURCES = [("af_capi.cpp", "af_capi.o", []),
+           ("af_common.hip", "af_common.o", []),
+           ("af_kern1d.hip", "af_kern1d.o", []),
+           ("af_stage2d.hip", "af_stage2d_fp64.o",
+            ["-DAF_STAGE_REAL=double", "-DAF_STAGE_TY=7", "-DAF_STAGE_ENTRY=stage2d_fp64"]),
+           ("af_stage2d.hip", "af_stage2d_mixed.o",
+            ["-DAF_STAGE_REAL=float", "-DAF_STAGE_TY=10", "-DAF_STAGE_ENTRY=stage2d_mixed"])]
 ARCH = "gfx950"
 
 
@@ -23,10 +32,10 @@ def build(verbose: bool = False) -> str:
     objs = []
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
-    for src in SOURCES:
-        obj = os.path.join(bdir, src + ".o")
+    for src, oname, extra in SOURCES:
+        obj = os.path.join(bdir, oname)
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        cmd = ["hipcc", *hip_flags(), *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = ["hipcc", *hip_flags(), *extra, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)

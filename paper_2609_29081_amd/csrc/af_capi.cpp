@@ -109,6 +109,7 @@ bool geometry(const af_ctx* c, afi::Geo* g) {
   for (int k = 0; k < 4; ++k) r.bc[k] = c->bc[k];
   r.dx = (p.x1 - p.x0) / p.n1;
   r.dy = p.dim == 2 ? (p.y1 - p.y0) / p.n2 : 1.0;
+  r.mixed = p.precision == AF_PREC_MIXED;
   if (p.dim == 1) {
     r.off_pts = 3L * p.n1;
     r.state_len = 3L * (p.n1 + r.n1x);
@@ -192,6 +193,7 @@ af_status af_default_params(af_params* p) {
   p->Cs = 1.0;
   p->limiter = AF_LIM_ALL;
   p->max_halvings = 40;
+  p->precision = AF_PREC_FP64;
   return AF_OK;
 }
 
@@ -212,6 +214,10 @@ af_status af_init_grid(const af_params* p, af_ctx** out) {
   if (!(p->Cs >= 0.0)) return fail(AF_E_ARG, "Cs must be >= 0");
   if (p->limiter < 0 || p->limiter > 31) return fail(AF_E_ARG, "bad limiter bits");
   if (p->max_halvings < 0) return fail(AF_E_ARG, "max_halvings must be >= 0");
+  if (p->precision != AF_PREC_FP64 && p->precision != AF_PREC_MIXED)
+    return fail(AF_E_ARG, "precision must be AF_PREC_FP64 or AF_PREC_MIXED");
+  if (p->precision == AF_PREC_MIXED && p->dim != 2)
+    return fail(AF_E_ARG, "the mixed-precision stage exists for 2D only");
   af_ctx* c = new (std::nothrow) af_ctx;
   if (!c) return fail(AF_E_ARG, "out of host memory");
   c->p = *p;

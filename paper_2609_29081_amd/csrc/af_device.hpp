@@ -20,17 +20,28 @@ enum : int { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_NOSLIP = 2, BC_SYMMETRY = 3 };
 enum : int { LIM_SMOOTH = 1, LIM_PP = 2, LIM_POINT = 4, LIM_CENTRE = 8, LIM_LOWONLY = 16 };
 enum : unsigned { FLAG_CELL_LOW = 1u, FLAG_POINT_LOW = 2u, FLAG_NONFINITE = 4u };
 
-struct Phys {
-  double gam, gm1, mu, kap, Cs;
+// gas and limiter constants in the arithmetic type R of a kernel (FP64, or
+// FP32 for the stencils of the mixed-precision stage)
+template <typename R>
+struct PhysT {
+  R gam, gm1, mu, kap, Cs;
   int lim;
 };
+using Phys = PhysT<double>;
+
+template <typename R>
+__host__ __device__ __forceinline__ PhysT<R> phys_as(const Phys& p) {
+  return PhysT<R>{R(p.gam), R(p.gm1), R(p.mu), R(p.kap), R(p.Cs), p.lim};
+}
 
 // NaN-propagating max/min: an inadmissible state anywhere in a stencil must
 // make the stage non-finite (and raise the flag), never be skipped
-__device__ __forceinline__ double mx(double a, double b) {
+template <typename R>
+__device__ __forceinline__ R mx(R a, R b) {
   return (a != a || b != b) ? a + b : (a > b ? a : b);
 }
-__device__ __forceinline__ double mn(double a, double b) {
+template <typename R>
+__device__ __forceinline__ R mn(R a, R b) {
   return (a != a || b != b) ? a + b : (a < b ? a : b);
 }
 
@@ -127,53 +138,58 @@ __device__ __forceinline__ double theta_pair1(const double* UL, const double* UH
 // identity D+(F+) + D-(F-) = D_c(F) + alpha/(6h) (1,-4,6,-4,1).U, which
 // follows from the biased stencils and the splitting F+- = (F +- alpha U)/2.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double dc5(double zm2, double zm1, double zp1, double zp2, double inv6h) {
-  return ((zm2 - zp2) + 8.0 * (zp1 - zm1)) * inv6h;
+template <typename R>
+__device__ __forceinline__ R dc5(R zm2, R zm1, R zp1, R zp2, R inv6h) {
+  return ((zm2 - zp2) + R(8.0) * (zp1 - zm1)) * inv6h;
 }
-__device__ __forceinline__ double d4(double a, double b, double c, double d, double e) {
-  return (a + e) - 4.0 * (b + d) + 6.0 * c;
+template <typename R>
+__device__ __forceinline__ R d4(R a, R b, R c, R d, R e) {
+  return (a + e) - R(4.0) * (b + d) + R(6.0) * c;
 }
 
 // compact second-derivative matrix B = [0 0; 0 M] - [M 0; 0 0] (rows: K site
 // m, columns: Z site n, both ordered -2..2) and its column sums
-__device__ __forceinline__ double bmat(int m, int n) {
+template <typename R>
+__device__ __forceinline__ R bmat(int m, int n) {
   constexpr double B[5][5] = {
       {-1.0 / 8.0, 1.0 / 6.0, -1.0 / 24.0, 0.0, 0.0},
       {1.0 / 6.0, 1.0 / 2.0, -5.0 / 6.0, 1.0 / 6.0, 0.0},
       {-1.0 / 8.0, 1.0 / 2.0, -3.0 / 4.0, 1.0 / 2.0, -1.0 / 8.0},
       {0.0, 1.0 / 6.0, -5.0 / 6.0, 1.0 / 2.0, 1.0 / 6.0},
       {0.0, 0.0, -1.0 / 24.0, 1.0 / 6.0, -1.0 / 8.0}};
-  return B[m][n];
+  return R(B[m][n]);
 }
 
 // sum_m sum_n b_mn a_m z_n  (quadratic/bilinear form of B)
-__device__ __forceinline__ double bform(const double* a, const double* z) {
-  double s = 0.0;
+template <typename R>
+__device__ __forceinline__ R bform(const R* a, const R* z) {
+  R s = R(0.0);
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
-    double t = 0.0;
+    R t = R(0.0);
 #pragma unroll
-    for (int n = 0; n < 5; ++n) t += bmat(m, n) * z[n];
+    for (int n = 0; n < 5; ++n) t += bmat<R>(m, n) * z[n];
     s += a[m] * t;
   }
   return s;
 }
 
 // sum_n (sum_m b_mn) z_n with column sums (-1/12, 4/3, -5/2, 4/3, -1/12)
-__device__ __forceinline__ double bcol(const double* z) {
-  return (-1.0 / 12.0) * (z[0] + z[4]) + (4.0 / 3.0) * (z[1] + z[3]) - 2.5 * z[2];
+template <typename R>
+__device__ __forceinline__ R bcol(const R* z) {
+  return R(-1.0 / 12.0) * (z[0] + z[4]) + R(4.0 / 3.0) * (z[1] + z[3]) - R(2.5) * z[2];
 }
 
 // viscous flux in direction d from the velocity/temperature gradients
 // (Newtonian stress, Fourier heat flux):
 //   Fv_x = (0, txx, txy, u txx + v txy + kappa Tx), Fv_y likewise.
-__device__ __forceinline__ void visc_flux2(int d, double u, double v, double ux, double vx,
-                                           double Tx, double uy, double vy, double Ty,
-                                           const Phys& ph, double* F) {
-  const double txx = ph.mu * ((4.0 / 3.0) * ux - (2.0 / 3.0) * vy);
-  const double tyy = ph.mu * ((4.0 / 3.0) * vy - (2.0 / 3.0) * ux);
-  const double txy = ph.mu * (uy + vx);
-  F[0] = 0.0;
+template <typename R>
+__device__ __forceinline__ void visc_flux2(int d, R u, R v, R ux, R vx, R Tx, R uy, R vy, R Ty,
+                                           const PhysT<R>& ph, R* F) {
+  const R txx = ph.mu * (R(4.0 / 3.0) * ux - R(2.0 / 3.0) * vy);
+  const R tyy = ph.mu * (R(4.0 / 3.0) * vy - R(2.0 / 3.0) * ux);
+  const R txy = ph.mu * (uy + vx);
+  F[0] = R(0.0);
   if (d == 0) {
     F[1] = txx;
     F[2] = txy;
@@ -189,30 +205,30 @@ __device__ __forceinline__ void visc_flux2(int d, double u, double v, double ux,
 //   b = (sqrt(q^2 + 2 e |tau_l|^2) + |q|) / (2 rho e)
 // both b_x and b_y with shared terms: e = T/(gamma-1), 1/(2 rho e) =
 // (gamma-1)/(2 p); one division for the pair
-__device__ __forceinline__ void bvisc2_xy(double p, double T, double ux, double vx, double Tx,
-                                          double uy, double vy, double Ty, const Phys& ph,
-                                          double& bx, double& by) {
-  const double txx = ph.mu * ((4.0 / 3.0) * ux - (2.0 / 3.0) * vy);
-  const double tyy = ph.mu * ((4.0 / 3.0) * vy - (2.0 / 3.0) * ux);
-  const double txy = ph.mu * (uy + vx);
-  const double qx = ph.kap * Tx, qy = ph.kap * Ty;
-  const double e2 = 2.0 * T / ph.gm1;
-  const double inv = 0.5 * ph.gm1 / p;
+template <typename R>
+__device__ __forceinline__ void bvisc2_xy(R p, R T, R ux, R vx, R Tx, R uy, R vy, R Ty,
+                                          const PhysT<R>& ph, R& bx, R& by) {
+  const R txx = ph.mu * (R(4.0 / 3.0) * ux - R(2.0 / 3.0) * vy);
+  const R tyy = ph.mu * (R(4.0 / 3.0) * vy - R(2.0 / 3.0) * ux);
+  const R txy = ph.mu * (uy + vx);
+  const R qx = ph.kap * Tx, qy = ph.kap * Ty;
+  const R e2 = R(2.0) * T / ph.gm1;
+  const R inv = R(0.5) * ph.gm1 / p;
   bx = (sqrt(qx * qx + e2 * (txx * txx + txy * txy)) + fabs(qx)) * inv;
   by = (sqrt(qy * qy + e2 * (txy * txy + tyy * tyy)) + fabs(qy)) * inv;
 }
 
 // b_d alone, in the same form
-__device__ __forceinline__ double bvisc2_dir(int d, double p, double T, double ux, double vx,
-                                             double Tx, double uy, double vy, double Ty,
-                                             const Phys& ph) {
-  const double txx = ph.mu * ((4.0 / 3.0) * ux - (2.0 / 3.0) * vy);
-  const double tyy = ph.mu * ((4.0 / 3.0) * vy - (2.0 / 3.0) * ux);
-  const double txy = ph.mu * (uy + vx);
-  const double q = ph.kap * (d == 0 ? Tx : Ty);
-  const double t2 = d == 0 ? txx * txx + txy * txy : txy * txy + tyy * tyy;
-  const double e2 = 2.0 * T / ph.gm1;
-  return (sqrt(q * q + e2 * t2) + fabs(q)) * (0.5 * ph.gm1 / p);
+template <typename R>
+__device__ __forceinline__ R bvisc2_dir(int d, R p, R T, R ux, R vx, R Tx, R uy, R vy, R Ty,
+                                        const PhysT<R>& ph) {
+  const R txx = ph.mu * (R(4.0 / 3.0) * ux - R(2.0 / 3.0) * vy);
+  const R tyy = ph.mu * (R(4.0 / 3.0) * vy - R(2.0 / 3.0) * ux);
+  const R txy = ph.mu * (uy + vx);
+  const R q = ph.kap * (d == 0 ? Tx : Ty);
+  const R t2 = d == 0 ? txx * txx + txy * txy : txy * txy + tyy * tyy;
+  const R e2 = R(2.0) * T / ph.gm1;
+  return (sqrt(q * q + e2 * t2) + fabs(q)) * (R(0.5) * ph.gm1 / p);
 }
 
 __device__ __forceinline__ double bvisc1(double rho, double p, double ux, double Tx,

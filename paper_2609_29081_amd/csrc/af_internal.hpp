@@ -21,6 +21,7 @@ struct Geo {
   long state_len;    // doubles per state
   int bc[4];
   double dx, dy;
+  int mixed;  // 2D: stencils in FP32, blends and updates in FP64
 };
 
 // device workspace carve-up (all device pointers)
@@ -68,9 +69,18 @@ struct Timer {
   } while (0)
 
 // launchers (enqueue on stream; return the first HIP error)
-hipError_t stage2d(const Geo& g, const afd::Phys& ph, const Work& w, const double* Un,
-                   const double* Uk, double* Uout, const double* dt_dev, double dt_host,
-                   StageCoef sc, hipStream_t s, Timer* tm);
+hipError_t stage2d_fp64(const Geo& g, const afd::Phys& ph, const Work& w, const double* Un,
+                        const double* Uk, double* Uout, const double* dt_dev, double dt_host,
+                        StageCoef sc, hipStream_t s, Timer* tm);
+hipError_t stage2d_mixed(const Geo& g, const afd::Phys& ph, const Work& w, const double* Un,
+                         const double* Uk, double* Uout, const double* dt_dev, double dt_host,
+                         StageCoef sc, hipStream_t s, Timer* tm);
+inline hipError_t stage2d(const Geo& g, const afd::Phys& ph, const Work& w, const double* Un,
+                          const double* Uk, double* Uout, const double* dt_dev, double dt_host,
+                          StageCoef sc, hipStream_t s, Timer* tm) {
+  return g.mixed ? stage2d_mixed(g, ph, w, Un, Uk, Uout, dt_dev, dt_host, sc, s, tm)
+                 : stage2d_fp64(g, ph, w, Un, Uk, Uout, dt_dev, dt_host, sc, s, tm);
+}
 hipError_t stage1d(const Geo& g, const afd::Phys& ph, const Work& w, const double* Un,
                    const double* Uk, double* Uout, const double* dt_dev, double dt_host,
                    StageCoef sc, hipStream_t s, Timer* tm);

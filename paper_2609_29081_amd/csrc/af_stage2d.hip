@@ -1,5 +1,5 @@
 // af_stage2d.hip -- one SSP-RK3 stage of the 2D compact AF method on gfx950
-// as a single fused, LDS-tiled kernel (FP64).
+// as a single fused, LDS-tiled kernel.
 //
 // A workgroup owns a tile of TX x TY cells, i.e. the half-lattice block
 // [X0, X0+2TX) x [Y0, Y0+2TY): the cell averages, x-edge, y-edge and corner
@@ -20,6 +20,15 @@
 //            point, compact D^2, mixed terms; Sec. 2.2), point LLF on the
 //            lattice of point values and cell averages and the scaling limiter
 //            (Sec. 3.4), wall projection, RK combination
+//
+// The kernel is a template over the arithmetic type R of the stencils, fluxes
+// and residuals (LDS included).  R = double is the FP64 stage.  R = float is
+// the mixed-precision stage: stencils and fluxes in FP32, while the density
+// and pressure blends (the Theta rule of Sec. 3.3 and 3.4), the cell-average
+// update and the point-value update stay FP64 on FP64 data read from the
+// state; the state itself is FP64 in both.
+#include <type_traits>
+
 #include "af_device.hpp"
 #include "af_internal.hpp"
 
@@ -27,9 +36,22 @@ using namespace afd;
 
 namespace {
 
-// tile shape: 16 x 7 cells, 512 threads (eight wave64s, two per SIMD); the
-// lattice region then holds <= 2 sites per thread
-constexpr int TX = 16, TY = 7, NT = 512;
+// One object file holds one instance: its arithmetic type and tile height
+// are set when it is compiled (the FP64 stage with 16 x 7 tiles, the mixed
+// stage with 16 x 10 tiles, which its FP32 LDS arrays leave room for), and
+// its entry point is afi::AF_STAGE_ENTRY.
+#ifndef AF_STAGE_REAL
+#define AF_STAGE_REAL double
+#endif
+#ifndef AF_STAGE_TY
+#define AF_STAGE_TY 7
+#endif
+#ifndef AF_STAGE_ENTRY
+#define AF_STAGE_ENTRY stage2d_fp64
+#endif
+
+// tile shape: 16 x TY cells, 512 threads (eight wave64s, two per SIMD)
+constexpr int TX = 16, TY = AF_STAGE_TY, NT = 512;
 // lattice region [X0-4, X0+2TX+4] x [Y0-4, Y0+2TY+4]: both edges are face
 // lines, so every centre inside has its eight neighbours inside
 constexpr int WA = 2 * TX + 9, HA = 2 * TY + 9, NA = WA * HA;
@@ -39,7 +61,6 @@ constexpr int NFX = TY * (TX + 1), NFY = (TY + 1) * TX;
 constexpr int NCEN = (TX + 4) * (TY + 4);  // centre sites of the lattice region
 constexpr int NPT = 3 * TX * TY;           // point DOF sites of a tile
 constexpr int kStage = 9 * NCEN > 4 * NPT ? 9 * NCEN : 4 * NPT;
-static_assert(NCEN <= NT / 2, "one centre per thread of the upper half");
 
 struct G2 {
   int n1, n2, n1x, n2y;
@@ -71,6 +92,9 @@ G2 make_g2(const afi::Geo& g) {
   return r;
 }
 
+template <typename R>
+constexpr bool kFP64 = std::is_same<R, double>::value;
+
 // offset of interior lattice site (X, Y) in a state (its first component;
 // centre sites hold the cell average, the periodic seam is folded) and the
 // distance between its component planes.  Plane indices fit 32 bits (the
@@ -85,9 +109,27 @@ __device__ __forceinline__ void site_ofs(const G2& g, int X, int Y, long& o, int
   o = base + (long)((Y >> 1) * ncol + (X >> 1));
 }
 
+// FP64 value of lattice site (X, Y), X in [-4, 2n1+4], read from the state:
+// ghosts are images of interior sites (centre sites hold the average)
+__device__ __forceinline__ void raw_value(const G2& g, const double* __restrict__ U, int X, int Y,
+                                          double* V) {
+  int kx, ky;
+  const int Xi = axis_image(X, 2 * g.n1, g.bc0, g.bc1, kx);
+  const int Yi = axis_image(Y, 2 * g.n2, g.bc2, g.bc3, ky);
+  const Signs sg = image_signs(kx, ky);
+  long o;
+  int st;
+  site_ofs(g, Xi, Yi, o, st);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) V[k] = U[o + (long)k * st];
+  V[1] *= sg.sx;
+  V[2] *= sg.sy;
+}
+
 // (u, v, p, T, c) of state V, given 1/rho
-__device__ __forceinline__ void aux_of(const Phys& ph, const double* V, double ir, double* w) {
-  const double p = ph.gm1 * (V[3] - 0.5 * (V[1] * V[1] + V[2] * V[2]) * ir);
+template <typename R>
+__device__ __forceinline__ void aux_of(const PhysT<R>& ph, const R* V, R ir, R* w) {
+  const R p = ph.gm1 * (V[3] - R(0.5) * (V[1] * V[1] + V[2] * V[2]) * ir);
   w[0] = V[1] * ir;
   w[1] = V[2] * ir;
   w[2] = p;
@@ -101,72 +143,74 @@ __device__ __forceinline__ void aux_of(const Phys& ph, const double* V, double i
 // and its (u, v, p, T, c).  A centre whose density and pressure are already
 // at least eps keeps its value: the rule's parameter is 1 there (the rule is
 // continuous at that threshold, so only round-off separates the two
-// evaluations of the test)
-__device__ __forceinline__ void centre_value(const Phys& ph, const double* Ub, const double* e,
-                                             const double* c, double* V, double* w) {
+// evaluations of the test).  The rule itself runs in FP64.
+template <typename R>
+__device__ __forceinline__ void centre_value(const PhysT<R>& ph, const Phys& phd, const R* Ub,
+                                             const R* e, const R* c, R* V, R* w) {
 #pragma unroll
-  for (int k = 0; k < 4; ++k) V[k] = (36.0 * Ub[k] - 4.0 * e[k] - c[k]) / 16.0;
-  double ir = 1.0 / V[0];
-  const double p = ph.gm1 * (V[3] - 0.5 * (V[1] * V[1] + V[2] * V[2]) * ir);
-  if ((ph.lim & LIM_CENTRE) && !(Ub[0] > 0.0 && V[0] >= kPPEps && p >= kPPEps)) {
-    if (!(Ub[0] > 0.0)) {
+  for (int k = 0; k < 4; ++k) V[k] = (R(36.0) * Ub[k] - R(4.0) * e[k] - c[k]) / R(16.0);
+  R ir = R(1.0) / V[0];
+  const R p = ph.gm1 * (V[3] - R(0.5) * (V[1] * V[1] + V[2] * V[2]) * ir);
+  if ((ph.lim & LIM_CENTRE) && !(Ub[0] > R(0.0) && V[0] >= R(kPPEps) && p >= R(kPPEps))) {
+    if (!(Ub[0] > R(0.0))) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) V[k] = Ub[k];
     } else {
+      double Ud[4], Vd[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        Ud[k] = Ub[k];
+        Vd[k] = V[k];
+      }
       bool bad = false;
-      const double th = theta_pair2(Ub, V, ph.gm1, bad);
+      const double th = theta_pair2(Ud, Vd, phd.gm1, bad);
       if (th < 1.0) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) V[k] = Ub[k] + th * (V[k] - Ub[k]);
+        for (int k = 0; k < 4; ++k) V[k] = R(Ud[k] + th * (Vd[k] - Ud[k]));
       }
     }
-    ir = 1.0 / V[0];
+    ir = R(1.0) / V[0];
   }
   aux_of(ph, V, ir, w);
 }
 
-// conservative value at lattice site (X, Y), X in [-4, 2n1+4], from device
-// memory: ghosts are images of interior sites, centres are Simpson values
-// scaled toward the cell average
-__device__ __forceinline__ void lattice_value(const G2& g, const Phys& ph,
-                                              const double* __restrict__ U, int X, int Y,
-                                              double* V, double* aux) {
+// lattice value at a centre site beyond a wall or outflow side, from device
+// memory: the Simpson value (scaled) of the image centre, with its signs
+template <typename R>
+__device__ __forceinline__ void ghost_centre(const G2& g, const PhysT<R>& ph, const Phys& phd,
+                                             const double* __restrict__ U, int X, int Y, R* V,
+                                             R* aux) {
   int kx, ky;
   const int Xi = axis_image(X, 2 * g.n1, g.bc0, g.bc1, kx);
   const int Yi = axis_image(Y, 2 * g.n2, g.bc2, g.bc3, ky);
   const Signs sg = image_signs(kx, ky);
-  const double sx = sg.sx, sy = sg.sy;
-  auto load4 = [&](int X, int Y, double* W) {
+  auto load4 = [&](int X, int Y, R* W) {
     long o;
     int st;
     site_ofs(g, X, Y, o, st);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) W[k] = U[o + (long)k * st];
+    for (int k = 0; k < 4; ++k) W[k] = R(U[o + (long)k * st]);
   };
-  if ((Xi & 1) && (Yi & 1)) {
-    double Ub[4], e[4] = {0.0, 0.0, 0.0, 0.0}, c[4] = {0.0, 0.0, 0.0, 0.0}, W[4];
-    load4(Xi, Yi, Ub);
-    // same summation order as the in-LDS path: (-x) + (+x) + (-y) + (+y)
-    const int ex[4] = {-1, 1, 0, 0}, ey[4] = {0, 0, -1, 1};
-    const int cx[4] = {-1, 1, -1, 1}, cy[4] = {-1, -1, 1, 1};
+  R Ub[4], e[4] = {R(0.0), R(0.0), R(0.0), R(0.0)}, c[4] = {R(0.0), R(0.0), R(0.0), R(0.0)},
+    W[4];
+  load4(Xi, Yi, Ub);
+  // same summation order as the in-LDS path: (-x) + (+x) + (-y) + (+y)
+  const int ex[4] = {-1, 1, 0, 0}, ey[4] = {0, 0, -1, 1};
+  const int cx[4] = {-1, 1, -1, 1}, cy[4] = {-1, -1, 1, 1};
 #pragma unroll
-    for (int n = 0; n < 4; ++n) {
-      load4(Xi + ex[n], Yi + ey[n], W);
+  for (int n = 0; n < 4; ++n) {
+    load4(Xi + ex[n], Yi + ey[n], W);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) e[k] += W[k];
-      load4(Xi + cx[n], Yi + cy[n], W);
+    for (int k = 0; k < 4; ++k) e[k] += W[k];
+    load4(Xi + cx[n], Yi + cy[n], W);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) c[k] += W[k];
-    }
-    centre_value(ph, Ub, e, c, V, aux);
-  } else {
-    load4(Xi, Yi, V);
-    aux_of(ph, V, 1.0 / V[0], aux);
+    for (int k = 0; k < 4; ++k) c[k] += W[k];
   }
-  V[1] *= sx;
-  V[2] *= sy;
-  aux[0] *= sx;
-  aux[1] *= sy;
+  centre_value(ph, phd, Ub, e, c, V, aux);
+  V[1] *= R(sg.sx);
+  V[2] *= R(sg.sy);
+  aux[0] *= R(sg.sx);
+  aux[1] *= R(sg.sy);
 }
 
 // per-cell low-order data (Sec. 3.1-3.2):
@@ -175,27 +219,28 @@ __device__ __forceinline__ void lattice_value(const G2& g, const Phys& ph,
 //   o[13] phi2, o[14..17] the cell average, o[18..22] its (u, v, p, T, c);
 //   from the averages of the cell and of its four neighbours (ghost cells as
 //   boundary images)
-__device__ __forceinline__ void cell_low(const G2& g, const Phys& ph, const double* C0,
-                                         const double* Cxm, const double* Cxp, const double* Cym,
-                                         const double* Cyp, double* o) {
+template <typename R>
+__device__ __forceinline__ void cell_low(const G2& g, const PhysT<R>& ph, const R* C0,
+                                         const R* Cxm, const R* Cxp, const R* Cym, const R* Cyp,
+                                         R* o) {
   // one reciprocal density per cell
-  const double r0 = 1.0 / C0[0], rxm = 1.0 / Cxm[0], rxp = 1.0 / Cxp[0], rym = 1.0 / Cym[0],
-               ryp = 1.0 / Cyp[0];
-  auto pr = [&](const double* V, double ir) {
-    return ph.gm1 * (V[3] - 0.5 * (V[1] * V[1] + V[2] * V[2]) * ir);
+  const R r0 = R(1.0) / C0[0], rxm = R(1.0) / Cxm[0], rxp = R(1.0) / Cxp[0],
+          rym = R(1.0) / Cym[0], ryp = R(1.0) / Cyp[0];
+  auto pr = [&](const R* V, R ir) {
+    return ph.gm1 * (V[3] - R(0.5) * (V[1] * V[1] + V[2] * V[2]) * ir);
   };
-  const double p0 = pr(C0, r0), pxm = pr(Cxm, rxm), pxp = pr(Cxp, rxp), pym = pr(Cym, rym),
-               pyp = pr(Cyp, ryp);
-  const double u0 = C0[1] * r0, v0 = C0[2] * r0;
-  const double i2x = 1.0 / (2.0 * g.dx), i2y = 1.0 / (2.0 * g.dy);
-  const double ux = (Cxp[1] * rxp - Cxm[1] * rxm) * i2x;
-  const double vx = (Cxp[2] * rxp - Cxm[2] * rxm) * i2x;
-  const double Tx = (pxp * rxp - pxm * rxm) * i2x;
-  const double uy = (Cyp[1] * ryp - Cym[1] * rym) * i2y;
-  const double vy = (Cyp[2] * ryp - Cym[2] * rym) * i2y;
-  const double Ty = (pyp * ryp - pym * rym) * i2y;
-  const double c0 = sqrt(ph.gam * p0 * r0);
-  double Fv[4];
+  const R p0 = pr(C0, r0), pxm = pr(Cxm, rxm), pxp = pr(Cxp, rxp), pym = pr(Cym, rym),
+          pyp = pr(Cyp, ryp);
+  const R u0 = C0[1] * r0, v0 = C0[2] * r0;
+  const R i2x = R(1.0 / (2.0 * g.dx)), i2y = R(1.0 / (2.0 * g.dy));
+  const R ux = (Cxp[1] * rxp - Cxm[1] * rxm) * i2x;
+  const R vx = (Cxp[2] * rxp - Cxm[2] * rxm) * i2x;
+  const R Tx = (pxp * rxp - pxm * rxm) * i2x;
+  const R uy = (Cyp[1] * ryp - Cym[1] * rym) * i2y;
+  const R vy = (Cyp[2] * ryp - Cym[2] * rym) * i2y;
+  const R Ty = (pyp * ryp - pym * rym) * i2y;
+  const R c0 = sqrt(ph.gam * p0 * r0);
+  R Fv[4];
   visc_flux2(0, u0, v0, ux, vx, Tx, uy, vy, Ty, ph, Fv);
   o[0] = C0[1] - Fv[0];
   o[1] = C0[1] * u0 + p0 - Fv[1];
@@ -214,11 +259,11 @@ __device__ __forceinline__ void cell_low(const G2& g, const Phys& ph, const doub
   o[21] = p0 * r0;
   o[22] = c0;
   bvisc2_xy(p0, p0 * r0, ux, vx, Tx, uy, vy, Ty, ph, o[10], o[11]);
-  const double jx = fabs(pxp - 2.0 * p0 + pxm) / fabs(pxp + 2.0 * p0 + pxm);
-  const double jy = fabs(pyp - 2.0 * p0 + pym) / fabs(pyp + 2.0 * p0 + pym);
+  const R jx = fabs(pxp - R(2.0) * p0 + pxm) / fabs(pxp + R(2.0) * p0 + pxm);
+  const R jy = fabs(pyp - R(2.0) * p0 + pym) / fabs(pyp + R(2.0) * p0 + pym);
   o[12] = mx(jx, jy);
-  const double div = ux + vy, curl = vx - uy;
-  o[13] = mx(-div / sqrt(div * div + curl * curl + kDucros), 0.0);
+  const R div = ux + vy, curl = vx - uy;
+  o[13] = mx(-div / sqrt(div * div + curl * curl + R(kDucros)), R(0.0));
 #pragma unroll
   for (int k = 0; k < 4; ++k) o[14 + k] = C0[k];
 }
@@ -241,24 +286,29 @@ __device__ __forceinline__ int wall_of(int bc) {
 }
 
 // LDS-resident tile data
+template <typename R>
 struct Tile {
-  double U[4][NA];   // conservative values, block +- 4
-  double A[5][NA];   // u, v, p, T, c
-  double G[6][NG];   // du/dx dv/dx dT/dx du/dy dv/dy dT/dy, block +- 2
-  double C[23][NC];  // cell low-order data, tile +- 1
+  R U[4][NA];   // conservative values, block +- 4
+  R A[5][NA];   // u, v, p, T, c
+  R G[6][NG];   // du/dx dv/dx dT/dx du/dy dv/dy dT/dy, block +- 2
+  R C[23][NC];  // cell low-order data, tile +- 1
   // staging: centre values and their (u, v, p, T, c) in phase 2, low-order
   // point values in phase 5
-  double STG[kStage];
-  double FX[4][NFX]; // limited x-face fluxes of the tile's cells
-  double FY[4][NFY]; // limited y-face fluxes
+  R STG[kStage];
+  R FX[4][NFX];  // limited x-face fluxes of the tile's cells
+  R FY[4][NFY];  // limited y-face fluxes
+  // FP64 cell averages of the tile +- 1 for the mixed-precision stage (the
+  // FP64 stage reads them from C)
+  double AV[4][kFP64<R> ? 1 : NC];
 };
 
 // auxiliaries (u, v, p, T, c) of LDS lattice site s
-__device__ __forceinline__ void store_aux(Tile& T, const Phys& ph, int s) {
-  const double r = T.U[0][s], m1 = T.U[1][s], m2 = T.U[2][s], E = T.U[3][s];
-  const double ir = 1.0 / r;
-  const double p = ph.gm1 * (E - 0.5 * (m1 * m1 + m2 * m2) * ir);
-  const double Tt = p * ir;
+template <typename R>
+__device__ __forceinline__ void store_aux(Tile<R>& T, const PhysT<R>& ph, int s) {
+  const R r = T.U[0][s], m1 = T.U[1][s], m2 = T.U[2][s], E = T.U[3][s];
+  const R ir = R(1.0) / r;
+  const R p = ph.gm1 * (E - R(0.5) * (m1 * m1 + m2 * m2) * ir);
+  const R Tt = p * ir;
   T.A[0][s] = m1 * ir;
   T.A[1][s] = m2 * ir;
   T.A[2][s] = p;
@@ -267,29 +317,31 @@ __device__ __forceinline__ void store_aux(Tile& T, const Phys& ph, int s) {
 }
 
 // total flux F_d = F^c_d - F^v_d at an LDS site (a: block+-4 index, q: block+-2 index)
-__device__ __forceinline__ void site_flux(const Tile& T, const Phys& ph, int a, int q, int d,
-                                          double* F) {
-  const double m1 = T.U[1][a], m2 = T.U[2][a], E = T.U[3][a];
-  const double u = T.A[0][a], v = T.A[1][a], p = T.A[2][a];
-  double Fv[4];
+template <typename R>
+__device__ __forceinline__ void site_flux(const Tile<R>& T, const PhysT<R>& ph, int a, int q,
+                                          int d, R* F) {
+  const R m1 = T.U[1][a], m2 = T.U[2][a], E = T.U[3][a];
+  const R u = T.A[0][a], v = T.A[1][a], p = T.A[2][a];
+  R Fv[4];
   visc_flux2(d, u, v, T.G[0][q], T.G[1][q], T.G[2][q], T.G[3][q], T.G[4][q], T.G[5][q], ph, Fv);
-  const double ud = d == 0 ? u : v;
+  const R ud = d == 0 ? u : v;
   F[0] = (d == 0 ? m1 : m2) - Fv[0];
-  F[1] = m1 * ud + (d == 0 ? p : 0.0) - Fv[1];
-  F[2] = m2 * ud + (d == 1 ? p : 0.0) - Fv[2];
+  F[1] = m1 * ud + (d == 0 ? p : R(0.0)) - Fv[1];
+  F[2] = m2 * ud + (d == 1 ? p : R(0.0)) - Fv[2];
   F[3] = (E + p) * ud - Fv[3];
 }
 
 // total flux F_d = F^c_d - F^v_d of state (m1, m2, E) with velocity (u, v),
 // pressure p and gradients gr = (u_x, v_x, T_x, u_y, v_y, T_y)
-__device__ __forceinline__ void tot_flux(int d, const double* U, double u, double v, double p,
-                                         const double* gr, const Phys& ph, double* F) {
-  double Fv[4];
+template <typename R>
+__device__ __forceinline__ void tot_flux(int d, const R* U, R u, R v, R p, const R* gr,
+                                         const PhysT<R>& ph, R* F) {
+  R Fv[4];
   visc_flux2(d, u, v, gr[0], gr[1], gr[2], gr[3], gr[4], gr[5], ph, Fv);
-  const double ud = d == 0 ? u : v;
+  const R ud = d == 0 ? u : v;
   F[0] = U[1 + d] - Fv[0];
-  F[1] = U[1] * ud + (d == 0 ? p : 0.0) - Fv[1];
-  F[2] = U[2] * ud + (d == 1 ? p : 0.0) - Fv[2];
+  F[1] = U[1] * ud + (d == 0 ? p : R(0.0)) - Fv[1];
+  F[2] = U[2] * ud + (d == 1 ? p : R(0.0)) - Fv[2];
   F[3] = (U[3] + p) * ud - Fv[3];
 }
 
@@ -301,8 +353,8 @@ __device__ __forceinline__ void tot_flux(int d, const double* U, double u, doubl
 __device__ __forceinline__ int lo_cell(int lx, int ly) {
   return ((ly - 3) >> 1) * WC + ((lx - 3) >> 1);
 }
-__device__ __forceinline__ void lo_z(const Tile& T, int lx, int ly, double& u, double& v,
-                                     double& t) {
+template <typename R>
+__device__ __forceinline__ void lo_z(const Tile<R>& T, int lx, int ly, R& u, R& v, R& t) {
   if (lx & ly & 1) {
     const int c = lo_cell(lx, ly);
     u = T.C[18][c];
@@ -316,7 +368,8 @@ __device__ __forceinline__ void lo_z(const Tile& T, int lx, int ly, double& u, d
   }
 }
 // state and (u, v, p, T, c) of a site
-__device__ __forceinline__ void lo_state(const Tile& T, int lx, int ly, double* U, double* w) {
+template <typename R>
+__device__ __forceinline__ void lo_state(const Tile<R>& T, int lx, int ly, R* U, R* w) {
   if (lx & ly & 1) {
     const int c = lo_cell(lx, ly);
 #pragma unroll
@@ -333,9 +386,9 @@ __device__ __forceinline__ void lo_state(const Tile& T, int lx, int ly, double* 
 }
 // low-order gradient at a site: central differences of Z = (u, v, T) over the
 // four neighbouring sites, half a cell away
-__device__ __forceinline__ void lo_grad(const Tile& T, int lx, int ly, double ihx, double ihy,
-                                        double* gr) {
-  double um, vm, tm, up, vp, tp;
+template <typename R>
+__device__ __forceinline__ void lo_grad(const Tile<R>& T, int lx, int ly, R ihx, R ihy, R* gr) {
+  R um, vm, tm, up, vp, tp;
   lo_z(T, lx - 1, ly, um, vm, tm);
   lo_z(T, lx + 1, ly, up, vp, tp);
   gr[0] = (up - um) * ihx;
@@ -351,41 +404,43 @@ __device__ __forceinline__ void lo_grad(const Tile& T, int lx, int ly, double ih
 // low-order point value U^L = U - sum_d (2 dt/h_d) (F^L(z, z+e_d) - F^L(z-e_d, z))
 // of the point at (lx, ly), with the LLF flux
 // F^L(a, b) = (F_a + F_b)/2 - (max(|u_d|+c) + max(b_d))/2 (U_b - U_a)
-__device__ __forceinline__ void lo_point(const Tile& T, const Phys& ph, int lx, int ly,
-                                         double dx, double dy, double dt, double* UL) {
-  const double ihx = 1.0 / dx, ihy = 1.0 / dy;
-  double U0[4], w0[5], g0[6];
+template <typename R>
+__device__ __forceinline__ void lo_point(const Tile<R>& T, const PhysT<R>& ph, int lx, int ly,
+                                         double dx, double dy, double dt, R* UL) {
+  const R ihx = R(1.0 / dx), ihy = R(1.0 / dy);
+  R U0[4], w0[5], g0[6];
   lo_state(T, lx, ly, U0, w0);
   lo_grad(T, lx, ly, ihx, ihy, g0);
-  double bx0, by0;
+  R bx0, by0;
   bvisc2_xy(w0[2], w0[3], g0[0], g0[1], g0[2], g0[3], g0[4], g0[5], ph, bx0, by0);
 #pragma unroll
   for (int k = 0; k < 4; ++k) UL[k] = U0[k];
 #pragma unroll
   for (int d = 0; d < 2; ++d) {
-    double F0[4];
+    R F0[4];
     tot_flux(d, U0, w0[0], w0[1], w0[2], g0, ph, F0);
-    const double r0 = fabs(w0[d]) + w0[4];
-    const double b0 = d == 0 ? bx0 : by0;
-    double Fp[4];
+    const R r0 = fabs(w0[d]) + w0[4];
+    const R b0 = d == 0 ? bx0 : by0;
+    R Fp[4];
     // the two neighbours one after the other (rolled: short live ranges)
 #pragma unroll 1
     for (int sg = 1; sg >= -1; sg -= 2) {
       const int nx = lx + (d == 0 ? sg : 0), ny = ly + (d == 1 ? sg : 0);
-      double Un[4], wn[5], gn[6], Fn[4];
+      R Un[4], wn[5], gn[6], Fn[4];
       lo_state(T, nx, ny, Un, wn);
       lo_grad(T, nx, ny, ihx, ihy, gn);
       tot_flux(d, Un, wn[0], wn[1], wn[2], gn, ph, Fn);
-      const double bn = bvisc2_dir(d, wn[2], wn[3], gn[0], gn[1], gn[2], gn[3], gn[4], gn[5], ph);
-      const double lam = mx(r0, fabs(wn[d]) + wn[4]) + mx(b0, bn);
+      const R bn = bvisc2_dir(d, wn[2], wn[3], gn[0], gn[1], gn[2], gn[3], gn[4], gn[5], ph);
+      const R lam = mx(r0, fabs(wn[d]) + wn[4]) + mx(b0, bn);
       if (sg == 1) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) Fp[k] = 0.5 * (F0[k] + Fn[k]) - 0.5 * lam * (Un[k] - U0[k]);
+        for (int k = 0; k < 4; ++k)
+          Fp[k] = R(0.5) * (F0[k] + Fn[k]) - R(0.5) * lam * (Un[k] - U0[k]);
       } else {
-        const double c = 2.0 * dt * (d == 0 ? ihx : ihy);
+        const R c = R(2.0 * dt) * (d == 0 ? ihx : ihy);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          const double Fm = 0.5 * (Fn[k] + F0[k]) - 0.5 * lam * (U0[k] - Un[k]);
+          const R Fm = R(0.5) * (Fn[k] + F0[k]) - R(0.5) * lam * (U0[k] - Un[k]);
           UL[k] -= c * (Fp[k] - Fm);
         }
       }
@@ -448,14 +503,16 @@ struct TileIter {
   }
 };
 
-__global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __restrict__ Uk,
+template <typename R>
+__global__ void __launch_bounds__(NT) k_stage(G2 g, Phys phd, const double* __restrict__ Uk,
                                               const double* __restrict__ Un,
                                               double* __restrict__ Uout, const double* dt_dev,
                                               double dt_host, double ca, double cb, int first,
                                               int skip_flagged, unsigned* flags, int ntx,
                                               int ntiles) {
-  __shared__ Tile T;
+  __shared__ Tile<R> T;
   __shared__ unsigned stop;  // workgroup-uniform copy of the flag word
+  const PhysT<R> ph = phys_as<R>(phd);
   const int tid = threadIdx.x;
   const double dt = dt_dev ? *dt_dev : dt_host;
   const int Xlim = 2 * g.n1, Ylim = 2 * g.n2;
@@ -480,38 +537,41 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
     const int X = X0 - 4 + s % WA, Y = Y0 - 4 + s / WA;
     if (s >= NA || X > Xlim + kMargin || Y > Ylim + kMargin) continue;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) T.U[k][s] = pre[r][k];
+    for (int k = 0; k < 4; ++k) T.U[k][s] = R(pre[r][k]);
   }
   __syncthreads();
 
-  // ---- phase 2: centre values (Simpson + scaling; waves 4-7, one centre per
-  //      thread, staged until the cells have read the averages in the centre
+  // ---- phase 2: centre values (Simpson + scaling; waves 4-7, compact
+  //      mapping, staged until the cells have read the averages in the centre
   //      slots), cell low-order data of the tile +- 1 (waves 0-2),
   //      auxiliaries of the point sites (all) ----
-  const int cidx = tid - NT / 2;  // this thread's centre, if in [0, NCEN)
-  int cs = -1;                    // its LDS lattice slot
-  if (cidx >= 0 && cidx < NCEN) {
+  // lattice slot of centre cidx of the region, or -1 beyond the grid's ghosts
+  auto centre_slot = [&](int cidx) {
     const int X = X0 - 3 + 2 * (cidx % (TX + 4)), Y = Y0 - 3 + 2 * (cidx / (TX + 4));
-    if (X <= Xlim + kMargin && Y <= Ylim + kMargin) {
-      cs = (Y - Y0 + 4) * WA + (X - X0 + 4);
-      double cV[4], cw[5];
+    return (X <= Xlim + kMargin && Y <= Ylim + kMargin) ? (Y - Y0 + 4) * WA + (X - X0 + 4) : -1;
+  };
+  for (int cidx = tid - NT / 2; cidx >= 0 && cidx < NCEN; cidx += NT / 2) {
+    const int cs = centre_slot(cidx);
+    if (cs >= 0) {
+      const int X = X0 - 3 + 2 * (cidx % (TX + 4)), Y = Y0 - 3 + 2 * (cidx / (TX + 4));
+      R cV[4], cw[5];
       {
         const bool ghost_x = (X < 0 || X > Xlim) && g.bc0 != BC_PERIODIC;
         const bool ghost_y = (Y < 0 || Y > Ylim) && g.bc2 != BC_PERIODIC;
         if (ghost_x || ghost_y) {
           // a centre beyond a wall or outflow side is the image of an interior one
-          lattice_value(g, ph, Uk, X, Y, cV, cw);
+          ghost_centre(g, ph, phd, Uk, X, Y, cV, cw);
         } else {
           // periodic ghosts included: their neighbours are the wrapped values
-          double Ub[4], e[4], cc[4];
+          R Ub[4], e[4], cc[4];
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
-            const double* z = T.U[k];
+            const R* z = T.U[k];
             Ub[k] = z[cs];
             e[k] = z[cs - 1] + z[cs + 1] + z[cs - WA] + z[cs + WA];
             cc[k] = z[cs - WA - 1] + z[cs - WA + 1] + z[cs + WA - 1] + z[cs + WA + 1];
           }
-          centre_value(ph, Ub, e, cc, cV, cw);
+          centre_value(ph, phd, Ub, e, cc, cV, cw);
         }
       }
 #pragma unroll
@@ -524,7 +584,7 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
     const int i = i0 - 1 + s % WC, j = j0 - 1 + s / WC;
     if (i > g.n1 || j > g.n2) continue;
     const int a = (2 * j + 1 - Y0 + 4) * WA + (2 * i + 1 - X0 + 4);
-    double C0[4], Cxm[4], Cxp[4], Cym[4], Cyp[4], o[23];
+    R C0[4], Cxm[4], Cxp[4], Cym[4], Cyp[4], o[23];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       C0[k] = T.U[k][a];
@@ -536,6 +596,12 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
     cell_low(g, ph, C0, Cxm, Cxp, Cym, Cyp, o);
 #pragma unroll
     for (int k = 0; k < 23; ++k) T.C[k][s] = o[k];
+    if constexpr (!kFP64<R>) {
+      double V[4];
+      raw_value(g, Uk, 2 * i + 1, 2 * j + 1, V);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) T.AV[k][s] = V[k];
+    }
   }
   for (int s = tid; s < NA; s += NT) {
     const int X = X0 - 4 + s % WA, Y = Y0 - 4 + s / WA;
@@ -543,7 +609,9 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
     store_aux(T, ph, s);
   }
   __syncthreads();
-  if (cs >= 0) {
+  for (int cidx = tid - NT / 2; cidx >= 0 && cidx < NCEN; cidx += NT / 2) {
+    const int cs = centre_slot(cidx);
+    if (cs < 0) continue;
 #pragma unroll
     for (int k = 0; k < 4; ++k) T.U[k][cs] = T.STG[k * NCEN + cidx];
 #pragma unroll
@@ -558,17 +626,17 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
 
   // ---- phase 1: gradients on the block +- 2 ----
   {
-    const double ihx = 1.0 / (6.0 * g.dx), ihy = 1.0 / (6.0 * g.dy);
+    const R ihx = R(1.0 / (6.0 * g.dx)), ihy = R(1.0 / (6.0 * g.dy));
     for (int s = tid; s < NG; s += NT) {
       const int lx = s % WG, ly = s / WG;
       const int X = X0 - 2 + lx, Y = Y0 - 2 + ly;
       if (X > Xlim + 2 || Y > Ylim + 2) continue;
       const int a = (ly + 2) * WA + (lx + 2);
-      double gr[6];
+      R gr[6];
       const int src[3] = {0, 1, 3};
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const double* z = T.A[src[c]];
+        const R* z = T.A[src[c]];
         gr[c] = dc5(z[a - 2], z[a - 1], z[a + 1], z[a + 2], ihx);
         gr[3 + c] = dc5(z[a - 2 * WA], z[a - WA], z[a + WA], z[a + 2 * WA], ihy);
       }
@@ -604,53 +672,62 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
     const int a = (Y - Y0 + 4) * WA + (X - X0 + 4);
     const int q = (Y - Y0 + 2) * WG + (X - X0 + 2);
     const int sa = d == 0 ? WA : 1, sq = d == 0 ? WG : 1;  // along the face
-    double Fa[4], Fm[4], Fb[4], FH[4], F[4];
+    R Fa[4], Fm[4], Fb[4], FH[4], F[4];
     site_flux(T, ph, a - sa, q - sq, d, Fa);
     site_flux(T, ph, a, q, d, Fm);
     site_flux(T, ph, a + sa, q + sq, d, Fb);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) FH[k] = (Fa[k] + 4.0 * Fm[k] + Fb[k]) / 6.0;
+    for (int k = 0; k < 4; ++k) FH[k] = (Fa[k] + R(4.0) * Fm[k] + Fb[k]) / R(6.0);
     if (!limc) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) F[k] = FH[k];
     } else {
       const int cbx = (j - j0 + 1) * WC + (i - i0 + 1);
       const int cax = d == 0 ? cbx - 1 : cbx - WC;
-      const double lam = mx(T.C[8 + d][cax], T.C[8 + d][cbx]) + mx(T.C[10 + d][cax], T.C[10 + d][cbx]);
-      double FL[4], Ua[4], Ub[4], Fca[4], Fcb[4];
+      const R lam = mx(T.C[8 + d][cax], T.C[8 + d][cbx]) + mx(T.C[10 + d][cax], T.C[10 + d][cbx]);
+      R FL[4], Fca[4], Fcb[4];
+      double Ua[4], Ub[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        Ua[k] = T.C[14 + k][cax];
-        Ub[k] = T.C[14 + k][cbx];
+        if constexpr (kFP64<R>) {
+          Ua[k] = T.C[14 + k][cax];
+          Ub[k] = T.C[14 + k][cbx];
+        } else {
+          Ua[k] = T.AV[k][cax];
+          Ub[k] = T.AV[k][cbx];
+        }
         Fca[k] = T.C[4 * d + k][cax];
         Fcb[k] = T.C[4 * d + k][cbx];
-        FL[k] = 0.5 * (Fca[k] + Fcb[k]) - 0.5 * lam * (Ub[k] - Ua[k]);
+        FL[k] = R(0.5) * (Fca[k] + Fcb[k]) - R(0.5) * lam * (T.C[14 + k][cbx] - T.C[14 + k][cax]);
       }
-      double ts = 1.0, tpp = 1.0;
+      R ts = R(1.0);
+      double tpp = 1.0;
       if (ph.lim & LIM_LOWONLY) {
-        ts = 0.0;
+        ts = R(0.0);
         tpp = 0.0;
       } else {
         if (ph.lim & LIM_SMOOTH)
           ts = exp(-ph.Cs * mx(T.C[12][cax], T.C[12][cbx]) * mx(T.C[13][cax], T.C[13][cbx]));
         if (ph.lim & LIM_PP) {
+          // the density and pressure blend in FP64 (Sec. 3.3)
           const double m4 = 4.0 * dt / (d == 0 ? g.dx : g.dy);
           double ULp[4], UHp[4], ULm[4], UHm[4];
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
-            const double Fs = FL[k] + ts * (FH[k] - FL[k]);
-            ULp[k] = Ua[k] - m4 * (FL[k] - Fca[k]);
-            UHp[k] = Ua[k] - m4 * (Fs - Fca[k]);
-            ULm[k] = Ub[k] - m4 * (Fcb[k] - FL[k]);
-            UHm[k] = Ub[k] - m4 * (Fcb[k] - Fs);
+            const double fl = FL[k], fh = FH[k], fca = Fca[k], fcb = Fcb[k];
+            const double Fs = fl + double(ts) * (fh - fl);
+            ULp[k] = Ua[k] - m4 * (fl - fca);
+            UHp[k] = Ua[k] - m4 * (Fs - fca);
+            ULm[k] = Ub[k] - m4 * (fcb - fl);
+            UHm[k] = Ub[k] - m4 * (fcb - Fs);
           }
           tpp = 0.0;
           bool bad = false;
           if (!(ULp[0] > 0.0) || !(ULm[0] > 0.0)) {
             bad = true;
           } else {
-            const double pLp = pressure2(ULp[0], ULp[1], ULp[2], ULp[3], ph.gm1);
-            const double pLm = pressure2(ULm[0], ULm[1], ULm[2], ULm[3], ph.gm1);
+            const double pLp = pressure2(ULp[0], ULp[1], ULp[2], ULp[3], phd.gm1);
+            const double pLm = pressure2(ULm[0], ULm[1], ULm[2], ULm[3], phd.gm1);
             if (!(pLp > 0.0) || !(pLm > 0.0)) bad = true;
             const double tr = mn(theta_lin(ULp[0], UHp[0], mn(kPPEps, ULp[0])),
                                  theta_lin(ULm[0], UHm[0], mn(kPPEps, ULm[0])));
@@ -661,16 +738,19 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
               Tm[k] = ULm[k] + tr * (UHm[k] - ULm[k]);
             }
             const double tp =
-                mn(theta_lin(pLp, pressure2(Tp[0], Tp[1], Tp[2], Tp[3], ph.gm1), mn(kPPEps, pLp)),
-                   theta_lin(pLm, pressure2(Tm[0], Tm[1], Tm[2], Tm[3], ph.gm1), mn(kPPEps, pLm)));
+                mn(theta_lin(pLp, pressure2(Tp[0], Tp[1], Tp[2], Tp[3], phd.gm1), mn(kPPEps, pLp)),
+                   theta_lin(pLm, pressure2(Tm[0], Tm[1], Tm[2], Tm[3], phd.gm1), mn(kPPEps, pLm)));
             tpp = tr * tp;
           }
           if (bad) raise_flag(flags, FLAG_CELL_LOW);
         }
       }
-      const double th = ts * tpp;
+      const double th = double(ts) * tpp;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) F[k] = FL[k] + th * (FH[k] - FL[k]);
+      for (int k = 0; k < 4; ++k) {
+        const double fl = FL[k], fh = FH[k];
+        F[k] = R(fl + th * (fh - fl));
+      }
     }
     if (d == 0) {
 #pragma unroll
@@ -682,7 +762,7 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
   }
   __syncthreads();
 
-  // ---- phase 4: cell averages ----
+  // ---- phase 4: cell averages (FP64 accumulation) ----
   {
     const double mxd = dt / g.dx, myd = dt / g.dy;
     const long nc = (long)g.n1 * g.n2;
@@ -694,9 +774,14 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
       const long gi = (long)j * g.n1 + i;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const double dfx = T.FX[k][jj * (TX + 1) + ii + 1] - T.FX[k][jj * (TX + 1) + ii];
-        const double dfy = T.FY[k][(jj + 1) * TX + ii] - T.FY[k][jj * TX + ii];
-        const double fe = T.C[14 + k][c] - mxd * dfx - myd * dfy;
+        const double dfx = double(T.FX[k][jj * (TX + 1) + ii + 1]) - double(T.FX[k][jj * (TX + 1) + ii]);
+        const double dfy = double(T.FY[k][(jj + 1) * TX + ii]) - double(T.FY[k][jj * TX + ii]);
+        double av;
+        if constexpr (kFP64<R>)
+          av = T.C[14 + k][c];
+        else
+          av = T.AV[k][c];
+        const double fe = av - mxd * dfx - myd * dfy;
         const double o = first ? fe : ca * Un[k * nc + gi] + cb * fe;
         if (!isfinite(o)) nonfinite = true;
         Uout[k * nc + gi] = o;
@@ -712,7 +797,7 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
       if (i >= (t == 1 ? g.n1 : g.n1x) || j >= (t == 0 ? g.n2 : g.n2y)) continue;
       const int X = t == 1 ? 2 * i + 1 : 2 * i;
       const int Y = t == 0 ? 2 * j + 1 : 2 * j;
-      double UL[4];
+      R UL[4];
       lo_point(T, ph, X - X0 + 4, Y - Y0 + 4, g.dx, g.dy, dt, UL);
 #pragma unroll
       for (int k = 0; k < 4; ++k) T.STG[k * NPT + s] = UL[k];
@@ -734,14 +819,14 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
       const int Y = t == 0 ? 2 * j + 1 : 2 * j;
       const int a = (Y - Y0 + 4) * WA + (X - X0 + 4);
       const int q = (Y - Y0 + 2) * WG + (X - X0 + 2);
-      double R[4] = {0.0, 0.0, 0.0, 0.0};
+      R Rs[4] = {R(0.0), R(0.0), R(0.0), R(0.0)};
 #pragma unroll
       for (int d = 0; d < 2; ++d) {
         const int sa = d == 0 ? 1 : WA, sq = d == 0 ? 1 : WG;
         const double h = d == 0 ? g.dx : g.dy;
-        const double i6h = 1.0 / (6.0 * h);
+        const R i6h = R(1.0 / (6.0 * h));
         // alpha: max of |u_d| + c over the five sites of the line
-        double alpha = 0.0;
+        R alpha = R(0.0);
 #pragma unroll
         for (int o = 0; o < 5; ++o) {
           const int b = a + (o - 2) * sa;
@@ -751,18 +836,18 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
         // one component at a time (short live ranges)
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          double f[5], w[5];
+          R f[5], w[5];
 #pragma unroll
           for (int o = 0; o < 5; ++o) {
             const int b = a + (o - 2) * sa;
-            const double ud = T.A[d][b], pb = T.A[2][b];
+            const R ud = T.A[d][b], pb = T.A[2][b];
             w[o] = T.U[k][b];
             f[o] = k == 0 ? T.U[1 + d][b]
-                          : (k == 3 ? (w[o] + pb) * ud : w[o] * ud + (k == 1 + d ? pb : 0.0));
+                          : (k == 3 ? (w[o] + pb) * ud : w[o] * ud + (k == 1 + d ? pb : R(0.0)));
           }
-          R[k] -= dc5(f[0], f[1], f[3], f[4], i6h) + alpha * i6h * d4(w[0], w[1], w[2], w[3], w[4]);
+          Rs[k] -= dc5(f[0], f[1], f[3], f[4], i6h) + alpha * i6h * d4(w[0], w[1], w[2], w[3], w[4]);
         }
-        double u[5], v[5], Tt[5];
+        R u[5], v[5], Tt[5];
 #pragma unroll
         for (int o = 0; o < 5; ++o) {
           const int b = a + (o - 2) * sa;
@@ -771,56 +856,61 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
           Tt[o] = T.A[3][b];
         }
         // compact D^{(d),2}(K_dd, Z)
-        const double s4 = 4.0 / (h * h);
-        const double mu = ph.mu, m43 = (4.0 / 3.0) * ph.mu;
-        const double cu = bcol(u), cv = bcol(v), cT = bcol(Tt);
-        const double fu = bform(u, u), fv = bform(v, v);
+        const R s4 = R(4.0 / (h * h));
+        const R mu = ph.mu, m43 = R(4.0 / 3.0) * ph.mu;
+        const R cu = bcol(u), cv = bcol(v), cT = bcol(Tt);
+        const R fu = bform(u, u), fv = bform(v, v);
         if (d == 0) {
-          R[1] += s4 * m43 * cu;
-          R[2] += s4 * mu * cv;
-          R[3] += s4 * (m43 * fu + mu * fv + ph.kap * cT);
+          Rs[1] += s4 * m43 * cu;
+          Rs[2] += s4 * mu * cv;
+          Rs[3] += s4 * (m43 * fu + mu * fv + ph.kap * cT);
         } else {
-          R[1] += s4 * mu * cu;
-          R[2] += s4 * m43 * cv;
-          R[3] += s4 * (mu * fu + m43 * fv + ph.kap * cT);
+          Rs[1] += s4 * mu * cu;
+          Rs[2] += s4 * m43 * cv;
+          Rs[3] += s4 * (mu * fu + m43 * fv + ph.kap * cT);
         }
         // mixed: D_c^{(d)} (K_{d,o} D_c^{(o)} Z), o the other direction
-        double m1[5], m2[5], m3[5];
+        R m1[5], m2[5], m3[5];
 #pragma unroll
         for (int o = 0; o < 5; ++o) {
           if (o == 2) {
-            m1[o] = m2[o] = m3[o] = 0.0;
+            m1[o] = m2[o] = m3[o] = R(0.0);
             continue;
           }
           const int qq = q + (o - 2) * sq;
           if (d == 0) {  // K_12 dZ/dy
-            const double uy = T.G[3][qq], vy = T.G[4][qq];
-            m1[o] = -(2.0 / 3.0) * mu * vy;
+            const R uy = T.G[3][qq], vy = T.G[4][qq];
+            m1[o] = -R(2.0 / 3.0) * mu * vy;
             m2[o] = mu * uy;
-            m3[o] = mu * (v[o] * uy - (2.0 / 3.0) * u[o] * vy);
+            m3[o] = mu * (v[o] * uy - R(2.0 / 3.0) * u[o] * vy);
           } else {  // K_21 dZ/dx
-            const double ux = T.G[0][qq], vx = T.G[1][qq];
+            const R ux = T.G[0][qq], vx = T.G[1][qq];
             m1[o] = mu * vx;
-            m2[o] = -(2.0 / 3.0) * mu * ux;
-            m3[o] = mu * (u[o] * vx - (2.0 / 3.0) * v[o] * ux);
+            m2[o] = -R(2.0 / 3.0) * mu * ux;
+            m3[o] = mu * (u[o] * vx - R(2.0 / 3.0) * v[o] * ux);
           }
         }
-        R[1] += dc5(m1[0], m1[1], m1[3], m1[4], i6h);
-        R[2] += dc5(m2[0], m2[1], m2[3], m2[4], i6h);
-        R[3] += dc5(m3[0], m3[1], m3[3], m3[4], i6h);
+        Rs[1] += dc5(m1[0], m1[1], m1[3], m1[4], i6h);
+        Rs[2] += dc5(m2[0], m2[1], m2[3], m2[4], i6h);
+        Rs[3] += dc5(m3[0], m3[1], m3[3], m3[4], i6h);
       }
+      const long gi = (long)j * ni + i;
+      // the point update and its blend in FP64, from the FP64 point value
       double U0[4], UH[4], out[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        U0[k] = T.U[k][a];
-        UH[k] = U0[k] + dt * R[k];
+        if constexpr (kFP64<R>)
+          U0[k] = T.U[k][a];
+        else
+          U0[k] = Uk[off + k * np + gi];
+        UH[k] = U0[k] + dt * double(Rs[k]);
       }
       if (ph.lim & LIM_POINT) {
         double UL[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) UL[k] = T.STG[k * NPT + s];
         bool lbad = false;
-        double th = theta_pair2(UL, UH, ph.gm1, lbad);
+        double th = theta_pair2(UL, UH, phd.gm1, lbad);
         if (ph.lim & LIM_LOWONLY) th = 0.0;
         if (lbad) raise_flag(flags, FLAG_POINT_LOW);
 #pragma unroll
@@ -833,7 +923,6 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
       if (X == Xlim) project(wall_of(g.bc1), 0, out);
       if (Y == 0) project(wall_of(g.bc2), 1, out);
       if (Y == Ylim) project(wall_of(g.bc3), 1, out);
-      const long gi = (long)j * ni + i;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const long idx = off + k * np + gi;
@@ -848,40 +937,51 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys ph, const double* __res
   if (nonfinite) raise_flag(flags, FLAG_NONFINITE);
 }
 
-// compute units of the current device (one persistent workgroup each: the
-// tile's LDS footprint admits one per CU)
-int device_cus() {
+// persistent workgroups of a stage kernel instance: as many as fit on the
+// device at once (the tile's LDS footprint decides), cached per device
+template <typename R>
+int resident_workgroups() {
   static int cache[64] = {0};
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
   if (cache[dev] == 0) {
-    int n = 0;
-    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
-      n = 256;
-    cache[dev] = n;
+    int cus = 0, per = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_stage<R>, NT, 0) != hipSuccess ||
+        per <= 0)
+      per = 1;
+    cache[dev] = cus * per;
   }
   return cache[dev];
+}
+
+template <typename R>
+hipError_t launch(const G2& g, const Phys& ph, const afi::Work& w, const double* Un,
+                  const double* Uk, double* Uout, const double* dt_dev, double dt_host,
+                  afi::StageCoef sc, hipStream_t s, afi::Timer* tm) {
+  // tiles cover cells [0, n1) and the point columns up to index n1
+  const int ntx = g.n1 / TX + 1, nty = g.n2 / TY + 1;
+  const int ntiles = ntx * nty;
+  int nwg = resident_workgroups<R>();
+  if (nwg > ntiles) nwg = ntiles;
+  if (nwg >= 8) nwg -= nwg % 8;
+  AFI_TIMED(tm, 7, s,
+            hipLaunchKernelGGL(k_stage<R>, dim3((unsigned)nwg), dim3(NT), 0, s, g, ph, Uk, Un,
+                               Uout, dt_dev, dt_host, sc.a, sc.b, sc.first, sc.skip_flagged,
+                               w.flags, ntx, ntiles));
+  return hipGetLastError();
 }
 
 }  // namespace
 
 namespace afi {
 
-hipError_t stage2d(const Geo& geo, const Phys& ph, const Work& w, const double* Un,
-                   const double* Uk, double* Uout, const double* dt_dev, double dt_host,
-                   StageCoef sc, hipStream_t s, Timer* tm) {
-  const G2 g = make_g2(geo);
-  // tiles cover cells [0, n1) and the point columns up to index n1
-  const int ntx = g.n1 / TX + 1, nty = g.n2 / TY + 1;
-  const int ntiles = ntx * nty;
-  int nwg = device_cus();
-  if (nwg > ntiles) nwg = ntiles;
-  if (nwg >= 8) nwg -= nwg % 8;
-  AFI_TIMED(tm, 7, s,
-            hipLaunchKernelGGL(k_stage, dim3((unsigned)nwg), dim3(NT), 0, s, g, ph, Uk, Un, Uout,
-                               dt_dev, dt_host, sc.a, sc.b, sc.first, sc.skip_flagged, w.flags,
-                               ntx, ntiles));
-  return hipGetLastError();
+hipError_t AF_STAGE_ENTRY(const Geo& geo, const Phys& ph, const Work& w, const double* Un,
+                          const double* Uk, double* Uout, const double* dt_dev, double dt_host,
+                          StageCoef sc, hipStream_t s, Timer* tm) {
+  return launch<AF_STAGE_REAL>(make_g2(geo), ph, w, Un, Uk, Uout, dt_dev, dt_host, sc, s, tm);
 }
 
 }  // namespace afi

@@ -1,8 +1,8 @@
 """HBM traffic and FP64 instruction counts of the fused 2D stage kernel
 from rocprofv3 counters.
 
-    python -m paper_2609_29081_amd.prof_counters            # driver (GPU machine)
-    python -m paper_2609_29081_amd.prof_counters --target   # profiled program
+    python -m paper_2609_29081_amd.prof_counters [--mixed]            # driver (GPU machine)
+    python -m paper_2609_29081_amd.prof_counters --target [--mixed]   # profiled program
 
 The driver runs three counter passes (FETCH_SIZE; WRITE_SIZE; the FP64 and
 LDS instruction counters) over the target, which launches the stage kernel on the 1000 x 500 shock tube (the
@@ -15,6 +15,9 @@ traffic.json and stage2d_shock_tube_1000x500_counters.md into its output
 folder (--out); copied into profiles/, traffic.json is what bench.py reports
 as the measured traffic and executed flops, as long as its hash of the
 kernel sources still matches (a stale measurement is never reported).
+With --mixed the same is done for the mixed-precision stage (FP32 stencils),
+counting FP32 and FP64 instructions, into traffic_mixed.json and
+stage2d_mixed_shock_tube_1000x500_counters.md.
 """
 from __future__ import annotations
 
@@ -45,7 +48,7 @@ def stage_sequence(S, U0, reps: int) -> None:
         S.af_rk_stage(2, U0, U2, U1, dt_dev=dt_dev)
 
 
-def target(reps: int = 3) -> None:
+def target(reps: int = 3, mixed: bool = False) -> None:
     sys.path.insert(0, ROOT)
     import torch
 
@@ -53,7 +56,8 @@ def target(reps: int = 3) -> None:
     from paper_2609_29081_amd import workloads as W
 
     g, f = W.shock_tube_2d(N1, N2)
-    S = af.Solver(g, mu=0.005, Pr=0.73, cfl_c=0.2, cfl_v=0.075)
+    S = af.Solver(g, mu=0.005, Pr=0.73, cfl_c=0.2, cfl_v=0.075,
+                  precision=af.PREC_MIXED if mixed else af.PREC_FP64)
     U0 = S.to_device(W.make_state(g, f, 1.4))
     stage_sequence(S, U0, reps)
     torch.cuda.synchronize()
@@ -68,14 +72,17 @@ def target(reps: int = 3) -> None:
 
 FP64_COUNTERS = ["SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_ADD_F64",
                  "SQ_INSTS_VALU_TRANS_F64", "SQ_INSTS_VALU", "SQ_INSTS_LDS"]
+MIXED_COUNTERS = ["SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_MUL_F32", "SQ_INSTS_VALU_ADD_F32",
+                  "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_ADD_F64",
+                  "SQ_INSTS_VALU", "SQ_INSTS_LDS"]
 
 
-def _pass(counters: list, outdir: str) -> dict:
+def _pass(counters: list, outdir: str, mixed: bool = False) -> dict:
     """one rocprofv3 run collecting `counters`; returns
     {counter: {"stage": [per launch], "copy": [per launch]}}"""
     cmd = ["timeout", "-s", "KILL", "120", "rocprofv3", "--pmc", " ".join(counters),
            "--output-format", "csv", "-d", outdir, "-o", "run", "--", sys.executable, "-m",
-           "paper_2609_29081_amd.prof_counters", "--target"]
+           "paper_2609_29081_amd.prof_counters", "--target"] + (["--mixed"] if mixed else [])
     env = dict(os.environ, TMPDIR="/tmp",
                PYTHONPATH=ROOT + os.pathsep + os.environ.get("PYTHONPATH", ""))
     subprocess.run(cmd, check=True, cwd="/tmp", env=env)
@@ -94,17 +101,20 @@ def _pass(counters: list, outdir: str) -> dict:
     return vals
 
 
-def driver(outroot: str) -> None:
+def driver(outroot: str, mixed: bool = False) -> None:
     sys.path.insert(0, ROOT)
     import bench
 
     res = {}
     for c in ("FETCH_SIZE", "WRITE_SIZE"):
-        res[c] = _pass([c], os.path.join(outroot, c.lower()))[c]
-    isa = _pass(FP64_COUNTERS, os.path.join(outroot, "fp64"))
-    per = {c: sum(isa[c]["stage"]) / len(isa[c]["stage"]) for c in FP64_COUNTERS}
+        res[c] = _pass([c], os.path.join(outroot, c.lower()), mixed)[c]
+    ilist = MIXED_COUNTERS if mixed else FP64_COUNTERS
+    isa = _pass(ilist, os.path.join(outroot, "isa"), mixed)
+    per = {c: sum(isa[c]["stage"]) / len(isa[c]["stage"]) for c in ilist}
     flops = 64.0 * (2.0 * per["SQ_INSTS_VALU_FMA_F64"] + per["SQ_INSTS_VALU_MUL_F64"]
                     + per["SQ_INSTS_VALU_ADD_F64"])
+    flops32 = (64.0 * (2.0 * per["SQ_INSTS_VALU_FMA_F32"] + per["SQ_INSTS_VALU_MUL_F32"]
+                       + per["SQ_INSTS_VALU_ADD_F32"]) if mixed else 0.0)
     fetch_kib = sum(res["FETCH_SIZE"]["stage"]) / len(res["FETCH_SIZE"]["stage"])
     write_kib = sum(res["WRITE_SIZE"]["stage"]) / len(res["WRITE_SIZE"]["stage"])
     copy_fetch = max(res["FETCH_SIZE"]["copy"])
@@ -113,7 +123,7 @@ def driver(outroot: str) -> None:
     w_scale = COPY_BYTES / copy_write      # bytes per counter unit, writes
     fetch_b = fetch_kib * f_scale
     write_b = write_kib * w_scale
-    out = {"kernel": "stage2d", "n1": N1, "n2": N2,
+    out = {"kernel": "stage2d", "precision": "mixed" if mixed else "fp64", "n1": N1, "n2": N2,
            "kernel_source_hash": bench.kernel_source_hash(),
            "fetch_counter_kib": fetch_kib, "write_counter_kib": write_kib,
            "copy_fetch_counter": copy_fetch, "copy_write_counter": copy_write,
@@ -122,17 +132,21 @@ def driver(outroot: str) -> None:
            "bytes_per_launch": fetch_b + write_b,
            "launches_averaged": len(res["FETCH_SIZE"]["stage"]),
            "instructions_per_launch": per,
-           "fp64_flops_per_launch": flops}
+           "fp64_flops_per_launch": flops,
+           "fp32_flops_per_launch": flops32}
     prof = outroot
     os.makedirs(prof, exist_ok=True)
-    with open(os.path.join(prof, "traffic.json"), "w") as fh:
+    tag = "_mixed" if mixed else ""
+    with open(os.path.join(prof, f"traffic{tag}.json"), "w") as fh:
         json.dump(out, fh, indent=1)
-    cmdline = "python -m paper_2609_29081_amd.prof_counters"
+    cmdline = "python -m paper_2609_29081_amd.prof_counters" + (" --mixed" if mixed else "")
     alg = 8.0 * 8.0 / 3.0 * (4 * (N1 * N2 + (N1 + 1) * N2 + N1 * (N2 + 1) + (N1 + 1) * (N2 + 1)))
-    md = [f"# Counters of the fused 2D stage kernel (shock tube {N1}x{N2}, FP64)", "",
+    what = "mixed-precision (FP32 stencils, FP64 blends and updates)" if mixed else "FP64"
+    md = [f"# Counters of the fused 2D stage kernel, {what} (shock tube {N1}x{N2})", "",
           f"Command: `{cmdline}` (three rocprofv3 passes, `--pmc FETCH_SIZE`,",
-          f"`--pmc WRITE_SIZE`, `--pmc {' '.join(FP64_COUNTERS)}`, each over",
-          "`python -m paper_2609_29081_amd.prof_counters --target`: three RK3 steps' worth of",
+          f"`--pmc WRITE_SIZE`, `--pmc {' '.join(ilist)}`, each over",
+          f"`python -m paper_2609_29081_amd.prof_counters --target{' --mixed' if mixed else ''}`: "
+          "three RK3 steps' worth of",
           "complete stage launches at the CFL dt of the initial state, then a 256 MiB device copy",
           "for calibration).", "",
           "| quantity | value |", "|---|---|",
@@ -148,9 +162,12 @@ def driver(outroot: str) -> None:
           f"{alg / 1e6:.1f} MB |",
           f"| kernel source hash | {out['kernel_source_hash']} |"]
     md += ["", "| instruction counter (per launch, wave instructions) | value |", "|---|---|"]
-    md += [f"| {c} | {per[c]:.4g} |" for c in FP64_COUNTERS]
+    md += [f"| {c} | {per[c]:.4g} |" for c in ilist]
     md += [f"| executed FP64 flops per launch (64 lanes x (2 FMA + MUL + ADD)) | {flops:.4g} |"]
-    with open(os.path.join(prof, "stage2d_shock_tube_1000x500_counters.md"), "w") as fh:
+    if mixed:
+        md += [f"| executed FP32 flops per launch (64 lanes x (2 FMA + MUL + ADD)) | {flops32:.4g} |"]
+    name = f"stage2d{tag}_shock_tube_1000x500_counters.md"
+    with open(os.path.join(prof, name), "w") as fh:
         fh.write("\n".join(md) + "\n")
     print(json.dumps(out))
 
@@ -158,9 +175,10 @@ def driver(outroot: str) -> None:
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--target", action="store_true")
+    ap.add_argument("--mixed", action="store_true")
     ap.add_argument("--out", default=os.path.join(ROOT, "gpurun_out", "traffic"))
     a = ap.parse_args()
     if a.target:
-        target()
+        target(mixed=a.mixed)
     else:
-        driver(a.out)
+        driver(a.out, mixed=a.mixed)
