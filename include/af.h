@@ -190,6 +190,32 @@ af_status af_timing(af_ctx* ctx, int enable);
 af_status af_timing_read(af_ctx* ctx, long* launches, double* ms);
 
 /* Message of the last error raised on the calling thread ("" if none). */
+/* ---- batches: many independent 2D instances advanced together ----
+ *
+ * A batch groups n contexts (2D, one precision; each with its own grid, gas,
+ * boundaries and switches).  Every stage of every instance of a step attempt
+ * is ONE persistent kernel launch over the tiles of all instances.  Each
+ * instance keeps its own CFL time step (eq. cfl) and its own halving (the
+ * remark on the time step at the end of Sec. 3.4), decided on the device
+ * after each attempt, so no host round trip separates the attempts.  The
+ * contexts must outlive the batch; 1 <= n <= 512. */
+typedef struct af_batch af_batch;
+af_status af_batch_create(af_ctx* const* ctxs, int n, af_batch** out);
+void af_batch_destroy(af_batch* b);
+/* Workspace of a batch run (descriptors and two stage buffers per instance). */
+size_t af_batch_workspace_bytes(const af_batch* b);
+/* Advance the device states U[i] (af_state_len doubles of ctxs[i] each) from
+ * t0 until t_final or max_steps accepted steps per instance; synchronous.
+ * Steps are enqueued in slots of one CFL step opening and attempts_per_slot
+ * (>= 1) attempts; an instance that needs more halvings continues in the
+ * next slot.  use_graph != 0 captures one slot in a HIP graph and replays
+ * it.  steps[i], t[i], status[i] (AF_OK, AF_E_PP, AF_E_NONFINITE: the state
+ * is then the one before the failed step) and attempts[i] (RK3 attempts,
+ * accepted and rejected) receive per-instance results; any may be NULL. */
+af_status af_batch_run(af_batch* b, double* const* U, void* ws, void* stream, double t0,
+                       double t_final, long max_steps, int attempts_per_slot, int use_graph,
+                       long* steps, double* t, int* status, long* attempts);
+
 const char* af_last_error(void);
 
 #ifdef __cplusplus

@@ -43,7 +43,8 @@ _lib = None
 EXPORTS = ["af_default_params", "af_init_grid", "af_destroy", "af_set_bc", "af_state_len",
            "af_state_bytes", "af_workspace_bytes", "af_set_state", "af_get_state",
            "af_check_admissible", "af_rk_stage", "af_cfl_dt", "af_step", "af_run",
-           "af_read_flags", "af_reset_flags", "af_timing", "af_timing_read", "af_last_error"]
+           "af_read_flags", "af_reset_flags", "af_timing", "af_timing_read", "af_last_error",
+           "af_batch_create", "af_batch_destroy", "af_batch_workspace_bytes", "af_batch_run"]
 
 # kernel kinds reported by af_timing_read
 KERNEL_KINDS = {0: "lattice", 1: "grad", 2: "cellpre", 3: "face", 4: "cells", 5: "points",
@@ -74,6 +75,14 @@ def lib():
         L.af_set_state.argtypes = [vp, vp, vp, vp]
         L.af_get_state.argtypes = [vp, vp, vp, vp]
         L.af_check_admissible.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_long)]
+        L.af_batch_create.argtypes = [C.POINTER(vp), ip, C.POINTER(vp)]
+        L.af_batch_destroy.argtypes = [vp]
+        L.af_batch_destroy.restype = None
+        L.af_batch_workspace_bytes.argtypes = [vp]
+        L.af_batch_workspace_bytes.restype = C.c_size_t
+        L.af_batch_run.argtypes = [vp, C.POINTER(vp), vp, vp, C.c_double, C.c_double, C.c_long, ip,
+                                   ip, C.POINTER(C.c_long), dp, C.POINTER(C.c_int),
+                                   C.POINTER(C.c_long)]
         L.af_rk_stage.argtypes = [vp, ip, vp, C.c_double, vp, vp, vp, vp, vp]
         L.af_cfl_dt.argtypes = [vp, vp, C.c_double, C.c_double, vp, vp, vp]
         L.af_step.argtypes = [vp, vp, vp, vp, C.c_double, C.c_double, C.c_double, dp,
@@ -221,3 +230,44 @@ class Solver:
         ms = (C.c_double * K_COUNT)()
         _check(lib().af_timing_read(self.ctx, n, ms))
         return {KERNEL_KINDS.get(k, f"k{k}"): (n[k], ms[k]) for k in range(K_COUNT) if n[k]}
+
+
+class Batch:
+    """A batch of 2D solvers (one precision) advanced together by af_batch_run:
+    each stage of every instance is one persistent launch, each instance with
+    its own time step and halving.  The solvers must outlive the batch."""
+
+    def __init__(self, solvers: list):
+        self.solvers = list(solvers)
+        n = len(self.solvers)
+        arr = (C.c_void_p * n)(*[s.ctx.value for s in self.solvers])
+        h = C.c_void_p()
+        _check(lib().af_batch_create(arr, n, C.byref(h)))
+        self.h = h
+        dev = self.solvers[0].device
+        nb = int(lib().af_batch_workspace_bytes(h))
+        self.ws = torch.empty(nb // 8 + 1, dtype=torch.float64, device=dev)
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) is not None and _lib is not None:
+                _lib.af_batch_destroy(self.h)
+        except Exception:
+            pass
+
+    def af_batch_run(self, states: list, t0: float, t_final: float, max_steps: int,
+                     attempts_per_slot: int = 4, use_graph: bool = False, stream=None):
+        """advance the device states in place; returns per-instance
+        (status, steps, t, attempts) lists"""
+        n = len(self.solvers)
+        if len(states) != n:
+            raise ValueError("one state per instance")
+        ptrs = (C.c_void_p * n)(*[U.data_ptr() for U in states])
+        steps = (C.c_long * n)()
+        t = (C.c_double * n)()
+        st = (C.c_int * n)()
+        att = (C.c_long * n)()
+        _check(lib().af_batch_run(self.h, ptrs, _ptr(self.ws), _stream(stream), t0, t_final,
+                                  max_steps, attempts_per_slot, 1 if use_graph else 0, steps, t,
+                                  st, att))
+        return list(st), list(steps), list(t), list(att)

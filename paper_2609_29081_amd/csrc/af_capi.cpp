@@ -9,6 +9,8 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <string.h>
+#include <memory>
 #include <new>
 #include <string>
 #include <utility>
@@ -61,6 +63,17 @@ struct af_ctx {
   af_params p;
   int bc[4];
   EventTimer* timer = nullptr;
+};
+
+struct af_batch {
+  std::vector<af_ctx*> ctx;
+  std::vector<afi::Geo> geo;
+  int mixed = 0;
+  int total_tiles = 0;
+  // workspace: descriptors, CFL partials, active count, then two stage
+  // buffers per instance
+  size_t off_partial = 0, off_nact = 0, bytes = 0;
+  std::vector<size_t> off_bufs;
 };
 
 namespace {
@@ -512,6 +525,171 @@ af_status af_run(af_ctx* c, double* U, void* ws, void* stream, double t0, double
   if (nsteps_out) *nsteps_out = done;
   if (t_out) *t_out = t;
   return status;
+}
+
+af_status af_batch_create(af_ctx* const* ctxs, int n, af_batch** out) {
+  if (!ctxs || !out || n < 1) return fail(AF_E_ARG, "af_batch_create: NULL argument or n < 1");
+  *out = nullptr;
+  if (n > 512) return fail(AF_E_ARG, "af_batch_create: at most 512 instances");
+  std::unique_ptr<af_batch> b(new (std::nothrow) af_batch);
+  if (!b) return fail(AF_E_ARG, "out of host memory");
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return o;
+  };
+  take(sizeof(afi::BatchInst) * n);
+  b->off_partial = take(sizeof(double) * 2 * afi::kBatchCflBlocks * n);
+  b->off_nact = take(sizeof(int));
+  for (int i = 0; i < n; ++i) {
+    af_ctx* c = ctxs[i];
+    if (!c) return fail(AF_E_ARG, "af_batch_create: context %d is NULL", i);
+    if (c->p.dim != 2) return fail(AF_E_ARG, "af_batch_create: context %d is not 2D", i);
+    if (i == 0) b->mixed = c->p.precision == AF_PREC_MIXED;
+    if ((c->p.precision == AF_PREC_MIXED) != (b->mixed != 0))
+      return fail(AF_E_ARG, "af_batch_create: the contexts must share one precision");
+    afi::Geo g;
+    if (!geometry(c, &g)) return AF_E_ARG;
+    b->ctx.push_back(c);
+    b->geo.push_back(g);
+    b->total_tiles += b->mixed ? afi::stage2d_mixed_tiles(g) : afi::stage2d_fp64_tiles(g);
+    b->off_bufs.push_back(take(sizeof(double) * g.state_len));
+    b->off_bufs.push_back(take(sizeof(double) * g.state_len));
+  }
+  b->bytes = off;
+  *out = b.release();
+  return AF_OK;
+}
+
+void af_batch_destroy(af_batch* b) { delete b; }
+
+size_t af_batch_workspace_bytes(const af_batch* b) { return b ? b->bytes : 0; }
+
+af_status af_batch_run(af_batch* b, double* const* U, void* ws, void* stream, double t0,
+                       double t_final, long max_steps, int attempts_per_slot, int use_graph,
+                       long* steps, double* t_out, int* status, long* attempts) {
+  if (!b || !U || !ws) return fail(AF_E_ARG, "af_batch_run: NULL argument");
+  if (attempts_per_slot < 1) return fail(AF_E_ARG, "attempts_per_slot must be >= 1");
+  if (max_steps < 0 || !(t_final >= t0)) return fail(AF_E_ARG, "af_batch_run: bad steps or times");
+  const int n = (int)b->ctx.size();
+  const hipStream_t s = (hipStream_t)stream;
+  char* base = (char*)ws;
+  afi::BatchInst* dinst = (afi::BatchInst*)base;
+  double* partial = (double*)(base + b->off_partial);
+  int* nact = (int*)(base + b->off_nact);
+  std::vector<afi::BatchInst> h(n);
+  int tile0 = 0;
+  for (int i = 0; i < n; ++i) {
+    const af_params& p = b->ctx[i]->p;
+    const afi::Geo& g = b->geo[i];
+    if (!U[i]) return fail(AF_E_ARG, "af_batch_run: state %d is NULL", i);
+    afi::BatchInst& I = h[i];
+    memset(&I, 0, sizeof(I));
+    I.g = afi::stage_geo(g);
+    I.ph = physics(p);
+    I.buf[0] = U[i];
+    I.buf[1] = (double*)(base + b->off_bufs[2 * i]);
+    I.buf[2] = (double*)(base + b->off_bufs[2 * i + 1]);
+    I.ntx = g.n1 / 16 + 1;
+    I.ntiles = b->mixed ? afi::stage2d_mixed_tiles(g) : afi::stage2d_fp64_tiles(g);
+    I.tile0 = tile0;
+    tile0 += I.ntiles;
+    I.ncell = (long)g.n1 * g.n2;
+    I.icx = 1.0 / (p.cfl_c * g.dx);
+    I.icy = 1.0 / (p.cfl_c * g.dy);
+    const double hmin = fmin(g.dx, g.dy);
+    I.vcoef = fmax(4.0 * p.mu / 3.0, p.gamma * p.mu / p.Pr) / (p.cfl_v * hmin * hmin);
+    I.t_final = t_final;
+    I.max_steps = max_steps;
+    I.max_halvings = p.max_halvings;
+    I.t = t0;
+  }
+  AF_HIP(hipMemcpyAsync(dinst, h.data(), sizeof(afi::BatchInst) * n, hipMemcpyHostToDevice, s));
+  auto slot = [&](hipStream_t q) -> hipError_t {
+    hipError_t e;
+    if ((e = afi::batch_cfl(dinst, n, partial, q)) != hipSuccess) return e;
+    if ((e = afi::batch_open(dinst, n, partial, nact, q)) != hipSuccess) return e;
+    for (int a = 0; a < attempts_per_slot; ++a) {
+      for (int k = 0; k < 3; ++k) {
+        e = b->mixed ? afi::stage2d_mixed_batch(dinst, n, b->total_tiles, nact, k, q, nullptr)
+                     : afi::stage2d_fp64_batch(dinst, n, b->total_tiles, nact, k, q, nullptr);
+        if (e != hipSuccess) return e;
+      }
+      if ((e = afi::batch_decide(dinst, n, nact, q)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  if (use_graph) {
+    // the slot is captured on a private stream (the caller's may be the null
+    // stream, which cannot be captured) and replayed on the caller's
+    hipStream_t cs = nullptr;
+    AF_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) e = slot(cs);
+    hipGraph_t gcap = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cs, &gcap);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (gcap) (void)hipGraphDestroy(gcap);
+      return hip_fail(e != hipSuccess ? e : e2, "af_batch_run: graph capture");
+    }
+    graph = gcap;
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return fail(AF_E_HIP, "af_batch_run: graph instantiation failed");
+    }
+  }
+  // enqueue step slots in chunks; after each chunk, stop once no instance is
+  // active or may open a step
+  af_status st = AF_OK;
+  long progress = -1;  // sum of steps and attempts: it grows while any instance works
+  for (;;) {
+    const long chunk = 8;
+    for (long c = 0; c < chunk; ++c) {
+      const hipError_t e = exec ? hipGraphLaunch(exec, s) : slot(s);
+      if (e != hipSuccess) {
+        st = hip_fail(e, "af_batch_run: launch");
+        break;
+      }
+    }
+    if (st != AF_OK) break;
+    if (hipMemcpyAsync(h.data(), dinst, sizeof(afi::BatchInst) * n, hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      st = fail(AF_E_HIP, "af_batch_run: read-back failed");
+      break;
+    }
+    bool busy = false;
+    long prog = 0;
+    for (int i = 0; i < n; ++i) {
+      const afi::BatchInst& I = h[i];
+      if (I.active || (I.status == 0 && I.steps < max_steps && I.t < t_final)) busy = true;
+      prog += I.steps + I.attempts;
+    }
+    if (!busy) break;
+    if (prog == progress) {
+      st = fail(AF_E_HIP, "af_batch_run: no instance made progress");
+      break;
+    }
+    progress = prog;
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (st != AF_OK) return st;
+  // the current state of every instance back into its U
+  for (int i = 0; i < n; ++i)
+    if (h[i].cur != 0) AF_HIP(afi::copy_state(U[i], h[i].buf[h[i].cur], b->geo[i].state_len, s));
+  AF_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < n; ++i) {
+    if (steps) steps[i] = h[i].steps;
+    if (t_out) t_out[i] = h[i].t;
+    if (status) status[i] = h[i].status;
+    if (attempts) attempts[i] = h[i].attempts;
+  }
+  return AF_OK;
 }
 
 const char* af_last_error(void) { return g_err.c_str(); }

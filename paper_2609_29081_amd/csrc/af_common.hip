@@ -149,6 +149,105 @@ __global__ void __launch_bounds__(kBlock) k_copy(double* __restrict__ d, const d
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// an instance may open a new step: idle, healthy, steps and time left
+__device__ __forceinline__ bool may_open(const afi::BatchInst& I) {
+  return !I.active && I.status == 0 && I.steps < I.max_steps && I.t < I.t_final;
+}
+
+// CFL partial maxima of instance blockIdx.y over its cell averages
+__global__ void __launch_bounds__(kBlock) k_batch_cfl(afi::BatchInst* inst, double* partial) {
+  const afi::BatchInst& I = inst[blockIdx.y];
+  if (!may_open(I)) return;
+  const double* U = I.buf[I.cur];
+  const long nc = I.ncell;
+  const double gm1 = I.ph.gm1, gam = I.ph.gam;
+  double a = 0.0, v = 0.0;
+  for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < nc;
+       c += (long)gridDim.x * blockDim.x) {
+    const double r = U[c];
+    const double m1 = U[nc + c], m2 = U[2 * nc + c], E = U[3 * nc + c];
+    const double p = pressure2(r, m1, m2, E, gm1);
+    const double cs = sqrt(gam * p / r);
+    a = mx(a, (fabs(m1 / r) + cs) * I.icx);
+    a = mx(a, (fabs(m2 / r) + cs) * I.icy);
+    v = mx(v, I.vcoef / r);
+  }
+  block_max2(a, v);
+  if (threadIdx.x == 0) {
+    double* q = partial + 2L * afi::kBatchCflBlocks * blockIdx.y;
+    q[blockIdx.x] = a;
+    q[afi::kBatchCflBlocks + blockIdx.x] = v;
+  }
+}
+
+// number of active instances, into *n_active (one block)
+__device__ void count_active(afi::BatchInst* inst, int n, int* n_active) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  int c = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) c += inst[i].active;
+  if (c) atomicAdd(&cnt, c);
+  __syncthreads();
+  if (threadIdx.x == 0) n_active[0] = cnt;
+}
+
+// open a step for every instance that may: dt = 1/(a + v) (eq. cfl),
+// clipped to t_final - t
+__global__ void __launch_bounds__(kBlock) k_batch_open(afi::BatchInst* inst, int n,
+                                                       const double* partial, int* n_active) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    afi::BatchInst& I = inst[i];
+    if (!may_open(I)) continue;
+    const double* q = partial + 2L * afi::kBatchCflBlocks * i;
+    double a = 0.0, v = 0.0;
+    for (int k = 0; k < afi::kBatchCflBlocks; ++k) {
+      a = mx(a, q[k]);
+      v = mx(v, q[afi::kBatchCflBlocks + k]);
+    }
+    double dt = 1.0 / (a + v);
+    if (I.t + dt > I.t_final) dt = I.t_final - I.t;
+    if (!(dt > 0.0)) {
+      I.status = 4;  // AF_E_NONFINITE: no finite time step from this state
+      continue;
+    }
+    I.dt = dt;
+    I.halvings = 0;
+    I.flags = 0u;
+    I.active = 1;
+  }
+  __syncthreads();
+  count_active(inst, n, n_active);
+}
+
+// after an attempt: accept it (the output becomes the current state) or
+// redo it with dt/2, up to max_halvings times (then the instance stops with
+// its status set and its state left at the start of the step)
+__global__ void __launch_bounds__(kBlock) k_batch_decide(afi::BatchInst* inst, int n,
+                                                         int* n_active) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    afi::BatchInst& I = inst[i];
+    if (!I.active) continue;
+    I.attempts += 1;
+    const unsigned f = I.flags;
+    if (f == 0u) {
+      I.t += I.dt;
+      I.steps += 1;
+      I.cur = (I.cur + 1) % 3;
+      I.active = 0;
+    } else if (I.halvings < I.max_halvings) {
+      I.dt *= 0.5;
+      I.halvings += 1;
+      I.flags = 0u;
+    } else {
+      I.status = (f & FLAG_NONFINITE) ? 4 : 3;  // AF_E_NONFINITE : AF_E_PP
+      I.active = 0;
+    }
+  }
+  __syncthreads();
+  count_active(inst, n, n_active);
+}
+
 }  // namespace
 
 namespace afi {
@@ -262,6 +361,23 @@ hipError_t count_inadmissible(const Geo& g, double gm1, const Work& w, const dou
     hipLaunchKernelGGL(k_inadmissible, dim3((unsigned)nb), dim3(kBlock), 0, s, nc, U + off[a],
                        len[a], gm1, w.count);
   }
+  return hipGetLastError();
+}
+
+hipError_t batch_cfl(BatchInst* inst, int n, double* partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_cfl, dim3(kBatchCflBlocks, (unsigned)n), dim3(kBlock), 0, s, inst,
+                     partial);
+  return hipGetLastError();
+}
+
+hipError_t batch_open(BatchInst* inst, int n, const double* partial, int* n_active,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_open, dim3(1), dim3(kBlock), 0, s, inst, n, partial, n_active);
+  return hipGetLastError();
+}
+
+hipError_t batch_decide(BatchInst* inst, int n, int* n_active, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_decide, dim3(1), dim3(kBlock), 0, s, inst, n, n_active);
   return hipGetLastError();
 }
 

@@ -24,6 +24,61 @@ struct Geo {
   int mixed;  // 2D: stencils in FP32, blends and updates in FP64
 };
 
+// geometry of a 2D grid as the stage kernels read it
+struct StageGeo {
+  int n1, n2, n1x, n2y;
+  long off_xe, off_ye, off_co;
+  int st_avg, st_xe, st_ye, st_co;  // distance between component planes
+  int bc0, bc1, bc2, bc3;
+  double dx, dy;
+};
+
+inline StageGeo stage_geo(const Geo& g) {
+  StageGeo r;
+  r.n1 = g.n1;
+  r.n2 = g.n2;
+  r.n1x = g.n1x;
+  r.n2y = g.n2y;
+  r.off_xe = g.off_xe;
+  r.off_ye = g.off_ye;
+  r.off_co = g.off_co;
+  r.st_avg = g.n1 * g.n2;
+  r.st_xe = g.n2 * g.n1x;
+  r.st_ye = g.n2y * g.n1;
+  r.st_co = g.n2y * g.n1x;
+  r.bc0 = g.bc[0];
+  r.bc1 = g.bc[1];
+  r.bc2 = g.bc[2];
+  r.bc3 = g.bc[3];
+  r.dx = g.dx;
+  r.dy = g.dy;
+  return r;
+}
+
+// One 2D instance of a batch, in device memory.  The host fills the static
+// part; the batch kernels update the rest.  A step of an instance is a
+// sequence of attempts: the CFL kernel opens it (active = 1, fresh dt), each
+// attempt runs the three stages from buf[cur], and the decide kernel either
+// accepts it (cur advances, t += dt) or halves dt for the next attempt.
+struct BatchInst {
+  StageGeo g;
+  afd::Phys ph;
+  double* buf[3];        // rotating states; buf[cur] is the current one
+  int ntx, ntiles, tile0;  // stage tiles of the instance, its first global tile
+  long ncell;            // CFL: cells, 1/(C^c dx), 1/(C^c dy), viscous rate factor
+  double icx, icy, vcoef;
+  double t_final;
+  long max_steps;
+  int max_halvings;
+  // updated on the device
+  double dt, t;
+  long steps;
+  int cur, active, halvings, status;
+  unsigned flags;
+  long attempts;  // RK3 attempts so far (accepted and rejected)
+};
+
+
 // device workspace carve-up (all device pointers)
 struct Work {
   double* scal;      // [0] dt  [1] t  [2] steps taken  [3] spare
@@ -97,5 +152,23 @@ hipError_t scale_scalar(double* dst, double f, hipStream_t s);
 // (NaN included), into *w.count (asynchronous)
 hipError_t count_inadmissible(const Geo& g, double gm1, const Work& w, const double* U,
                               hipStream_t s);
+
+// batch kernels (af_common.hip): CFL partial maxima of every instance that
+// may open a step (B blocks each); opening of steps (fresh CFL dt, active);
+// the decision after an attempt.  Both of the latter recount the active
+// instances into *n_active.
+constexpr int kBatchCflBlocks = 32;
+hipError_t batch_cfl(BatchInst* inst, int n, double* partial, hipStream_t s);
+hipError_t batch_open(BatchInst* inst, int n, const double* partial, int* n_active,
+                      hipStream_t s);
+hipError_t batch_decide(BatchInst* inst, int n, int* n_active, hipStream_t s);
+// the 2D stage over a batch (af_stage2d.hip, one per precision), and the
+// number of stage tiles of a grid for that instance's tile shape
+hipError_t stage2d_fp64_batch(BatchInst* inst, int ninst, int total_tiles, const int* n_active,
+                              int k, hipStream_t s, Timer* tm);
+hipError_t stage2d_mixed_batch(BatchInst* inst, int ninst, int total_tiles, const int* n_active,
+                               int k, hipStream_t s, Timer* tm);
+int stage2d_fp64_tiles(const Geo& g);
+int stage2d_mixed_tiles(const Geo& g);
 
 }  // namespace afi

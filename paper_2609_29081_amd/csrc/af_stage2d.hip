@@ -49,6 +49,10 @@ namespace {
 #ifndef AF_STAGE_ENTRY
 #define AF_STAGE_ENTRY stage2d_fp64
 #endif
+#define AF_CAT2(a, b) a##b
+#define AF_CAT(a, b) AF_CAT2(a, b)
+#define AF_STAGE_TILES AF_CAT(AF_STAGE_ENTRY, _tiles)
+#define AF_STAGE_BATCH AF_CAT(AF_STAGE_ENTRY, _batch)
 
 // tile shape: 16 x TY cells, 512 threads (eight wave64s, two per SIMD)
 constexpr int TX = 16, TY = AF_STAGE_TY, NT = 512;
@@ -62,35 +66,7 @@ constexpr int NCEN = (TX + 4) * (TY + 4);  // centre sites of the lattice region
 constexpr int NPT = 3 * TX * TY;           // point DOF sites of a tile
 constexpr int kStage = 9 * NCEN > 4 * NPT ? 9 * NCEN : 4 * NPT;
 
-struct G2 {
-  int n1, n2, n1x, n2y;
-  long off_xe, off_ye, off_co;
-  int st_avg, st_xe, st_ye, st_co;  // distance between component planes
-  int bc0, bc1, bc2, bc3;
-  double dx, dy;
-};
-
-G2 make_g2(const afi::Geo& g) {
-  G2 r;
-  r.n1 = g.n1;
-  r.n2 = g.n2;
-  r.n1x = g.n1x;
-  r.n2y = g.n2y;
-  r.off_xe = g.off_xe;
-  r.off_ye = g.off_ye;
-  r.off_co = g.off_co;
-  r.st_avg = g.n1 * g.n2;
-  r.st_xe = g.n2 * g.n1x;
-  r.st_ye = g.n2y * g.n1;
-  r.st_co = g.n2y * g.n1x;
-  r.bc0 = g.bc[0];
-  r.bc1 = g.bc[1];
-  r.bc2 = g.bc[2];
-  r.bc3 = g.bc[3];
-  r.dx = g.dx;
-  r.dy = g.dy;
-  return r;
-}
+using G2 = afi::StageGeo;
 
 template <typename R>
 constexpr bool kFP64 = std::is_same<R, double>::value;
@@ -503,32 +479,154 @@ struct TileIter {
   }
 };
 
-template <typename R>
-__global__ void __launch_bounds__(NT) k_stage(G2 g, Phys phd, const double* __restrict__ Uk,
-                                              const double* __restrict__ Un,
-                                              double* __restrict__ Uout, const double* dt_dev,
-                                              double dt_host, double ca, double cb, int first,
-                                              int skip_flagged, unsigned* flags, int ntx,
-                                              int ntiles) {
+// launch arguments of a stage: one instance, or a batch of 2D instances
+constexpr int kMaxBatch = 512;
+struct StageArgs {
+  // one instance
+  G2 g;
+  Phys ph;
+  const double* Uk;
+  const double* Un;
+  double* Uout;
+  const double* dt_dev;
+  double dt_host;
+  unsigned* flags;
+  int ntx;
+  // a batch: its instances (stage k reads and writes their rotating buffers)
+  afi::BatchInst* inst;
+  int ninst, k;
+  const int* n_active;
+  // both
+  double ca, cb;
+  int first, skip_flagged, ntiles;
+};
+
+// what one tile of a stage works on
+struct TileArgs {
+  G2 g;
+  Phys phd;
+  const double* Uk;
+  const double* Un;
+  double* Uout;
+  double dt;
+  unsigned* flags;
+  int ntx, lt;  // tiles along x of its grid, the tile's index in its grid
+};
+
+// tile t of a batch: t0[i] is the first global tile of instance i
+__device__ __forceinline__ int batch_instance(const int* t0, int n, int t) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (t0[mid] <= t)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ TileArgs batch_tile(const StageArgs& sa, const int* t0, int t) {
+  const int in = batch_instance(t0, sa.ninst, t);
+  const afi::BatchInst& I = sa.inst[in];
+  TileArgs A;
+  A.g = I.g;
+  A.phd = I.ph;
+  A.ntx = I.ntx;
+  A.lt = t - t0[in];
+  A.dt = I.dt;
+  A.flags = &sa.inst[in].flags;
+  // the three RK3 stages from buf[cur], through the other two buffers
+  const int c = I.cur, a = (c + 1) % 3, b = (c + 2) % 3;
+  A.Un = I.buf[c];
+  A.Uk = sa.k == 0 ? I.buf[c] : (sa.k == 1 ? I.buf[a] : I.buf[b]);
+  A.Uout = sa.k == 1 ? I.buf[b] : I.buf[a];
+  return A;
+}
+
+template <typename R, bool BATCH>
+__global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
   __shared__ Tile<R> T;
   __shared__ unsigned stop;  // workgroup-uniform copy of the flag word
-  const PhysT<R> ph = phys_as<R>(phd);
   const int tid = threadIdx.x;
-  const double dt = dt_dev ? *dt_dev : dt_host;
-  const int Xlim = 2 * g.n1, Ylim = 2 * g.n2;
+  const double ca = sa.ca, cb = sa.cb;
+  const int first = sa.first, skip_flagged = sa.skip_flagged;
   bool nonfinite = false;
-  TileIter it(ntiles, blockIdx.x, gridDim.x);
-  int tile = it.get();
+  // a batch: first global tile of each instance and whether it is active
+  __shared__ int bt0[BATCH ? kMaxBatch : 1], bact[BATCH ? kMaxBatch : 1];
+  if constexpr (BATCH) {
+    if (*sa.n_active == 0) return;  // every instance has finished its step
+    for (int i = tid; i < sa.ninst; i += NT) {
+      bt0[i] = sa.inst[i].tile0;
+      bact[i] = sa.inst[i].active;
+    }
+    __syncthreads();
+  }
+  TileArgs A0;  // the one instance
+  if constexpr (!BATCH) {
+    A0.g = sa.g;
+    A0.phd = sa.ph;
+    A0.Uk = sa.Uk;
+    A0.Un = sa.Un;
+    A0.Uout = sa.Uout;
+    A0.dt = sa.dt_dev ? *sa.dt_dev : sa.dt_host;
+    A0.flags = sa.flags;
+    A0.ntx = sa.ntx;
+  }
+  auto args = [&](int t) {
+    if constexpr (BATCH) {
+      return batch_tile(sa, bt0, t);
+    } else {
+      TileArgs A = A0;
+      A.lt = t;
+      return A;
+    }
+  };
+  // the next tile of this workgroup that belongs to an active instance
+  TileIter it(sa.ntiles, blockIdx.x, gridDim.x);
+  auto next_tile = [&](int t) {
+    if constexpr (BATCH) {
+      while (t >= 0 && !bact[batch_instance(bt0, sa.ninst, t)]) t = it.advance();
+    }
+    return t;
+  };
+  int tile = next_tile(it.get());
   double pre[kRawPerThread][4];
-  if (tile >= 0) load_raw(g, Uk, 2 * TX * (tile % ntx), 2 * TY * (tile / ntx), tid, pre);
+  if (tile >= 0) {
+    const TileArgs A = args(tile);
+    load_raw(A.g, A.Uk, 2 * TX * (A.lt % A.ntx), 2 * TY * (A.lt / A.ntx), tid, pre);
+  }
   while (tile >= 0) {
-  const int i0 = (tile % ntx) * TX, j0 = (tile / ntx) * TY;
+  const TileArgs A = args(tile);
+  const G2& g = A.g;
+  const Phys& phd = A.phd;
+  const PhysT<R> ph = phys_as<R>(phd);
+  const double* __restrict__ Uk = A.Uk;
+  const double* __restrict__ Un = A.Un;
+  double* __restrict__ Uout = A.Uout;
+  const double dt = A.dt;
+  unsigned* flags = A.flags;
+  const int Xlim = 2 * g.n1, Ylim = 2 * g.n2;
+  const int i0 = (A.lt % A.ntx) * TX, j0 = (A.lt / A.ntx) * TY;
   const int X0 = 2 * i0, Y0 = 2 * j0;
   // inside a step attempt, stop once any workgroup has flagged the attempt:
-  // it is rejected and this output is never read
+  // it is rejected and this output is never read (a batch skips the tiles of
+  // that instance only)
   if (tid == 0) stop = skip_flagged ? peek_flags(flags) : 0u;
   __syncthreads();  // the previous tile is done with the LDS; stop is visible
-  if (stop) break;
+  if (stop) {
+    if constexpr (BATCH) {
+      const int nt = next_tile(it.advance());
+      if (nt >= 0) {
+        const TileArgs An = args(nt);
+        load_raw(An.g, An.Uk, 2 * TX * (An.lt % An.ntx), 2 * TY * (An.lt / An.ntx), tid, pre);
+      }
+      tile = nt;
+      continue;
+    } else {
+      break;
+    }
+  }
 
   // ---- phase 0a: raw values of the lattice region (prefetched) ----
 #pragma unroll
@@ -621,8 +719,11 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys phd, const double* __re
 
   // prefetch the next tile's raw values; the loads complete while this tile
   // computes
-  const int next = it.advance();
-  if (next >= 0) load_raw(g, Uk, 2 * TX * (next % ntx), 2 * TY * (next / ntx), tid, pre);
+  const int next = next_tile(it.advance());
+  if (next >= 0) {
+    const TileArgs An = args(next);
+    load_raw(An.g, An.Uk, 2 * TX * (An.lt % An.ntx), 2 * TY * (An.lt / An.ntx), tid, pre);
+  }
 
   // ---- phase 1: gradients on the block +- 2 ----
   {
@@ -932,9 +1033,15 @@ __global__ void __launch_bounds__(NT) k_stage(G2 g, Phys phd, const double* __re
       }
     }
   }
+  if constexpr (BATCH) {
+    if (nonfinite) raise_flag(flags, FLAG_NONFINITE);
+    nonfinite = false;
+  }
   tile = next;
   }  // tiles
-  if (nonfinite) raise_flag(flags, FLAG_NONFINITE);
+  if constexpr (!BATCH) {
+    if (nonfinite) raise_flag(sa.flags, FLAG_NONFINITE);
+  }
 }
 
 // persistent workgroups of a stage kernel instance: as many as fit on the
@@ -949,7 +1056,7 @@ int resident_workgroups() {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         cus <= 0)
       cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_stage<R>, NT, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_stage<R, false>, NT, 0) != hipSuccess ||
         per <= 0)
       per = 1;
     cache[dev] = cus * per;
@@ -967,10 +1074,45 @@ hipError_t launch(const G2& g, const Phys& ph, const afi::Work& w, const double*
   int nwg = resident_workgroups<R>();
   if (nwg > ntiles) nwg = ntiles;
   if (nwg >= 8) nwg -= nwg % 8;
+  StageArgs sa{};
+  sa.g = g;
+  sa.ph = ph;
+  sa.Uk = Uk;
+  sa.Un = Un;
+  sa.Uout = Uout;
+  sa.dt_dev = dt_dev;
+  sa.dt_host = dt_host;
+  sa.flags = w.flags;
+  sa.ntx = ntx;
+  sa.ca = sc.a;
+  sa.cb = sc.b;
+  sa.first = sc.first;
+  sa.skip_flagged = sc.skip_flagged;
+  sa.ntiles = ntiles;
   AFI_TIMED(tm, 7, s,
-            hipLaunchKernelGGL(k_stage<R>, dim3((unsigned)nwg), dim3(NT), 0, s, g, ph, Uk, Un,
-                               Uout, dt_dev, dt_host, sc.a, sc.b, sc.first, sc.skip_flagged,
-                               w.flags, ntx, ntiles));
+            hipLaunchKernelGGL((k_stage<R, false>), dim3((unsigned)nwg), dim3(NT), 0, s, sa));
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_batch(afi::BatchInst* inst, int ninst, int total_tiles, const int* n_active,
+                        int k, hipStream_t s, afi::Timer* tm) {
+  if (ninst > kMaxBatch) return hipErrorInvalidValue;
+  StageArgs sa{};
+  sa.inst = inst;
+  sa.ninst = ninst;
+  sa.k = k;
+  sa.n_active = n_active;
+  sa.ca = k == 0 ? 0.0 : (k == 1 ? 0.75 : 1.0 / 3.0);
+  sa.cb = k == 0 ? 1.0 : (k == 1 ? 0.25 : 2.0 / 3.0);
+  sa.first = k == 0;
+  sa.skip_flagged = 1;
+  sa.ntiles = total_tiles;
+  int nwg = resident_workgroups<R>();
+  if (nwg > total_tiles) nwg = total_tiles;
+  if (nwg >= 8) nwg -= nwg % 8;
+  AFI_TIMED(tm, 7, s,
+            hipLaunchKernelGGL((k_stage<R, true>), dim3((unsigned)nwg), dim3(NT), 0, s, sa));
   return hipGetLastError();
 }
 
@@ -981,7 +1123,16 @@ namespace afi {
 hipError_t AF_STAGE_ENTRY(const Geo& geo, const Phys& ph, const Work& w, const double* Un,
                           const double* Uk, double* Uout, const double* dt_dev, double dt_host,
                           StageCoef sc, hipStream_t s, Timer* tm) {
-  return launch<AF_STAGE_REAL>(make_g2(geo), ph, w, Un, Uk, Uout, dt_dev, dt_host, sc, s, tm);
+  return launch<AF_STAGE_REAL>(afi::stage_geo(geo), ph, w, Un, Uk, Uout, dt_dev, dt_host, sc, s, tm);
+}
+
+// tiles of one 2D grid for this instance's tile shape
+int AF_STAGE_TILES(const Geo& geo) { return (geo.n1 / TX + 1) * (geo.n2 / TY + 1); }
+
+// stage k of a step attempt of every active instance of a batch, one launch
+hipError_t AF_STAGE_BATCH(BatchInst* inst, int ninst, int total_tiles, const int* n_active, int k,
+                          hipStream_t s, Timer* tm) {
+  return launch_batch<AF_STAGE_REAL>(inst, ninst, total_tiles, n_active, k, s, tm);
 }
 
 }  // namespace afi

@@ -1,0 +1,99 @@
+"""GPU checks of batches (af_batch_*): many independent 2D instances whose
+stages run as one persistent launch per stage, each instance with its own
+CFL time step and its own step halving decided on the device.  The batch
+must reproduce, bit for bit, what af_run gives for each instance alone (the
+same tile arithmetic, the same exact max-reductions for dt, the same
+decisions), with and without HIP-graph replay, in both precisions; and a
+small batch is checked against the FP64 oracle directly."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from parity import assert_close
+from paper_2609_29081_amd import af
+from paper_2609_29081_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GAMMA = 1.4
+
+
+def instances():
+    """heterogeneous instances: sizes, boundaries, viscosities, a shock tube
+    that halves its steps and a smooth periodic field that does not"""
+    out = []
+    g, f = W.shock_tube_2d(40, 20, rho_left=60.0)
+    out.append((g, f, dict(mu=0.005, Pr=0.73)))
+    g, f = W.vortex_wave_2d(24)
+    out.append((g, f, dict(mu=1e-3, Pr=0.72)))
+    g, f = W.random_smooth_2d(19, 33, seed=5, bc=(W.NOSLIP, W.OUTFLOW, W.SYMMETRY, W.NOSLIP),
+                              amp=0.15)
+    out.append((g, f, dict(mu=0.01, Pr=0.72)))
+    g, f = W.shock_tube_2d(70, 35, rho_left=120.0)
+    out.append((g, f, dict(mu=0.002, Pr=0.73)))
+    g, f = W.double_rarefaction(30, 26, speed=1.5, angle=0.3)
+    out.append((g, f, dict(mu=1e-3, Pr=0.72)))
+    return out
+
+
+def run_single(g, f, kw, steps, precision):
+    S = af.Solver(g, precision=precision, **kw)
+    U = S.to_device(W.make_state(g, f, GAMMA))
+    st, n, t = S.af_run(U, 0.0, 1e30, steps, check_every=1)
+    assert st == af.AF_OK and n == steps
+    return U.cpu().numpy(), t
+
+
+@pytest.mark.parametrize("precision,use_graph,aps", [(af.PREC_FP64, False, 4),
+                                                     (af.PREC_FP64, True, 3),
+                                                     (af.PREC_FP64, False, 1),
+                                                     (af.PREC_MIXED, True, 4)])
+def test_batch_reproduces_single_runs(precision, use_graph, aps):
+    steps = 6
+    insts = instances()
+    solvers = [af.Solver(g, precision=precision, **kw) for g, f, kw in insts]
+    states = [S.to_device(W.make_state(g, f, GAMMA)) for S, (g, f, kw) in zip(solvers, insts)]
+    B = af.Batch(solvers)
+    st, n, t, att = B.af_batch_run(states, 0.0, 1e30, steps, attempts_per_slot=aps,
+                                   use_graph=use_graph)
+    assert st == [af.AF_OK] * len(insts)
+    assert n == [steps] * len(insts)
+    assert max(att) > steps  # at least one instance halved a step
+    for (g, f, kw), U, ti in zip(insts, states, t):
+        ref, tr = run_single(g, f, kw, steps, precision)
+        assert ti == tr
+        assert np.array_equal(U.cpu().numpy(), ref)
+
+
+def test_batch_matches_the_oracle():
+    insts = instances()[1:3]
+    solvers = [af.Solver(g, **kw) for g, f, kw in insts]
+    states = [S.to_device(W.make_state(g, f, GAMMA)) for S, (g, f, kw) in zip(solvers, insts)]
+    B = af.Batch(solvers)
+    st, n, t, att = B.af_batch_run(states, 0.0, 1e30, 3)
+    assert st == [af.AF_OK, af.AF_OK] and n == [3, 3]
+    for (g, f, kw), U, ti in zip(insts, states, t):
+        cfg = O.make_cfg(g, **kw)
+        ref = W.make_state(g, f, GAMMA)
+        sto, no, to = O.run(cfg, ref, 0.0, 1e30, 3)
+        assert sto == 0 and no == 3
+        assert ti == pytest.approx(to, rel=1e-13)
+        assert_close(g, U.cpu().numpy(), ref, what="batch vs oracle")
+
+
+def test_batch_stops_at_t_final_and_counts_attempts():
+    insts = instances()[:2]
+    solvers = [af.Solver(g, **kw) for g, f, kw in insts]
+    states = [S.to_device(W.make_state(g, f, GAMMA)) for S, (g, f, kw) in zip(solvers, insts)]
+    t_final = 2e-4
+    st, n, t, att = af.Batch(solvers).af_batch_run(states, 0.0, t_final, 10 ** 6)
+    assert st == [af.AF_OK, af.AF_OK]
+    assert all(abs(ti - t_final) <= 1e-15 * t_final for ti in t)
+    assert all(a >= k for a, k in zip(att, n))
+    for (g, f, kw), U, ni, ti in zip(insts, states, n, t):
+        S = af.Solver(g, **kw)
+        V = S.to_device(W.make_state(g, f, GAMMA))
+        st1, n1, t1 = S.af_run(V, 0.0, t_final, 10 ** 6, check_every=1)
+        assert n1 == ni and t1 == ti
+        assert np.array_equal(U.cpu().numpy(), V.cpu().numpy())
