@@ -79,6 +79,12 @@ def main() -> int:
                     help="skip the mixed-precision form")
     ap.add_argument("--roofline-reps", type=int, default=10,
                     help="repetitions of the three stage kinds timed for the roofline")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched shock-tube sweep form")
+    ap.add_argument("--batch-n", type=int, default=64,
+                    help="instances of the batched shock-tube sweep")
+    ap.add_argument("--batch-steps", type=int, default=100,
+                    help="accepted steps per instance of the batched sweep")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -265,6 +271,8 @@ def main() -> int:
                     "traffic": trm["bytes_per_launch"],
                     "executed_TFLOPs": {"fp32": round(f32 / stage_s_m / 1e12, 2),
                                         "fp64": round(f64 / stage_s_m / 1e12, 2)}})
+    if not args.no_batched:
+        forms["batched"] = batched_form(args, stream)
     out = {
         "metric": METRIC, "value": value, "unit": "DOF-updates/s", "n_gpus": 1, "steps": K,
         "warmup": Wm, "ms_per_step": gpu_ms / K, "higher_is_better": True, "scaling": "weak",
@@ -290,6 +298,67 @@ def main() -> int:
     }
     print(json.dumps(out))
     return 0
+
+
+def batched_form(args, stream) -> dict:
+    """The batched form: a seeded sweep of viscous shock tubes (random
+    Reynolds number, density ratio and grid, see workloads.shock_tube_sweep),
+    mixed precision, advanced together by af_batch_run with HIP-graph replay,
+    each instance with its own time step and halving; the stage variant (tile
+    shape) is chosen by af_batch_tune on the initial states.  Timed: K
+    accepted steps of every instance from t = 0 (inputs resident in HBM).
+    value = sum over instances of DOF sites x 3 stages x steps / second."""
+    import torch
+
+    from paper_2609_29081_amd import af
+    from paper_2609_29081_amd import workloads as W
+
+    print(f"bench: batched sweep of {args.batch_n} shock tubes", file=sys.stderr, flush=True)
+    insts = W.shock_tube_sweep(args.batch_n, seed=0)
+    solvers = [af.Solver(g, precision=af.PREC_MIXED, cfl_c=0.2, cfl_v=0.075,
+                         limiter=af.LIM_ALL, **kw) for g, f, kw in insts]
+    init = [S.to_device(W.make_state(g, f, kw["gamma"])) for S, (g, f, kw) in zip(solvers, insts)]
+    states = [U.clone() for U in init]
+    B = af.Batch(solvers)
+    t0 = time.perf_counter()
+    us = B.af_batch_tune(states, 0.0, 1e30, reps=3)
+    tune_s = time.perf_counter() - t0
+    names = af.stage_variants()
+    chosen = names[B.variant]
+    K, Wm = args.batch_steps, min(args.warmup, 2)
+    if Wm > 0:
+        B.af_batch_run(states, 0.0, 1e30, Wm, attempts_per_slot=4, use_graph=True)
+        for U, U0 in zip(states, init):
+            U.copy_(U0)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    e0.record(stream)
+    st, n, t, att = B.af_batch_run(states, 0.0, 1e30, K, attempts_per_slot=4, use_graph=True,
+                                   stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    if st != [af.AF_OK] * len(insts) or n != [K] * len(insts):
+        raise RuntimeError(f"batched run failed: status {st}, steps {n}")
+    ms = e0.elapsed_time(e1)
+    dof = sum(g.dof_sites for g, f, kw in insts)
+    cells = sum(g.n1 * g.n2 for g, f, kw in insts)
+    return {"value": dof * 3 * K / (ms / 1e3), "unit": "DOF-updates/s",
+            "cell_updates_per_s": cells * 3 * K / (ms / 1e3),
+            "ms_total": round(ms, 1), "wall_s": round(wall, 2),
+            "workload": f"{len(insts)} viscous shock tubes, rng seed 0: Re ~ U[200,1000], "
+                        "density ratio ~ U[50,200], N1 on {128,...,1024} step 64, N2 = N1/2; "
+                        f"{K} accepted steps each, own dt and halving; mixed precision",
+            "instances": len(insts), "cells": cells, "dof_sites": dof,
+            "rk3_attempts_per_step": round(sum(att) / (K * len(insts)), 3),
+            "graph": True, "attempts_per_slot": 4,
+            "variant": chosen[0], "tile": f"16x{chosen[2]}",
+            "tune_us_per_slot": {nm[0]: round(u, 1) for nm, u in zip(names, us) if u > 0},
+            "tune_s": round(tune_s, 2),
+            "error": "bitwise equal to single-instance mixed runs; FP32-stencil error as in "
+                     "the mixed form"}
 
 
 if __name__ == "__main__":

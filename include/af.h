@@ -206,15 +206,41 @@ void af_batch_destroy(af_batch* b);
 size_t af_batch_workspace_bytes(const af_batch* b);
 /* Advance the device states U[i] (af_state_len doubles of ctxs[i] each) from
  * t0 until t_final or max_steps accepted steps per instance; synchronous.
- * Steps are enqueued in slots of one CFL step opening and attempts_per_slot
- * (>= 1) attempts; an instance that needs more halvings continues in the
- * next slot.  use_graph != 0 captures one slot in a HIP graph and replays
- * it.  steps[i], t[i], status[i] (AF_OK, AF_E_PP, AF_E_NONFINITE: the state
+ * Work is enqueued in slots of attempts_per_slot (>= 1) rounds: a round
+ * opens a step (fresh CFL dt) for every instance that is between steps and
+ * runs one RK3 attempt of every instance inside a step; the attempt is then
+ * accepted or redone with dt/2 in the next round (af_run's halving rule).
+ * use_graph != 0 captures one slot in a HIP graph and replays it.  steps[i], t[i], status[i] (AF_OK, AF_E_PP, AF_E_NONFINITE: the state
  * is then the one before the failed step) and attempts[i] (RK3 attempts,
  * accepted and rejected) receive per-instance results; any may be NULL. */
 af_status af_batch_run(af_batch* b, double* const* U, void* ws, void* stream, double t0,
                        double t_final, long max_steps, int attempts_per_slot, int use_graph,
                        long* steps, double* t, int* status, long* attempts);
+
+/* Compiled variants of the 2D stage kernel.  Each is the same arithmetic
+ * (results are identical to the last bit) over a different tile shape:
+ * tiles are 16 cells wide and tile_height cells high, and the taller the
+ * tile the fewer halo sites are recomputed but the more LDS a workgroup
+ * takes, so fewer workgroups are resident per CU.  The first variant of
+ * each precision is the one af_rk_stage, af_step, af_run and new batches
+ * use. */
+int af_stage_variant_count(void);
+/* name (static storage), precision (AF_PREC_*) and tile height of variant
+ * i in [0, af_stage_variant_count()); any output may be NULL. */
+af_status af_stage_variant_info(int i, const char** name, int* precision, int* tile_height);
+/* Index of the variant the batch's stage launches use. */
+int af_batch_variant(const af_batch* b);
+/* Use variant i for the batch; it must have the batch's precision. */
+af_status af_batch_set_variant(af_batch* b, int i);
+/* Autotuner: for every variant of the batch's precision, time one step slot
+ * (CFL step opening, one RK3 attempt of every instance from the states U at
+ * time t0, and the accept/halve decision) reps times after one untimed slot,
+ * and keep the fastest variant for the batch's later runs.  Synchronous; U
+ * is read, never written (ws must be the batch's workspace).  us_per_slot,
+ * if not NULL, receives af_stage_variant_count() entries: the fastest time
+ * of each variant in microseconds, -1 for variants of the other precision. */
+af_status af_batch_tune(af_batch* b, double* const* U, void* ws, void* stream, double t0,
+                        double t_final, int reps, double* us_per_slot);
 
 const char* af_last_error(void);
 

@@ -44,7 +44,9 @@ EXPORTS = ["af_default_params", "af_init_grid", "af_destroy", "af_set_bc", "af_s
            "af_state_bytes", "af_workspace_bytes", "af_set_state", "af_get_state",
            "af_check_admissible", "af_rk_stage", "af_cfl_dt", "af_step", "af_run",
            "af_read_flags", "af_reset_flags", "af_timing", "af_timing_read", "af_last_error",
-           "af_batch_create", "af_batch_destroy", "af_batch_workspace_bytes", "af_batch_run"]
+           "af_batch_create", "af_batch_destroy", "af_batch_workspace_bytes", "af_batch_run",
+           "af_stage_variant_count", "af_stage_variant_info", "af_batch_variant",
+           "af_batch_set_variant", "af_batch_tune"]
 
 # kernel kinds reported by af_timing_read
 KERNEL_KINDS = {0: "lattice", 1: "grad", 2: "cellpre", 3: "face", 4: "cells", 5: "points",
@@ -80,6 +82,12 @@ def lib():
         L.af_batch_destroy.restype = None
         L.af_batch_workspace_bytes.argtypes = [vp]
         L.af_batch_workspace_bytes.restype = C.c_size_t
+        L.af_stage_variant_count.argtypes = []
+        L.af_stage_variant_info.argtypes = [ip, C.POINTER(C.c_char_p), C.POINTER(ip),
+                                            C.POINTER(ip)]
+        L.af_batch_variant.argtypes = [vp]
+        L.af_batch_set_variant.argtypes = [vp, ip]
+        L.af_batch_tune.argtypes = [vp, C.POINTER(vp), vp, vp, C.c_double, C.c_double, ip, dp]
         L.af_batch_run.argtypes = [vp, C.POINTER(vp), vp, vp, C.c_double, C.c_double, C.c_long, ip,
                                    ip, C.POINTER(C.c_long), dp, C.POINTER(C.c_int),
                                    C.POINTER(C.c_long)]
@@ -232,6 +240,16 @@ class Solver:
         return {KERNEL_KINDS.get(k, f"k{k}"): (n[k], ms[k]) for k in range(K_COUNT) if n[k]}
 
 
+def stage_variants() -> list:
+    """the compiled 2D stage variants: (name, precision, tile height) each"""
+    out = []
+    for i in range(lib().af_stage_variant_count()):
+        name, prec, ty = C.c_char_p(), C.c_int(), C.c_int()
+        _check(lib().af_stage_variant_info(i, C.byref(name), C.byref(prec), C.byref(ty)))
+        out.append((name.value.decode(), prec.value, ty.value))
+    return out
+
+
 class Batch:
     """A batch of 2D solvers (one precision) advanced together by af_batch_run:
     each stage of every instance is one persistent launch, each instance with
@@ -271,3 +289,27 @@ class Batch:
                                   max_steps, attempts_per_slot, 1 if use_graph else 0, steps, t,
                                   st, att))
         return list(st), list(steps), list(t), list(att)
+
+    @property
+    def variant(self) -> int:
+        """index (into stage_variants()) of the stage variant the batch uses"""
+        return int(lib().af_batch_variant(self.h))
+
+    @variant.setter
+    def variant(self, i: int):
+        _check(lib().af_batch_set_variant(self.h, int(i)))
+
+    def af_batch_tune(self, states: list, t0: float, t_final: float, reps: int = 3,
+                      stream=None) -> list:
+        """time every stage variant of the batch's precision on one step slot
+        from the given states and keep the fastest; returns the time per slot
+        of each variant in microseconds (-1 for the other precision)"""
+        n = len(self.solvers)
+        if len(states) != n:
+            raise ValueError("one state per instance")
+        ptrs = (C.c_void_p * n)(*[U.data_ptr() for U in states])
+        nv = lib().af_stage_variant_count()
+        us = (C.c_double * nv)()
+        _check(lib().af_batch_tune(self.h, ptrs, _ptr(self.ws), _stream(stream), t0, t_final,
+                                   reps, us))
+        return list(us)

@@ -8,16 +8,22 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libaf.so")
-# (source, object, extra flags): the 2D stage is compiled twice, as the FP64
-# stage (16 x 7 tiles) and as the mixed-precision stage (FP32 stencils, whose
-# smaller LDS footprint admits 16 x 10 tiles)
+# The 2D stage is compiled once per variant (arithmetic type, tile height):
+# the FP64 stage with 16x7 tiles (the largest its LDS admits) and 16x5, the
+# mixed-precision stage (FP32 stencils) with 16x10, 16x7 and 16x14.  The
+# first variant of each precision is the one single-instance stages use; the
+# batch autotuner chooses among all of a precision.  (entry name, type, TY)
+STAGE_VARIANTS = [("stage2d_fp64_t7", "double", 7), ("stage2d_fp64_t5", "double", 5),
+                  ("stage2d_mixed_t10", "float", 10), ("stage2d_mixed_t7", "float", 7),
+                  ("stage2d_mixed_t14", "float", 14)]
+# (source, object, extra flags)
 SOURCES = [("af_capi.cpp", "af_capi.o", []),
+           ("af_variants.cpp", "af_variants.o", ["--cuda-host-only"]),
            ("af_common.hip", "af_common.o", []),
-           ("af_kern1d.hip", "af_kern1d.o", []),
-           ("af_stage2d.hip", "af_stage2d_fp64.o",
-            ["-DAF_STAGE_REAL=double", "-DAF_STAGE_TY=7", "-DAF_STAGE_ENTRY=stage2d_fp64"]),
-           ("af_stage2d.hip", "af_stage2d_mixed.o",
-            ["-DAF_STAGE_REAL=float", "-DAF_STAGE_TY=10", "-DAF_STAGE_ENTRY=stage2d_mixed"])]
+           ("af_kern1d.hip", "af_kern1d.o", [])] + [
+    ("af_stage2d.hip", f"{name}.o",
+     [f"-DAF_STAGE_REAL={real}", f"-DAF_STAGE_TY={ty}", f"-DAF_STAGE_ENTRY={name}"])
+    for name, real, ty in STAGE_VARIANTS]
 ARCH = "gfx950"
 
 
@@ -32,14 +38,18 @@ def build(verbose: bool = False) -> str:
     objs = []
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
+    procs = []
     for src, oname, extra in SOURCES:
         obj = os.path.join(bdir, oname)
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
         cmd = ["hipcc", *hip_flags(), *extra, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        procs.append((cmd, subprocess.Popen(cmd)))
         objs.append(obj)
+    for cmd, p in procs:
+        if p.wait() != 0:
+            raise subprocess.CalledProcessError(p.returncode, cmd)
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", LIB + ".tmp", *objs]
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)

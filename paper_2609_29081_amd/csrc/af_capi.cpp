@@ -69,7 +69,7 @@ struct af_batch {
   std::vector<af_ctx*> ctx;
   std::vector<afi::Geo> geo;
   int mixed = 0;
-  int total_tiles = 0;
+  const afi::StageVariant* var = nullptr;  // stage variant (tile shape) of the batch
   // workspace: descriptors, CFL partials, active count, then two stage
   // buffers per instance
   size_t off_partial = 0, off_nact = 0, bytes = 0;
@@ -183,6 +183,61 @@ hipError_t rk3(const afi::Geo& g, const afd::Phys& ph, const afi::Work& w, const
   if ((e = launch_stage(g, ph, w, 0, cur, cur, w.S1, dt_dev, dt, s, tm)) != hipSuccess) return e;
   if ((e = launch_stage(g, ph, w, 1, cur, w.S1, w.S2, dt_dev, dt, s, tm)) != hipSuccess) return e;
   return launch_stage(g, ph, w, 2, cur, w.S2, out, dt_dev, dt, s, tm);
+}
+
+// host copies of the batch descriptors for states U, times t0..t_final and
+// the tile shape of stage variant v; *total_tiles receives the tiles of all
+// instances (a stage launch has at most that many)
+af_status batch_descriptors(const af_batch* b, const afi::StageVariant* v, double* const* U,
+                            char* base, double t0, double t_final, long max_steps,
+                            std::vector<afi::BatchInst>& h, int* total_tiles) {
+  const int n = (int)b->ctx.size();
+  h.assign(n, afi::BatchInst{});
+  int total = 0;
+  for (int i = 0; i < n; ++i) {
+    const af_params& p = b->ctx[i]->p;
+    const afi::Geo& g = b->geo[i];
+    if (!U[i]) return fail(AF_E_ARG, "batch: state %d is NULL", i);
+    afi::BatchInst& I = h[i];
+    memset(&I, 0, sizeof(I));
+    I.g = afi::stage_geo(g);
+    I.ph = physics(p);
+    I.buf[0] = U[i];
+    I.buf[1] = (double*)(base + b->off_bufs[2 * i]);
+    I.buf[2] = (double*)(base + b->off_bufs[2 * i + 1]);
+    I.ntx = g.n1 / 16 + 1;
+    I.ntiles = v->tiles(g);
+    total += I.ntiles;
+    I.ncell = (long)g.n1 * g.n2;
+    I.icx = 1.0 / (p.cfl_c * g.dx);
+    I.icy = 1.0 / (p.cfl_c * g.dy);
+    const double hmin = fmin(g.dx, g.dy);
+    I.vcoef = fmax(4.0 * p.mu / 3.0, p.gamma * p.mu / p.Pr) / (p.cfl_v * hmin * hmin);
+    I.t_final = t_final;
+    I.max_steps = max_steps;
+    I.max_halvings = p.max_halvings;
+    I.t = t0;
+  }
+  *total_tiles = total;
+  return AF_OK;
+}
+
+// one slot of a batch: `rounds` rounds, each of which opens a step (fresh
+// CFL dt) for every instance that is between steps and then runs one RK3
+// attempt of every instance inside a step (three stage launches of variant
+// v, then the accept/halve decision).  An instance that accepts a step opens
+// the next one in the following round, while others redo theirs with dt/2.
+hipError_t batch_slot(const afi::StageVariant* v, afi::BatchInst* dinst, int n, int total_tiles,
+                      double* partial, int* nact, int rounds, hipStream_t q) {
+  hipError_t e;
+  for (int a = 0; a < rounds; ++a) {
+    if ((e = afi::batch_cfl(dinst, n, partial, q)) != hipSuccess) return e;
+    if ((e = afi::batch_open(dinst, n, partial, nact, q)) != hipSuccess) return e;
+    for (int k = 0; k < 3; ++k)
+      if ((e = v->batch(dinst, n, total_tiles, nact, k, q, nullptr)) != hipSuccess) return e;
+    if ((e = afi::batch_decide(dinst, n, nact, q)) != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace
@@ -553,11 +608,11 @@ af_status af_batch_create(af_ctx* const* ctxs, int n, af_batch** out) {
     if (!geometry(c, &g)) return AF_E_ARG;
     b->ctx.push_back(c);
     b->geo.push_back(g);
-    b->total_tiles += b->mixed ? afi::stage2d_mixed_tiles(g) : afi::stage2d_fp64_tiles(g);
     b->off_bufs.push_back(take(sizeof(double) * g.state_len));
     b->off_bufs.push_back(take(sizeof(double) * g.state_len));
   }
   b->bytes = off;
+  b->var = afi::default_variant(b->mixed);
   *out = b.release();
   return AF_OK;
 }
@@ -578,47 +633,14 @@ af_status af_batch_run(af_batch* b, double* const* U, void* ws, void* stream, do
   afi::BatchInst* dinst = (afi::BatchInst*)base;
   double* partial = (double*)(base + b->off_partial);
   int* nact = (int*)(base + b->off_nact);
-  std::vector<afi::BatchInst> h(n);
-  int tile0 = 0;
-  for (int i = 0; i < n; ++i) {
-    const af_params& p = b->ctx[i]->p;
-    const afi::Geo& g = b->geo[i];
-    if (!U[i]) return fail(AF_E_ARG, "af_batch_run: state %d is NULL", i);
-    afi::BatchInst& I = h[i];
-    memset(&I, 0, sizeof(I));
-    I.g = afi::stage_geo(g);
-    I.ph = physics(p);
-    I.buf[0] = U[i];
-    I.buf[1] = (double*)(base + b->off_bufs[2 * i]);
-    I.buf[2] = (double*)(base + b->off_bufs[2 * i + 1]);
-    I.ntx = g.n1 / 16 + 1;
-    I.ntiles = b->mixed ? afi::stage2d_mixed_tiles(g) : afi::stage2d_fp64_tiles(g);
-    I.tile0 = tile0;
-    tile0 += I.ntiles;
-    I.ncell = (long)g.n1 * g.n2;
-    I.icx = 1.0 / (p.cfl_c * g.dx);
-    I.icy = 1.0 / (p.cfl_c * g.dy);
-    const double hmin = fmin(g.dx, g.dy);
-    I.vcoef = fmax(4.0 * p.mu / 3.0, p.gamma * p.mu / p.Pr) / (p.cfl_v * hmin * hmin);
-    I.t_final = t_final;
-    I.max_steps = max_steps;
-    I.max_halvings = p.max_halvings;
-    I.t = t0;
-  }
+  std::vector<afi::BatchInst> h;
+  int total_tiles = 0;
+  const af_status sd =
+      batch_descriptors(b, b->var, U, base, t0, t_final, max_steps, h, &total_tiles);
+  if (sd != AF_OK) return sd;
   AF_HIP(hipMemcpyAsync(dinst, h.data(), sizeof(afi::BatchInst) * n, hipMemcpyHostToDevice, s));
-  auto slot = [&](hipStream_t q) -> hipError_t {
-    hipError_t e;
-    if ((e = afi::batch_cfl(dinst, n, partial, q)) != hipSuccess) return e;
-    if ((e = afi::batch_open(dinst, n, partial, nact, q)) != hipSuccess) return e;
-    for (int a = 0; a < attempts_per_slot; ++a) {
-      for (int k = 0; k < 3; ++k) {
-        e = b->mixed ? afi::stage2d_mixed_batch(dinst, n, b->total_tiles, nact, k, q, nullptr)
-                     : afi::stage2d_fp64_batch(dinst, n, b->total_tiles, nact, k, q, nullptr);
-        if (e != hipSuccess) return e;
-      }
-      if ((e = afi::batch_decide(dinst, n, nact, q)) != hipSuccess) return e;
-    }
-    return hipSuccess;
+  auto slot = [&](hipStream_t q) {
+    return batch_slot(b->var, dinst, n, total_tiles, partial, nact, attempts_per_slot, q);
   };
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -690,6 +712,92 @@ af_status af_batch_run(af_batch* b, double* const* U, void* ws, void* stream, do
     if (attempts) attempts[i] = h[i].attempts;
   }
   return AF_OK;
+}
+
+int af_stage_variant_count(void) { return afi::kNumStageVariants; }
+
+af_status af_stage_variant_info(int i, const char** name, int* precision, int* tile_height) {
+  if (i < 0 || i >= afi::kNumStageVariants)
+    return fail(AF_E_ARG, "af_stage_variant_info: no variant %d", i);
+  const afi::StageVariant& v = afi::kStageVariants[i];
+  if (name) *name = v.name;
+  if (precision) *precision = v.mixed ? AF_PREC_MIXED : AF_PREC_FP64;
+  if (tile_height) *tile_height = v.ty;
+  return AF_OK;
+}
+
+int af_batch_variant(const af_batch* b) {
+  return b ? (int)(b->var - afi::kStageVariants) : -1;
+}
+
+af_status af_batch_set_variant(af_batch* b, int i) {
+  if (!b) return fail(AF_E_ARG, "af_batch_set_variant: NULL batch");
+  if (i < 0 || i >= afi::kNumStageVariants)
+    return fail(AF_E_ARG, "af_batch_set_variant: no variant %d", i);
+  if (afi::kStageVariants[i].mixed != b->mixed)
+    return fail(AF_E_ARG, "af_batch_set_variant: variant %s has another precision",
+                afi::kStageVariants[i].name);
+  b->var = &afi::kStageVariants[i];
+  return AF_OK;
+}
+
+af_status af_batch_tune(af_batch* b, double* const* U, void* ws, void* stream, double t0,
+                        double t_final, int reps, double* us_per_slot) {
+  if (!b || !U || !ws) return fail(AF_E_ARG, "af_batch_tune: NULL argument");
+  if (reps < 1) return fail(AF_E_ARG, "af_batch_tune: reps must be >= 1");
+  if (!(t_final > t0)) return fail(AF_E_ARG, "af_batch_tune: t_final must exceed t0");
+  const int n = (int)b->ctx.size();
+  const hipStream_t s = (hipStream_t)stream;
+  char* base = (char*)ws;
+  afi::BatchInst* dinst = (afi::BatchInst*)base;
+  double* partial = (double*)(base + b->off_partial);
+  int* nact = (int*)(base + b->off_nact);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  AF_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(AF_E_HIP, "af_batch_tune: event creation failed");
+  }
+  af_status st = AF_OK;
+  const afi::StageVariant* best = b->var;
+  double best_us = -1.0;
+  std::vector<afi::BatchInst> h;
+  for (int i = 0; i < afi::kNumStageVariants && st == AF_OK; ++i) {
+    const afi::StageVariant* v = &afi::kStageVariants[i];
+    if (us_per_slot) us_per_slot[i] = -1.0;
+    if (v->mixed != b->mixed) continue;
+    int total = 0;
+    st = batch_descriptors(b, v, U, base, t0, t_final, 1, h, &total);
+    if (st != AF_OK) break;
+    // one untimed slot, then the fastest of reps; every slot starts from the
+    // same descriptors (current buffer U, so U is never written)
+    double best_v = -1.0;
+    for (int r = 0; r <= reps; ++r) {
+      hipError_t e = hipMemcpyAsync(dinst, h.data(), sizeof(afi::BatchInst) * n,
+                                    hipMemcpyHostToDevice, s);
+      if (e == hipSuccess) e = hipEventRecord(e0, s);
+      if (e == hipSuccess) e = batch_slot(v, dinst, n, total, partial, nact, 1, s);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        st = hip_fail(e, "af_batch_tune");
+        break;
+      }
+      if (r > 0 && (best_v < 0.0 || ms * 1e3 < best_v)) best_v = ms * 1e3;
+    }
+    if (st != AF_OK) break;
+    if (us_per_slot) us_per_slot[i] = best_v;
+    if (best_us < 0.0 || best_v < best_us) {
+      best_us = best_v;
+      best = v;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st == AF_OK) b->var = best;
+  return st;
 }
 
 const char* af_last_error(void) { return g_err.c_str(); }

@@ -64,7 +64,7 @@ struct BatchInst {
   StageGeo g;
   afd::Phys ph;
   double* buf[3];        // rotating states; buf[cur] is the current one
-  int ntx, ntiles, tile0;  // stage tiles of the instance, its first global tile
+  int ntx, ntiles;       // stage tiles along x and in all
   long ncell;            // CFL: cells, 1/(C^c dx), 1/(C^c dy), viscous rate factor
   double icx, icy, vcoef;
   double t_final;
@@ -124,18 +124,10 @@ struct Timer {
   } while (0)
 
 // launchers (enqueue on stream; return the first HIP error)
-hipError_t stage2d_fp64(const Geo& g, const afd::Phys& ph, const Work& w, const double* Un,
-                        const double* Uk, double* Uout, const double* dt_dev, double dt_host,
-                        StageCoef sc, hipStream_t s, Timer* tm);
-hipError_t stage2d_mixed(const Geo& g, const afd::Phys& ph, const Work& w, const double* Un,
-                         const double* Uk, double* Uout, const double* dt_dev, double dt_host,
-                         StageCoef sc, hipStream_t s, Timer* tm);
-inline hipError_t stage2d(const Geo& g, const afd::Phys& ph, const Work& w, const double* Un,
-                          const double* Uk, double* Uout, const double* dt_dev, double dt_host,
-                          StageCoef sc, hipStream_t s, Timer* tm) {
-  return g.mixed ? stage2d_mixed(g, ph, w, Un, Uk, Uout, dt_dev, dt_host, sc, s, tm)
-                 : stage2d_fp64(g, ph, w, Un, Uk, Uout, dt_dev, dt_host, sc, s, tm);
-}
+// the 2D stage of one instance, with its precision's default variant
+hipError_t stage2d(const Geo& g, const afd::Phys& ph, const Work& w, const double* Un,
+                   const double* Uk, double* Uout, const double* dt_dev, double dt_host,
+                   StageCoef sc, hipStream_t s, Timer* tm);
 hipError_t stage1d(const Geo& g, const afd::Phys& ph, const Work& w, const double* Un,
                    const double* Uk, double* Uout, const double* dt_dev, double dt_host,
                    StageCoef sc, hipStream_t s, Timer* tm);
@@ -162,13 +154,20 @@ hipError_t batch_cfl(BatchInst* inst, int n, double* partial, hipStream_t s);
 hipError_t batch_open(BatchInst* inst, int n, const double* partial, int* n_active,
                       hipStream_t s);
 hipError_t batch_decide(BatchInst* inst, int n, int* n_active, hipStream_t s);
-// the 2D stage over a batch (af_stage2d.hip, one per precision), and the
-// number of stage tiles of a grid for that instance's tile shape
-hipError_t stage2d_fp64_batch(BatchInst* inst, int ninst, int total_tiles, const int* n_active,
-                              int k, hipStream_t s, Timer* tm);
-hipError_t stage2d_mixed_batch(BatchInst* inst, int ninst, int total_tiles, const int* n_active,
-                               int k, hipStream_t s, Timer* tm);
-int stage2d_fp64_tiles(const Geo& g);
-int stage2d_mixed_tiles(const Geo& g);
+// Compiled variants of the 2D stage (af_stage2d.hip, one object each): the
+// single-instance stage, the batch stage and the tile count of a grid.
+struct StageVariant {
+  const char* name;
+  int mixed;  // 1: FP32 stencils
+  int ty;     // tile height (cells)
+  hipError_t (*single)(const Geo&, const afd::Phys&, const Work&, const double*, const double*,
+                       double*, const double*, double, StageCoef, hipStream_t, Timer*);
+  hipError_t (*batch)(BatchInst*, int, int, const int*, int, hipStream_t, Timer*);
+  int (*tiles)(const Geo&);
+};
+// all variants; the first of each precision is its default
+extern const StageVariant kStageVariants[];
+extern const int kNumStageVariants;
+const StageVariant* default_variant(int mixed);
 
 }  // namespace afi

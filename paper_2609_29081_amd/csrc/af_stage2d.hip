@@ -501,10 +501,14 @@ struct StageArgs {
   int first, skip_flagged, ntiles;
 };
 
-// what one tile of a stage works on
+// what one tile of a stage works on.  Geometry and physics are referenced,
+// not copied: a copy would hold some thirty uniform values live across the
+// whole tile (register pressure of a kernel that is at its VGPR limit), while
+// a reference to the kernel arguments or to the batch descriptor in global
+// memory is re-read where needed.
 struct TileArgs {
-  G2 g;
-  Phys phd;
+  const G2* g;
+  const Phys* phd;
   const double* Uk;
   const double* Un;
   double* Uout;
@@ -513,8 +517,9 @@ struct TileArgs {
   int ntx, lt;  // tiles along x of its grid, the tile's index in its grid
 };
 
-// tile t of a batch: t0[i] is the first global tile of instance i
-__device__ __forceinline__ int batch_instance(const int* t0, int n, int t) {
+// position of tile t in a batch's list of n active instances whose first
+// tiles are t0[0] = 0 < t0[1] < ...
+__device__ __forceinline__ int batch_slot_of(const int* t0, int n, int t) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -526,14 +531,19 @@ __device__ __forceinline__ int batch_instance(const int* t0, int n, int t) {
   return lo;
 }
 
-__device__ __forceinline__ TileArgs batch_tile(const StageArgs& sa, const int* t0, int t) {
-  const int in = batch_instance(t0, sa.ninst, t);
+// tile t of the active tiles of a batch: active instance j is instance
+// id[j] and owns tiles [t0[j], t0[j + 1])
+__device__ __forceinline__ TileArgs batch_tile(const StageArgs& sa, const int* t0, const int* id,
+                                               int nact, int t) {
+  // the instance is the same for the whole workgroup
+  const int j = __builtin_amdgcn_readfirstlane(batch_slot_of(t0, nact, t));
+  const int in = __builtin_amdgcn_readfirstlane(id[j]);
   const afi::BatchInst& I = sa.inst[in];
   TileArgs A;
-  A.g = I.g;
-  A.phd = I.ph;
+  A.g = &I.g;
+  A.phd = &I.ph;
   A.ntx = I.ntx;
-  A.lt = t - t0[in];
+  A.lt = t - t0[j];
   A.dt = I.dt;
   A.flags = &sa.inst[in].flags;
   // the three RK3 stages from buf[cur], through the other two buffers
@@ -552,54 +562,73 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
   const double ca = sa.ca, cb = sa.cb;
   const int first = sa.first, skip_flagged = sa.skip_flagged;
   bool nonfinite = false;
-  // a batch: first global tile of each instance and whether it is active
-  __shared__ int bt0[BATCH ? kMaxBatch : 1], bact[BATCH ? kMaxBatch : 1];
+  // a batch: only the tiles of its active instances are numbered, so that
+  // every XCD band holds an equal share of the work whichever instances are
+  // active (instances finish their steps after different numbers of
+  // attempts).  Active instance j is instance bid[j] and owns tiles
+  // [bt0[j], bt0[j] + its ntiles); the numbering comes from two inclusive
+  // scans over the instances (one per thread), done in place in bt0 / bid.
+  __shared__ int bt0[BATCH ? kMaxBatch : 1], bid[BATCH ? kMaxBatch : 1];
+  int ntiles = sa.ntiles, nact = 0;
   if constexpr (BATCH) {
+    static_assert(kMaxBatch == NT, "one instance per thread in the scans");
     if (*sa.n_active == 0) return;  // every instance has finished its step
-    for (int i = tid; i < sa.ninst; i += NT) {
-      bt0[i] = sa.inst[i].tile0;
-      bact[i] = sa.inst[i].active;
+    const bool act = tid < sa.ninst && sa.inst[tid].active;
+    const int own = act ? sa.inst[tid].ntiles : 0;
+    bid[tid] = act ? 1 : 0;
+    bt0[tid] = own;
+    __syncthreads();
+    for (int off = 1; off < NT; off <<= 1) {
+      const int c = tid >= off ? bid[tid - off] : 0;
+      const int t = tid >= off ? bt0[tid - off] : 0;
+      __syncthreads();
+      bid[tid] += c;
+      bt0[tid] += t;
+      __syncthreads();
+    }
+    const int pos = bid[tid] - 1, first_tile = bt0[tid] - own;
+    nact = bid[NT - 1];
+    ntiles = bt0[NT - 1];
+    __syncthreads();
+    if (act) {
+      bid[pos] = tid;
+      bt0[pos] = first_tile;
     }
     __syncthreads();
   }
-  TileArgs A0;  // the one instance
-  if constexpr (!BATCH) {
-    A0.g = sa.g;
-    A0.phd = sa.ph;
-    A0.Uk = sa.Uk;
-    A0.Un = sa.Un;
-    A0.Uout = sa.Uout;
-    A0.dt = sa.dt_dev ? *sa.dt_dev : sa.dt_host;
-    A0.flags = sa.flags;
-    A0.ntx = sa.ntx;
-  }
+  // the one instance's dt, read once (a per-tile read costs ~3% of the stage)
+  double dt1 = 0.0;
+  if constexpr (!BATCH) dt1 = sa.dt_dev ? *sa.dt_dev : sa.dt_host;
+  // what tile t works on (built where used, from the kernel arguments or the
+  // batch descriptors, so that nothing of it stays live across tiles)
   auto args = [&](int t) {
     if constexpr (BATCH) {
-      return batch_tile(sa, bt0, t);
+      return batch_tile(sa, bt0, bid, nact, t);
     } else {
-      TileArgs A = A0;
+      TileArgs A;
+      A.g = &sa.g;
+      A.phd = &sa.ph;
+      A.Uk = sa.Uk;
+      A.Un = sa.Un;
+      A.Uout = sa.Uout;
+      A.dt = dt1;
+      A.flags = sa.flags;
+      A.ntx = sa.ntx;
       A.lt = t;
       return A;
     }
   };
-  // the next tile of this workgroup that belongs to an active instance
-  TileIter it(sa.ntiles, blockIdx.x, gridDim.x);
-  auto next_tile = [&](int t) {
-    if constexpr (BATCH) {
-      while (t >= 0 && !bact[batch_instance(bt0, sa.ninst, t)]) t = it.advance();
-    }
-    return t;
-  };
-  int tile = next_tile(it.get());
+  TileIter it(ntiles, blockIdx.x, gridDim.x);
+  int tile = it.get();
   double pre[kRawPerThread][4];
   if (tile >= 0) {
     const TileArgs A = args(tile);
-    load_raw(A.g, A.Uk, 2 * TX * (A.lt % A.ntx), 2 * TY * (A.lt / A.ntx), tid, pre);
+    load_raw(*A.g, A.Uk, 2 * TX * (A.lt % A.ntx), 2 * TY * (A.lt / A.ntx), tid, pre);
   }
   while (tile >= 0) {
   const TileArgs A = args(tile);
-  const G2& g = A.g;
-  const Phys& phd = A.phd;
+  const G2& g = *A.g;
+  const Phys& phd = *A.phd;
   const PhysT<R> ph = phys_as<R>(phd);
   const double* __restrict__ Uk = A.Uk;
   const double* __restrict__ Un = A.Un;
@@ -616,10 +645,10 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
   __syncthreads();  // the previous tile is done with the LDS; stop is visible
   if (stop) {
     if constexpr (BATCH) {
-      const int nt = next_tile(it.advance());
+      const int nt = it.advance();
       if (nt >= 0) {
         const TileArgs An = args(nt);
-        load_raw(An.g, An.Uk, 2 * TX * (An.lt % An.ntx), 2 * TY * (An.lt / An.ntx), tid, pre);
+        load_raw(*An.g, An.Uk, 2 * TX * (An.lt % An.ntx), 2 * TY * (An.lt / An.ntx), tid, pre);
       }
       tile = nt;
       continue;
@@ -719,10 +748,10 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
 
   // prefetch the next tile's raw values; the loads complete while this tile
   // computes
-  const int next = next_tile(it.advance());
+  const int next = it.advance();
   if (next >= 0) {
     const TileArgs An = args(next);
-    load_raw(An.g, An.Uk, 2 * TX * (An.lt % An.ntx), 2 * TY * (An.lt / An.ntx), tid, pre);
+    load_raw(*An.g, An.Uk, 2 * TX * (An.lt % An.ntx), 2 * TY * (An.lt / An.ntx), tid, pre);
   }
 
   // ---- phase 1: gradients on the block +- 2 ----

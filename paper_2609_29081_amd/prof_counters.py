@@ -3,6 +3,7 @@ from rocprofv3 counters.
 
     python -m paper_2609_29081_amd.prof_counters [--mixed]            # driver (GPU machine)
     python -m paper_2609_29081_amd.prof_counters --target [--mixed]   # profiled program
+    python -m paper_2609_29081_amd.prof_counters --target-batch       # batched sweep
 
 The driver runs three counter passes (FETCH_SIZE; WRITE_SIZE; the FP64 and
 LDS instruction counters) over the target, which launches the stage kernel on the 1000 x 500 shock tube (the
@@ -68,6 +69,26 @@ def target(reps: int = 3, mixed: bool = False) -> None:
     b.copy_(a)
     torch.cuda.synchronize()
     print("target done", flush=True)
+
+
+def target_batch(steps: int = 3) -> None:
+    """the batched form's launches: the 64-instance shock-tube sweep (mixed
+    precision), tuned, then `steps` accepted steps of every instance with
+    HIP-graph replay (for a kernel trace of the batch stage kernel)"""
+    sys.path.insert(0, ROOT)
+    from paper_2609_29081_amd import af
+    from paper_2609_29081_amd import workloads as W
+
+    insts = W.shock_tube_sweep(64, seed=0)
+    solvers = [af.Solver(g, precision=af.PREC_MIXED, cfl_c=0.2, cfl_v=0.075, **kw)
+               for g, f, kw in insts]
+    states = [S.to_device(W.make_state(g, f, kw["gamma"])) for S, (g, f, kw) in zip(solvers, insts)]
+    B = af.Batch(solvers)
+    B.af_batch_tune(states, 0.0, 1e30, reps=1)
+    st, n, t, att = B.af_batch_run(states, 0.0, 1e30, steps, attempts_per_slot=4, use_graph=True)
+    assert st == [af.AF_OK] * len(insts)
+    print("target done: variant", af.stage_variants()[B.variant][0], "attempts", sum(att),
+          flush=True)
 
 
 FP64_COUNTERS = ["SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_ADD_F64",
@@ -176,9 +197,12 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--target", action="store_true")
     ap.add_argument("--mixed", action="store_true")
+    ap.add_argument("--target-batch", action="store_true")
     ap.add_argument("--out", default=os.path.join(ROOT, "gpurun_out", "traffic"))
     a = ap.parse_args()
-    if a.target:
+    if a.target_batch:
+        target_batch()
+    elif a.target:
         target(mixed=a.mixed)
     else:
         driver(a.out, mixed=a.mixed)

@@ -199,6 +199,25 @@ def shock_tube_2d(n1: int = 1000, n2: int = 500, gamma: float = 1.4,
     return g, f
 
 
+def shock_tube_sweep(n: int = 64, seed: int = 0, gamma: float = 1.4,
+                     n1_choices=tuple(range(128, 1025, 64))):
+    """Parameter sweep of viscous shock tubes (the shock tube above with
+    random parameters): for each of n instances, drawn in this order from
+    numpy's default_rng(seed), Re ~ U[200, 1000] (mu = 1/Re), density ratio
+    r ~ U[50, 200] (left rho = 1.2 r, p = rho/gamma; right rho = 1.2,
+    p = 1.2/gamma) and N1 uniform on n1_choices with N2 = N1/2.  Returns a
+    list of (grid, prim_fn, physics keywords) triples."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        re = float(rng.uniform(200.0, 1000.0))
+        ratio = float(rng.uniform(50.0, 200.0))
+        n1 = int(rng.choice(np.asarray(n1_choices)))
+        g, f = shock_tube_2d(n1, n1 // 2, gamma=gamma, rho_left=1.2 * ratio, rho_right=1.2)
+        out.append((g, f, dict(mu=1.0 / re, Pr=0.73, gamma=gamma)))
+    return out
+
+
 def leblanc_1d(n: int = 800):
     """LeBlanc-type near-vacuum Riemann problem on [-0.5,0.5], outflow."""
     g = Grid(dim=1, n1=n, x0=-0.5, x1=0.5, bc=(OUTFLOW, OUTFLOW, OUTFLOW, OUTFLOW))
