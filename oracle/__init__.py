@@ -52,6 +52,12 @@ def lib():
         L.orc_state_len.restype = C.c_long
         L.orc_fe.argtypes = [cp, dp, C.c_double, dp, dp, dp]
         L.orc_fe.restype = C.c_int
+        L.orc_fe_blend.argtypes = [cp, dp, C.c_double, dp, dp, dp, dp]
+        L.orc_fe_blend.restype = C.c_int
+        L.orc_nfaces.argtypes = [cp]
+        L.orc_nfaces.restype = C.c_long
+        L.orc_blend_features.argtypes = [cp, dp, dp]
+        L.orc_blend_features.restype = C.c_int
         L.orc_rhs.argtypes = [cp, dp, dp]
         L.orc_rhs.restype = None
         L.orc_dt.argtypes = [cp, dp]
@@ -114,6 +120,32 @@ def fe(cfg: Cfg, U: np.ndarray, dt: float, want_theta: bool = False):
         return out, fl, ts, tp
     fl = lib().orc_fe(C.byref(cfg), _p(U), dt, _p(out), None, None)
     return out, fl
+
+
+def fe_blend(cfg: Cfg, U: np.ndarray, dt: float, theta_nn: np.ndarray, want_theta: bool = False):
+    """2D forward-Euler stage with a given blend coefficient per face
+    (F = F^L + min(theta_nn, theta_pp) (F^H - F^L)); returns (Ufe, flags) or,
+    with want_theta, also theta^s (1 here) and theta_pp per face"""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    th = np.ascontiguousarray(theta_nn, dtype=np.float64)
+    assert th.shape == (nfaces(cfg),)
+    out = np.empty_like(U)
+    ts = np.empty(nfaces(cfg)) if want_theta else None
+    tp = np.empty(nfaces(cfg)) if want_theta else None
+    fl = lib().orc_fe_blend(C.byref(cfg), _p(U), dt, _p(th), _p(out),
+                            _p(ts) if want_theta else None, _p(tp) if want_theta else None)
+    if fl < 0:
+        raise ValueError("fe_blend needs a 2D config")
+    return (out, fl, ts, tp) if want_theta else (out, fl)
+
+
+def blend_features(cfg: Cfg, U: np.ndarray) -> np.ndarray:
+    """the 40 features of every face (2D), shape (nfaces, 40)"""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    out = np.empty((nfaces(cfg), 40))
+    if lib().orc_blend_features(C.byref(cfg), _p(U), _p(out)) < 0:
+        raise ValueError("blend_features needs a 2D config")
+    return out
 
 
 def rhs(cfg: Cfg, U: np.ndarray) -> np.ndarray:

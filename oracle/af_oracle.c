@@ -1049,8 +1049,11 @@ static void point_xy(int type, int i, int j, int* X, int* Y) {
   }
 }
 
+/* thnn: NULL, or a blend coefficient per face (x-faces, then y-faces) that
+ * replaces theta^s: the face flux is then F^L + min(thnn, theta_pp)(F^H - F^L),
+ * with theta_pp the density/pressure limiter of the unblended high-order flux */
 static int fe2(const orc_cfg* c, const double* U, double dt, double* Ufe, double* ths,
-               double* thpp) {
+               double* thpp, const double* thnn) {
   lat2 Ls, *L = &Ls;
   setup2(L, c, U);
   int n1 = L->n1, n2 = L->n2;
@@ -1188,7 +1191,7 @@ static int fe2(const orc_cfg* c, const double* U, double dt, double* Ufe, double
             ts = 0.0;
             tpp = 0.0;
           } else {
-            if (c->limiter & ORC_LIM_SMOOTH)
+            if ((c->limiter & ORC_LIM_SMOOTH) && !thnn)
               ts = exp(-c->Cs * dmax(ph1[qa], ph1[qb]) * dmax(ph2[qa], ph2[qb]));
             if (c->limiter & ORC_LIM_PP) {
               double Fs[4], ULp[4], UHp[4], ULm[4], UHm[4];
@@ -1220,7 +1223,12 @@ static int fe2(const orc_cfg* c, const double* U, double dt, double* Ufe, double
               if (bad) fl |= ORC_FLAG_CELL_LOW;
             }
           }
+          /* on a periodic axis the last face is the first one again */
+          int fi = (d == 0 && i == n1 && c->bc[0] == ORC_PERIODIC) ? 0 : i;
+          int fj = (d == 1 && j == n2 && c->bc[2] == ORC_PERIODIC) ? 0 : j;
+          long f = (d == 0 ? 0 : nfx) + (long)fj * ni + fi;
           double th = ts * tpp;
+          if (thnn && !(c->limiter & ORC_LIM_LOWONLY)) th = dmin(thnn[f], tpp);
           for (int k = 0; k < 4; ++k) F[k] = FL[k] + th * (FH[k] - FL[k]);
         }
         long fidx = (long)j * ni + i;
@@ -1309,7 +1317,82 @@ long orc_state_len(const orc_cfg* c) {
 
 int orc_fe(const orc_cfg* c, const double* U, double dt, double* Ufe, double* ths,
            double* thpp) {
-  return c->dim == 1 ? fe1(c, U, dt, Ufe, ths, thpp) : fe2(c, U, dt, Ufe, ths, thpp);
+  return c->dim == 1 ? fe1(c, U, dt, Ufe, ths, thpp) : fe2(c, U, dt, Ufe, ths, thpp, NULL);
+}
+
+int orc_fe_blend(const orc_cfg* c, const double* U, double dt, const double* theta_nn,
+                 double* Ufe, double* ths, double* thpp) {
+  if (c->dim != 2 || !theta_nn) return -1;
+  return fe2(c, U, dt, Ufe, ths, thpp, theta_nn);
+}
+
+long orc_nfaces(const orc_cfg* c) {
+  return c->dim == 1 ? c->n1 + 1 : (long)c->n2 * (c->n1 + 1) + (long)(c->n2 + 1) * c->n1;
+}
+
+/* Features of the learned blend coefficient of one face (a reading of the
+ * paper's limiter as a function of local data; the paper has no learned
+ * part).  The face lies between cells a and b; in its frame (normal n along
+ * the face's axis, tangent t along the other axis) the stencil is the 4 x 3
+ * block of cell averages at normal offsets -2, -1 (a), +1 (b), +2 and
+ * tangential offsets -1, 0, +1, ghost cells being the boundary images used by
+ * the stage.  With face values rho_f = (rho_a + rho_b)/2, p_f likewise,
+ * u_nf, u_tf likewise and c_f = sqrt(gamma p_f / rho_f), the 40 features are:
+ * for tangential offset s = -1, 0, +1 and normal offset m = -2, -1, +1, +2,
+ * [ln(p / p_f), (u_n - u_nf) / c_f, (u_t - u_tf) / c_f] (36 values), then
+ * ln(rho / rho_f) for m = -2, -1, +1, +2 at s = 0.  The smoothness blend of
+ * Sec. 3.2 is a function of the same block, through pressure ratios and
+ * velocity gradients relative to a velocity scale. */
+static double pos_or_tiny(double v) { return v > 1e-300 ? v : 1e-300; }
+
+int orc_blend_features(const orc_cfg* c, const double* U, double* feat) {
+  if (c->dim != 2) return -1;
+  lat2 Ls, *L = &Ls;
+  setup2(L, c, U);
+  int n1 = c->n1, n2 = c->n2;
+  long nfx = (long)n2 * (n1 + 1);
+  for (int d = 0; d < 2; ++d) {
+    int ni = d == 0 ? n1 + 1 : n1, nj = d == 0 ? n2 : n2 + 1;
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < nj; ++j)
+      for (int i = 0; i < ni; ++i) {
+        /* primitives (rho, u_n, u_t, p) of the cell at normal offset m and
+           tangential offset s; cell a is m = -1, cell b is m = +1 */
+        double P[3][4][4];
+        const int moff[4] = {-2, -1, 1, 2};
+        for (int s = 0; s < 3; ++s)
+          for (int q = 0; q < 4; ++q) {
+            int m = moff[q];
+            int nidx = (d == 0 ? i : j) + (m < 0 ? m : m - 1);
+            int ci = d == 0 ? nidx : i + (s - 1);
+            int cj = d == 0 ? j + (s - 1) : nidx;
+            double Uc[4], W[4];
+            for (int k = 0; k < 4; ++k) Uc[k] = C2(k, ci, cj);
+            prim(c, Uc, W);
+            P[s][q][0] = Uc[0];
+            P[s][q][1] = d == 0 ? W[1] : W[2];
+            P[s][q][2] = d == 0 ? W[2] : W[1];
+            P[s][q][3] = W[3];
+          }
+        double rf = 0.5 * (P[1][1][0] + P[1][2][0]);
+        double pf = 0.5 * (P[1][1][3] + P[1][2][3]);
+        double unf = 0.5 * (P[1][1][1] + P[1][2][1]);
+        double utf = 0.5 * (P[1][1][2] + P[1][2][2]);
+        double cf = sqrt(c->gamma * pos_or_tiny(pf) / pos_or_tiny(rf));
+        long f = (d == 0 ? 0 : nfx) + (long)j * ni + i;
+        double* o = feat + 40 * f;
+        int n = 0;
+        for (int s = 0; s < 3; ++s)
+          for (int q = 0; q < 4; ++q) {
+            o[n++] = log(pos_or_tiny(P[s][q][3]) / pos_or_tiny(pf));
+            o[n++] = (P[s][q][1] - unf) / cf;
+            o[n++] = (P[s][q][2] - utf) / cf;
+          }
+        for (int q = 0; q < 4; ++q) o[n++] = log(pos_or_tiny(P[1][q][0]) / pos_or_tiny(rf));
+      }
+  }
+  free2(L);
+  return 0;
 }
 
 void orc_rhs(const orc_cfg* c, const double* U, double* dUdt) {

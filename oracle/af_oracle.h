@@ -68,6 +68,25 @@ long orc_state_len(const orc_cfg* c);
 int orc_fe(const orc_cfg* c, const double* U, double dt, double* Ufe,
            double* theta_s_out, double* theta_pp_out);
 
+/* 2D forward-Euler stage whose cell-average fluxes use a given blend
+ * coefficient per face instead of the smoothness blend theta^s:
+ * F = F^L + min(theta_nn, theta_pp) (F^H - F^L), theta_pp being the density/
+ * pressure limiter of the unblended high-order flux (so every coefficient
+ * used is admissible).  theta_nn has orc_nfaces() entries: x-faces [n2][n1+1]
+ * then y-faces [n2+1][n1]; on a periodic axis the last face of a line is the
+ * first one again and takes its entry.  Returns the flags, or -1 for a 1D
+ * config. */
+int orc_fe_blend(const orc_cfg* c, const double* U, double dt, const double* theta_nn,
+                 double* Ufe, double* theta_s_out, double* theta_pp_out);
+
+/* faces of the grid: 1D n1+1; 2D x-faces n2*(n1+1) plus y-faces (n2+1)*n1 */
+long orc_nfaces(const orc_cfg* c);
+
+/* 2D: the 40 features of the learned blend coefficient of every face
+ * (feat[face][40], faces ordered as above); see the .c file for their
+ * definition.  Returns -1 for a 1D config. */
+int orc_blend_features(const orc_cfg* c, const double* U, double* feat);
+
 /* unlimited semi-discrete right-hand side dU/dt (cell averages and points) */
 void orc_rhs(const orc_cfg* c, const double* U, double* dUdt);
 

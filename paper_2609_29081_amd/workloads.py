@@ -218,6 +218,21 @@ def shock_tube_sweep(n: int = 64, seed: int = 0, gamma: float = 1.4,
     return out
 
 
+def mlp_init(seed: int = 0, nin: int = 40, nh: int = 64) -> np.ndarray:
+    """Seeded initial parameters of the blend network (nin -> nh -> nh -> 1),
+    as one float32 vector [W1 (nh x nin, row-major), b1, W2 (nh x nh), b2,
+    w3 (nh), b3]: Glorot-uniform weights from numpy's default_rng(seed),
+    zero hidden biases, output bias 1/2."""
+    rng = np.random.default_rng(seed)
+
+    def glorot(fan_out, fan_in):
+        a = np.sqrt(6.0 / (fan_in + fan_out))
+        return rng.uniform(-a, a, size=(fan_out, fan_in))
+    parts = [glorot(nh, nin).ravel(), np.zeros(nh), glorot(nh, nh).ravel(), np.zeros(nh),
+             glorot(1, nh).ravel(), np.array([0.5])]
+    return np.concatenate(parts).astype(np.float32)
+
+
 def leblanc_1d(n: int = 800):
     """LeBlanc-type near-vacuum Riemann problem on [-0.5,0.5], outflow."""
     g = Grid(dim=1, n1=n, x0=-0.5, x1=0.5, bc=(OUTFLOW, OUTFLOW, OUTFLOW, OUTFLOW))
