@@ -85,6 +85,10 @@ def main() -> int:
                     help="instances of the batched shock-tube sweep")
     ap.add_argument("--batch-steps", type=int, default=100,
                     help="accepted steps per instance of the batched sweep")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-blend form")
+    ap.add_argument("--learned-train-steps", type=int, default=3000,
+                    help="Adam steps of the learned blend's training")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -273,6 +277,8 @@ def main() -> int:
                                         "fp64": round(f64 / stage_s_m / 1e12, 2)}})
     if not args.no_batched:
         forms["batched"] = batched_form(args, stream)
+    if not args.no_learned:
+        forms["learned"] = learned_form(args, stream)
     out = {
         "metric": METRIC, "value": value, "unit": "DOF-updates/s", "n_gpus": 1, "steps": K,
         "warmup": Wm, "ms_per_step": gpu_ms / K, "higher_is_better": True, "scaling": "weak",
@@ -298,6 +304,113 @@ def main() -> int:
     }
     print(json.dumps(out))
     return 0
+
+
+def learned_form(args, stream) -> dict:
+    """The learned-blend form.  Training data: features and theta^s of every
+    face of the 1000 x 500 shock tube (FP64, plain limiter) after steps 1,
+    2, 3, 5, 10, 20 and 50 (7.0 M faces; the first steps, where the
+    diaphragm's jump turns into a viscous shock, are where the blend acts
+    most; a tenth held out, the rest balanced by workloads.balanced_rows); training: Adam (lr 2e-3, minibatches of 1024)
+    from the seeded initial weights.  Evaluation on the 2048 x 1024 shock tube
+    (FP64, Re = 200) from t = 0 to t = 1e-4: the plain limiter, the learned
+    blend (AF_LIM_LEARNED: the network's theta_nn in place of theta^s, then
+    the density/pressure limiter), the untrained network, and no smoothness
+    blend at all (theta^s = 1).  Each run is
+    timed with HIP events; value = DOF sites x 3 x accepted steps / second.
+    The plain limiter judges the error: L1 = sum |rho - rho_plain| dx dy of
+    the cell averages at t = 1e-4."""
+    import numpy as np
+    import torch
+
+    from paper_2609_29081_amd import af
+    from paper_2609_29081_amd import workloads as W
+
+    gamma = 1.4
+    kw = dict(gamma=gamma, mu=0.005, Pr=0.73, cfl_c=0.2, cfl_v=0.075)
+    dev = torch.device("cuda:0")
+    print("bench: learned blend, training data", file=sys.stderr, flush=True)
+    g3, f3 = W.shock_tube_2d(1000, 500, gamma=gamma)
+    S3 = af.Solver(g3, limiter=af.LIM_ALL, **kw)
+    U = S3.to_device(W.make_state(g3, f3, gamma))
+    Xs, ys, done = [], [], 0
+    tmp = torch.empty_like(U)
+    for target in (1, 2, 3, 5, 10, 20, 50):
+        st, n, _ = S3.af_run(U, 0.0, 1e30, target - done, check_every=1)
+        if st != af.AF_OK:
+            raise RuntimeError(f"training-data run failed: {st}")
+        done = target
+        Xs.append(S3.af_blend_features(U))
+        ts = torch.empty(S3.face_count, dtype=torch.float32, device=dev)
+        S3.af_rk_stage_blend(0, None, U, tmp, dt=0.0, theta_s_out=ts)
+        ys.append(ts)
+    X, y = torch.cat(Xs), torch.cat(ys)
+    # a held-out tenth of the faces; the training rows are every face of the
+    # rest where theta^s < 0.999 and three times as many of the others
+    perm = torch.randperm(X.shape[0], generator=torch.Generator().manual_seed(0)).to(dev)
+    X, y = X[perm].contiguous(), y[perm].contiguous()
+    nhold = X.shape[0] // 10
+    Xh, yh = X[:nhold], y[:nhold]
+    idx = torch.as_tensor(W.balanced_rows(y[nhold:].cpu().numpy(), seed=0), device=dev) + nhold
+    Xt, yt = X[idx].contiguous(), y[idx].contiguous()
+    P0 = torch.as_tensor(W.mlp_init(0), device=dev)
+    P = P0.clone()
+    m, v = torch.zeros_like(P), torch.zeros_like(P)
+    _, l0 = af.mlp_grad(Xh, yh, P)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    af.mlp_train(Xt, yt, P, m, v, 0, args.learned_train_steps, 1024, 2e-3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    _, l1 = af.mlp_grad(Xh, yh, P)
+    frac_lt1 = float((yh < 0.999).float().mean().item())
+    low = torch.nonzero(yh < 0.999).flatten()
+    _, l_low = af.mlp_grad(Xh[low].contiguous(), yh[low].contiguous(), P)
+    rmse_low = float(l_low.item()) ** 0.5
+    rmse_one = float(((1.0 - yh[low]) ** 2).mean().item()) ** 0.5
+
+    print("bench: learned blend, 2048x1024 runs", file=sys.stderr, flush=True)
+    g5, f5 = W.shock_tube_2d(2048, 1024, gamma=gamma)
+    U5 = W.make_state(g5, f5, gamma)
+    t_final = 1e-4
+    runs = {}
+    for name, lim, net in (("plain", af.LIM_ALL, None),
+                           ("learned", af.LIM_ALL | af.LIM_LEARNED, P),
+                           ("untrained", af.LIM_ALL | af.LIM_LEARNED, P0),
+                           ("no_smoothness", af.LIM_PP | af.LIM_POINT | af.LIM_CENTRE, None)):
+        S = af.Solver(g5, limiter=lim, **kw)
+        if net is not None:
+            S.af_set_blend_net(net)
+        Ud = S.to_device(U5)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        st, n, t = S.af_run(Ud, 0.0, t_final, 10 ** 6, check_every=1)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if st != af.AF_OK:
+            raise RuntimeError(f"{name} run failed: {st}")
+        ms = e0.elapsed_time(e1)
+        runs[name] = (g5.split(Ud.cpu().numpy())["avg"][0], n, ms)
+        del S, Ud
+    rho_plain = runs["plain"][0]
+    out = {"workload": "2D viscous shock tube 2048x1024 (Re=200, FP64) from t=0 to t=1e-4; "
+                       "network trained on theta^s of the 1000x500 tube after steps "
+                       "1, 2, 3, 5, 10, 20, 50",
+           "train": {"samples": int(Xt.shape[0]), "held_out": nhold, "steps": args.learned_train_steps,
+                     "batch": 1024, "lr": 2e-3, "seconds": round(train_s, 2),
+                     "loss_held_out_before": float(l0.item()),
+                     "loss_held_out_after": float(l1.item()),
+                     "fraction_theta_s_below_1": round(frac_lt1, 4),
+                     "rmse_held_out_where_theta_s_below_1": round(rmse_low, 5),
+                     "rmse_of_constant_1_there": round(rmse_one, 5)}}
+    for name, (rho, n, ms) in runs.items():
+        out[name] = {"value": g5.dof_sites * 3 * n / (ms / 1e3), "unit": "DOF-updates/s",
+                     "steps": n, "ms": round(ms, 1),
+                     "l1_rho_vs_plain": float(np.abs(rho - rho_plain).sum() * g5.dx * g5.dy)}
+    out["value"] = out["learned"]["value"]
+    return out
 
 
 def batched_form(args, stream) -> dict:

@@ -66,7 +66,18 @@ enum {
   /* diagnostic: the low-order schemes alone (blend parameters 0): LLF cell
      fluxes (Sec. 3.1) and, together with AF_LIM_POINT, the low-order point
      values (Sec. 3.4) */
-  AF_LIM_LOWONLY = 16
+  AF_LIM_LOWONLY = 16,
+  /* 2D: the learned blend.  The smoothness blend theta^s of the cell fluxes
+     (Sec. 3.2) is replaced by a small network's proposal theta_nn per face,
+     computed from the stage input's cell averages (af_blend_infer, with the
+     network set by af_set_blend_net).  The density/pressure blend then acts
+     on the candidate F^L + theta_nn (F^H - F^L) exactly as it acts on the
+     smoothness-blended one: F = F^L + theta_nn theta^rho theta^p (F^H - F^L)
+     with AF_LIM_PP, so the coefficient never exceeds theta_nn nor the
+     admissible bound (Sec. 3.3), and positivity and conservation are as in
+     the plain method; theta_nn = theta^s gives the plain stage.
+     AF_LIM_SMOOTH is ignored. */
+  AF_LIM_LEARNED = 32
 };
 
 /* sticky status flags accumulated in the workspace by af_rk_stage */
@@ -184,7 +195,8 @@ enum {
   AF_K_POINTS = 5,   /* 1D: point-value update                          */
   AF_K_CFL = 6,      /* time-step reduction                             */
   AF_K_STAGE2D = 7,  /* 2D: the fused stage kernel                      */
-  AF_K_COUNT = 8
+  AF_K_BLEND = 8,    /* 2D: the learned blend's features and network   */
+  AF_K_COUNT = 9
 };
 af_status af_timing(af_ctx* ctx, int enable);
 af_status af_timing_read(af_ctx* ctx, long* launches, double* ms);
@@ -241,6 +253,73 @@ af_status af_batch_set_variant(af_batch* b, int i);
  * of each variant in microseconds, -1 for variants of the other precision. */
 af_status af_batch_tune(af_batch* b, double* const* U, void* ws, void* stream, double t0,
                         double t_final, int reps, double* us_per_slot);
+
+/* ---- the learned blend coefficient (2D; AF_LIM_LEARNED) ----
+ *
+ * Faces are numbered x-faces first, [n2][n1+1] (face (i, j) at x = x0 +
+ * i dx between cells i-1 and i of row j), then y-faces, [n2+1][n1].  On a
+ * periodic axis the last face of a line is the first one again: stages read
+ * the first one's entry.
+ *
+ * The network is 40 -> 64 -> 64 -> 1 with tanh hidden units:
+ * h1 = tanh(W1 x + b1), h2 = tanh(W2 h1 + b2), z = w3.h2 + b3,
+ * theta_nn = min(max(z, 0), 1).  Its parameters are one device array of
+ * af_mlp_param_count() floats: [W1 (64 x 40, row-major W1[o][i]), b1 (64),
+ * W2 (64 x 64), b2 (64), w3 (64), b3].  Inference stores W1, W2, w3 and the
+ * layer inputs in bfloat16 and accumulates in FP32 on the matrix cores.
+ *
+ * Features of a face (40 floats), in the face's frame (normal n along its
+ * axis, tangent t along the other): the 4 x 3 block of cell averages at
+ * normal offsets -2, -1, +1, +2 (cells -1 and +1 adjoin the face) and
+ * tangential offsets -1, 0, +1, ghost cells being the stage's boundary
+ * images.  With rho_f, p_f, u_nf, u_tf the means over the two adjoining
+ * cells and c_f = sqrt(gamma p_f / rho_f): for s = -1, 0, +1 and
+ * m = -2, -1, +1, +2 the triple ln(p/p_f), (u_n - u_nf)/c_f,
+ * (u_t - u_tf)/c_f; then ln(rho/rho_f) for m = -2, -1, +1, +2 at s = 0. */
+long af_face_count(const af_ctx* ctx);
+size_t af_mlp_param_count(void);
+
+/* Features of every face of the device state U into feat (af_face_count x
+ * 40 floats, device), asynchronous. */
+af_status af_blend_features(af_ctx* ctx, const double* U, float* feat, void* stream);
+
+/* The network of the learned blend: a device array of af_mlp_param_count()
+ * floats owned by the caller, read at every later inference (it must stay
+ * valid while the context uses AF_LIM_LEARNED); NULL clears it. */
+af_status af_set_blend_net(af_ctx* ctx, const float* params);
+
+/* theta_nn of every face of U into theta (af_face_count floats, device),
+ * asynchronous; uses the workspace for the packed weights. */
+af_status af_blend_infer(af_ctx* ctx, const double* U, float* theta, void* ws, void* stream);
+
+/* af_rk_stage (2D) with explicit blend arrays: theta (af_face_count floats,
+ * values in [0, 1]) takes the place of theta^s as under AF_LIM_LEARNED, or
+ * NULL for the context's own rule; theta_s_out, if not NULL, receives the
+ * coefficient that took theta^s's place at every face: theta^s itself for
+ * a plain stage (the training targets of the learned blend), theta where it
+ * is given, 1 with the smoothness blend off, 0 under AF_LIM_LOWONLY. */
+af_status af_rk_stage_blend(af_ctx* ctx, int k, const double* dt_dev, double dt_host,
+                            const double* Un, const double* Uk, double* Uout,
+                            const float* theta, float* theta_s_out, void* ws, void* stream);
+
+/* Training.  af_mlp_grad: mean of (z - y)^2 over the n rows of X (n x 40
+ * floats) and targets y, its gradient (af_mlp_param_count floats) and the
+ * loss (one float; may be NULL), all device arrays, asynchronous, FP32 and
+ * deterministic; gws is a device scratch array of
+ * af_mlp_grad_workspace_bytes(n) bytes.  af_mlp_adam: one Adam update
+ * (beta1 0.9, beta2 0.999, eps 1e-8, step counted from 1) of params with
+ * moment arrays m and v.  af_mlp_train: `steps` minibatches of `batch` rows
+ * taken in order (wrapping around the n rows), gradient and Adam each,
+ * steps counted from step0 + 1; *loss_out (device, may be NULL) receives the
+ * last minibatch's loss. */
+size_t af_mlp_grad_workspace_bytes(long n);
+af_status af_mlp_grad(const float* X, const float* y, long n, const float* params, float* grad,
+                      float* loss, void* gws, void* stream);
+af_status af_mlp_adam(float* params, const float* grad, float* m, float* v, long step, float lr,
+                      void* stream);
+af_status af_mlp_train(const float* X, const float* y, long n, float* params, float* grad,
+                       float* m, float* v, long step0, int steps, int batch, float lr,
+                       float* loss_out, void* gws, void* stream);
 
 const char* af_last_error(void);
 

@@ -123,9 +123,10 @@ def fe(cfg: Cfg, U: np.ndarray, dt: float, want_theta: bool = False):
 
 
 def fe_blend(cfg: Cfg, U: np.ndarray, dt: float, theta_nn: np.ndarray, want_theta: bool = False):
-    """2D forward-Euler stage with a given blend coefficient per face
-    (F = F^L + min(theta_nn, theta_pp) (F^H - F^L)); returns (Ufe, flags) or,
-    with want_theta, also theta^s (1 here) and theta_pp per face"""
+    """2D forward-Euler stage with a given blend coefficient per face in
+    place of theta^s (F = F^L + theta_nn theta^rho theta^p (F^H - F^L));
+    returns (Ufe, flags) or, with want_theta, also the coefficient used in
+    theta^s's place and theta^rho theta^p per face"""
     U = np.ascontiguousarray(U, dtype=np.float64)
     th = np.ascontiguousarray(theta_nn, dtype=np.float64)
     assert th.shape == (nfaces(cfg),)

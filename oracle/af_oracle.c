@@ -1050,8 +1050,9 @@ static void point_xy(int type, int i, int j, int* X, int* Y) {
 }
 
 /* thnn: NULL, or a blend coefficient per face (x-faces, then y-faces) that
- * replaces theta^s: the face flux is then F^L + min(thnn, theta_pp)(F^H - F^L),
- * with theta_pp the density/pressure limiter of the unblended high-order flux */
+ * takes the place of theta^s: the density/pressure limiter of Sec. 3.3 then
+ * acts on the candidate F^L + thnn (F^H - F^L), so the face flux is
+ * F^L + thnn theta^rho theta^p (F^H - F^L) */
 static int fe2(const orc_cfg* c, const double* U, double dt, double* Ufe, double* ths,
                double* thpp, const double* thnn) {
   lat2 Ls, *L = &Ls;
@@ -1059,7 +1060,7 @@ static int fe2(const orc_cfg* c, const double* U, double dt, double* Ufe, double
   int n1 = L->n1, n2 = L->n2;
   double dx = L->dx, dy = L->dy;
   int flags = 0;
-  int lim_cell = c->limiter & (ORC_LIM_SMOOTH | ORC_LIM_PP | ORC_LIM_LOWONLY);
+  int lim_cell = (c->limiter & (ORC_LIM_SMOOTH | ORC_LIM_PP | ORC_LIM_LOWONLY)) || thnn;
 
   /* ---- point values ---- */
   double* outp[3];
@@ -1191,8 +1192,14 @@ static int fe2(const orc_cfg* c, const double* U, double dt, double* Ufe, double
             ts = 0.0;
             tpp = 0.0;
           } else {
-            if ((c->limiter & ORC_LIM_SMOOTH) && !thnn)
+            if (thnn) {
+              /* on a periodic axis the last face is the first one again */
+              int fi = (d == 0 && i == n1 && c->bc[0] == ORC_PERIODIC) ? 0 : i;
+              int fj = (d == 1 && j == n2 && c->bc[2] == ORC_PERIODIC) ? 0 : j;
+              ts = thnn[(d == 0 ? 0 : nfx) + (long)fj * ni + fi];
+            } else if (c->limiter & ORC_LIM_SMOOTH) {
               ts = exp(-c->Cs * dmax(ph1[qa], ph1[qb]) * dmax(ph2[qa], ph2[qb]));
+            }
             if (c->limiter & ORC_LIM_PP) {
               double Fs[4], ULp[4], UHp[4], ULm[4], UHm[4];
               for (int k = 0; k < 4; ++k) {
@@ -1223,12 +1230,7 @@ static int fe2(const orc_cfg* c, const double* U, double dt, double* Ufe, double
               if (bad) fl |= ORC_FLAG_CELL_LOW;
             }
           }
-          /* on a periodic axis the last face is the first one again */
-          int fi = (d == 0 && i == n1 && c->bc[0] == ORC_PERIODIC) ? 0 : i;
-          int fj = (d == 1 && j == n2 && c->bc[2] == ORC_PERIODIC) ? 0 : j;
-          long f = (d == 0 ? 0 : nfx) + (long)fj * ni + fi;
           double th = ts * tpp;
-          if (thnn && !(c->limiter & ORC_LIM_LOWONLY)) th = dmin(thnn[f], tpp);
           for (int k = 0; k < 4; ++k) F[k] = FL[k] + th * (FH[k] - FL[k]);
         }
         long fidx = (long)j * ni + i;

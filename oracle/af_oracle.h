@@ -69,10 +69,11 @@ int orc_fe(const orc_cfg* c, const double* U, double dt, double* Ufe,
            double* theta_s_out, double* theta_pp_out);
 
 /* 2D forward-Euler stage whose cell-average fluxes use a given blend
- * coefficient per face instead of the smoothness blend theta^s:
- * F = F^L + min(theta_nn, theta_pp) (F^H - F^L), theta_pp being the density/
- * pressure limiter of the unblended high-order flux (so every coefficient
- * used is admissible).  theta_nn has orc_nfaces() entries: x-faces [n2][n1+1]
+ * coefficient per face in place of the smoothness blend theta^s: the
+ * density/pressure limiter (Sec. 3.3) acts on the candidate
+ * F^L + theta_nn (F^H - F^L), so F = F^L + theta_nn theta^rho theta^p
+ * (F^H - F^L), never above theta_nn and always admissible.  With theta_nn =
+ * theta^s this is the plain stage.  theta_nn has orc_nfaces() entries: x-faces [n2][n1+1]
  * then y-faces [n2+1][n1]; on a periodic axis the last face of a line is the
  * first one again and takes its entry.  Returns the flags, or -1 for a 1D
  * config. */

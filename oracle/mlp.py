@@ -7,8 +7,8 @@ The learned limiter is not in the paper: it is a small multilayer perceptron
 that proposes the blend coefficient of a face's cell-average flux (the role
 the smoothness indicator of Sec. 3.2 plays), trained on the method's own
 theta^s, and always clamped by the density/pressure limiter of Sec. 3.3
-(theta = min(theta_nn, theta_pp)), which keeps the admissibility argument of
-Sec. 3.3 intact.  This module is that network written out in numpy:
+exactly as theta^s is, which keeps the admissibility argument of Sec. 3.3
+intact.  This module is that network written out in numpy:
 
   h1 = tanh(W1 x + b1)      W1: 64 x 40
   h2 = tanh(W2 h1 + b2)     W2: 64 x 64

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libaf.so")
 
 AF_OK, AF_E_ARG, AF_E_HIP, AF_E_PP, AF_E_NONFINITE = 0, 1, 2, 3, 4
 PERIODIC, OUTFLOW, NOSLIP, SYMMETRY = 0, 1, 2, 3
-LIM_SMOOTH, LIM_PP, LIM_POINT, LIM_CENTRE, LIM_LOWONLY = 1, 2, 4, 8, 16
+LIM_SMOOTH, LIM_PP, LIM_POINT, LIM_CENTRE, LIM_LOWONLY, LIM_LEARNED = 1, 2, 4, 8, 16, 32
 LIM_ALL = 15
 PREC_FP64, PREC_MIXED = 0, 1
 FLAG_CELL_LOW, FLAG_POINT_LOW, FLAG_NONFINITE = 1, 2, 4
@@ -46,12 +46,14 @@ EXPORTS = ["af_default_params", "af_init_grid", "af_destroy", "af_set_bc", "af_s
            "af_read_flags", "af_reset_flags", "af_timing", "af_timing_read", "af_last_error",
            "af_batch_create", "af_batch_destroy", "af_batch_workspace_bytes", "af_batch_run",
            "af_stage_variant_count", "af_stage_variant_info", "af_batch_variant",
-           "af_batch_set_variant", "af_batch_tune"]
+           "af_batch_set_variant", "af_batch_tune", "af_face_count", "af_mlp_param_count",
+           "af_blend_features", "af_set_blend_net", "af_blend_infer", "af_rk_stage_blend",
+           "af_mlp_grad_workspace_bytes", "af_mlp_grad", "af_mlp_adam", "af_mlp_train"]
 
 # kernel kinds reported by af_timing_read
 KERNEL_KINDS = {0: "lattice", 1: "grad", 2: "cellpre", 3: "face", 4: "cells", 5: "points",
-                6: "cfl", 7: "stage2d"}
-K_COUNT = 8
+                6: "cfl", 7: "stage2d", 8: "blend"}
+K_COUNT = 9
 
 
 def lib():
@@ -82,6 +84,21 @@ def lib():
         L.af_batch_destroy.restype = None
         L.af_batch_workspace_bytes.argtypes = [vp]
         L.af_batch_workspace_bytes.restype = C.c_size_t
+        fp = C.POINTER(C.c_float)
+        L.af_face_count.argtypes = [vp]
+        L.af_face_count.restype = C.c_long
+        L.af_mlp_param_count.argtypes = []
+        L.af_mlp_param_count.restype = C.c_size_t
+        L.af_blend_features.argtypes = [vp, vp, vp, vp]
+        L.af_set_blend_net.argtypes = [vp, vp]
+        L.af_blend_infer.argtypes = [vp, vp, vp, vp, vp]
+        L.af_rk_stage_blend.argtypes = [vp, ip, vp, C.c_double, vp, vp, vp, vp, vp, vp, vp]
+        L.af_mlp_grad_workspace_bytes.argtypes = [C.c_long]
+        L.af_mlp_grad_workspace_bytes.restype = C.c_size_t
+        L.af_mlp_grad.argtypes = [vp, vp, C.c_long, vp, vp, vp, vp, vp]
+        L.af_mlp_adam.argtypes = [vp, vp, vp, vp, C.c_long, C.c_float, vp]
+        L.af_mlp_train.argtypes = [vp, vp, C.c_long, vp, vp, vp, vp, C.c_long, ip, ip, C.c_float,
+                                   vp, vp, vp]
         L.af_stage_variant_count.argtypes = []
         L.af_stage_variant_info.argtypes = [ip, C.POINTER(C.c_char_p), C.POINTER(ip),
                                             C.POINTER(ip)]
@@ -229,6 +246,38 @@ class Solver:
                                          C.byref(n)))
         return n.value
 
+    # -- the learned blend (2D) --------------------------------------------
+    @property
+    def face_count(self) -> int:
+        return int(lib().af_face_count(self.ctx))
+
+    def af_blend_features(self, U, stream=None) -> torch.Tensor:
+        """(faces, 40) float32 features of the device state U"""
+        out = torch.empty((self.face_count, 40), dtype=torch.float32, device=self.device)
+        _check(lib().af_blend_features(self.ctx, _ptr(U), _ptr(out), _stream(stream)))
+        return out
+
+    def af_set_blend_net(self, params):
+        """the network (af_mlp_param_count float32 values on the device); the
+        solver keeps a reference to it"""
+        if params is not None:
+            params = params.contiguous()
+            if params.dtype != torch.float32 or params.numel() != mlp_param_count():
+                raise ValueError("params: float32 tensor of af_mlp_param_count values")
+        self.net = params
+        _check(lib().af_set_blend_net(self.ctx, _ptr(params)))
+
+    def af_blend_infer(self, U, stream=None) -> torch.Tensor:
+        out = torch.empty(self.face_count, dtype=torch.float32, device=self.device)
+        _check(lib().af_blend_infer(self.ctx, _ptr(U), _ptr(out), _ptr(self.ws), _stream(stream)))
+        return out
+
+    def af_rk_stage_blend(self, k: int, Un, Uk, Uout, dt: float | None = None, dt_dev=None,
+                          theta=None, theta_s_out=None, stream=None):
+        _check(lib().af_rk_stage_blend(self.ctx, k, _ptr(dt_dev), 0.0 if dt is None else float(dt),
+                                       _ptr(Un), _ptr(Uk), _ptr(Uout), _ptr(theta),
+                                       _ptr(theta_s_out), _ptr(self.ws), _stream(stream)))
+
     def af_timing(self, enable: bool):
         _check(lib().af_timing(self.ctx, 1 if enable else 0))
 
@@ -238,6 +287,44 @@ class Solver:
         ms = (C.c_double * K_COUNT)()
         _check(lib().af_timing_read(self.ctx, n, ms))
         return {KERNEL_KINDS.get(k, f"k{k}"): (n[k], ms[k]) for k in range(K_COUNT) if n[k]}
+
+
+def mlp_param_count() -> int:
+    return int(lib().af_mlp_param_count())
+
+
+def _grad_ws(n: int, device) -> torch.Tensor:
+    nb = int(lib().af_mlp_grad_workspace_bytes(n))
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+def mlp_grad(X, y, params, stream=None):
+    """(gradient, loss) of the mean squared error of the network on rows X
+    (n x 40 float32) against y (n), all on the device"""
+    n = X.shape[0]
+    grad = torch.empty_like(params)
+    loss = torch.empty(1, dtype=torch.float32, device=params.device)
+    gws = _grad_ws(n, params.device)
+    _check(lib().af_mlp_grad(_ptr(X), _ptr(y), n, _ptr(params), _ptr(grad), _ptr(loss), _ptr(gws),
+                             _stream(stream)))
+    return grad, loss
+
+
+def mlp_adam(params, grad, m, v, step: int, lr: float, stream=None):
+    _check(lib().af_mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), step, lr,
+                             _stream(stream)))
+
+
+def mlp_train(X, y, params, m, v, step0: int, steps: int, batch: int, lr: float, stream=None):
+    """`steps` Adam steps over minibatches of X, y in order; returns the last
+    minibatch's loss (a device tensor)"""
+    n = X.shape[0]
+    grad = torch.empty_like(params)
+    loss = torch.empty(1, dtype=torch.float32, device=params.device)
+    gws = _grad_ws(min(n, batch), params.device)
+    _check(lib().af_mlp_train(_ptr(X), _ptr(y), n, _ptr(params), _ptr(grad), _ptr(m), _ptr(v),
+                              step0, steps, batch, lr, _ptr(loss), _ptr(gws), _stream(stream)))
+    return loss
 
 
 def stage_variants() -> list:

@@ -20,7 +20,8 @@ STAGE_VARIANTS = [("stage2d_fp64_t7", "double", 7), ("stage2d_fp64_t5", "double"
 SOURCES = [("af_capi.cpp", "af_capi.o", []),
            ("af_variants.cpp", "af_variants.o", ["--cuda-host-only"]),
            ("af_common.hip", "af_common.o", []),
-           ("af_kern1d.hip", "af_kern1d.o", [])] + [
+           ("af_kern1d.hip", "af_kern1d.o", []),
+           ("af_learn.hip", "af_learn.o", [])] + [
     ("af_stage2d.hip", f"{name}.o",
      [f"-DAF_STAGE_REAL={real}", f"-DAF_STAGE_TY={ty}", f"-DAF_STAGE_ENTRY={name}"])
     for name, real, ty in STAGE_VARIANTS]

@@ -63,6 +63,7 @@ struct af_ctx {
   af_params p;
   int bc[4];
   EventTimer* timer = nullptr;
+  const float* net = nullptr;  // learned-blend network parameters (device), or NULL
 };
 
 struct af_batch {
@@ -99,6 +100,25 @@ af_status hip_fail(hipError_t e, const char* where) {
     hipError_t e_ = (call);                            \
     if (e_ != hipSuccess) return hip_fail(e_, #call);  \
   } while (0)
+
+bool geometry(const af_ctx* c, afi::Geo* g);
+
+// a context under AF_LIM_LEARNED needs its network
+bool net_ready(const af_ctx* c) {
+  if ((c->p.limiter & AF_LIM_LEARNED) && !c->net) {
+    fail(AF_E_ARG, "AF_LIM_LEARNED: no network set (af_set_blend_net)");
+    return false;
+  }
+  return true;
+}
+
+// the workspace carve-up of a context, with its network pointer
+afi::Work work_of(const af_ctx* c, const afi::Geo& g, const void* ws) {
+  afi::Work w;
+  afi::workspace_layout(g, &w, (char*)const_cast<void*>(ws));
+  w.net = c->net;
+  return w;
+}
 
 bool geometry(const af_ctx* c, afi::Geo* g) {
   const af_params& p = c->p;
@@ -158,6 +178,14 @@ hipError_t launch_stage(const afi::Geo& g, const afd::Phys& ph, const afi::Work&
   if (!Un) Un = Uk;
   afi::StageCoef sc = kCoef[k];
   sc.skip_flagged = in_step ? 1 : 0;
+  if (g.dim == 2 && (ph.lim & afd::LIM_LEARNED)) {
+    // the network's blend from this stage's input, then the stage
+    if (!w.net) return hipErrorInvalidValue;
+    hipError_t e;
+    if ((e = afi::mlp_pack(w.net, w.mlp, s)) != hipSuccess) return e;
+    if ((e = afi::blend_infer(g, ph, Uk, w.mlp, w.blend, s, tm)) != hipSuccess) return e;
+    sc.blend = w.blend;
+  }
   return g.dim == 1 ? afi::stage1d(g, ph, w, Un, Uk, Uout, dt_dev, dt_host, sc, s, tm)
                     : afi::stage2d(g, ph, w, Un, Uk, Uout, dt_dev, dt_host, sc, s, tm);
 }
@@ -280,7 +308,9 @@ af_status af_init_grid(const af_params* p, af_ctx** out) {
   if (!(p->Pr > 0.0)) return fail(AF_E_ARG, "Pr must be > 0");
   if (!(p->cfl_c > 0.0) || !(p->cfl_v > 0.0)) return fail(AF_E_ARG, "CFL numbers must be > 0");
   if (!(p->Cs >= 0.0)) return fail(AF_E_ARG, "Cs must be >= 0");
-  if (p->limiter < 0 || p->limiter > 31) return fail(AF_E_ARG, "bad limiter bits");
+  if (p->limiter < 0 || p->limiter > 63) return fail(AF_E_ARG, "bad limiter bits");
+  if ((p->limiter & AF_LIM_LEARNED) && p->dim != 2)
+    return fail(AF_E_ARG, "the learned blend exists for 2D only");
   if (p->max_halvings < 0) return fail(AF_E_ARG, "max_halvings must be >= 0");
   if (p->precision != AF_PREC_FP64 && p->precision != AF_PREC_MIXED)
     return fail(AF_E_ARG, "precision must be AF_PREC_FP64 or AF_PREC_MIXED");
@@ -376,8 +406,7 @@ af_status af_check_admissible(af_ctx* c, const double* U, void* ws, void* stream
   if (!c || !U || !ws || !count) return fail(AF_E_ARG, "af_check_admissible: NULL argument");
   afi::Geo g;
   if (!geometry(c, &g)) return AF_E_ARG;
-  afi::Work w;
-  afi::workspace_layout(g, &w, (char*)ws);
+  const afi::Work w = work_of(c, g, ws);
   const hipStream_t s = (hipStream_t)stream;
   AF_HIP(afi::count_inadmissible(g, c->p.gamma - 1.0, w, U, s));
   unsigned long long n = 0;
@@ -396,14 +425,14 @@ size_t af_workspace_bytes(const af_ctx* c) {
 af_status af_rk_stage(af_ctx* c, int k, const double* dt_dev, double dt_host, const double* Un,
                       const double* Uk, double* Uout, void* ws, void* stream) {
   if (!c || !Uk || !Uout || !ws) return fail(AF_E_ARG, "af_rk_stage: NULL argument");
+  if (!net_ready(c)) return AF_E_ARG;
   if (k < 0 || k > 2) return fail(AF_E_ARG, "stage index must be 0..2 (got %d)", k);
   if (k > 0 && !Un) return fail(AF_E_ARG, "stage %d needs Un", k);
   if (Uout == Uk || (Un && Uout == Un)) return fail(AF_E_ARG, "Uout aliases an input");
   if (!dt_dev && !(dt_host >= 0.0)) return fail(AF_E_ARG, "dt must be >= 0");
   afi::Geo g;
   if (!geometry(c, &g)) return AF_E_ARG;
-  afi::Work w;
-  afi::workspace_layout(g, &w, (char*)ws);
+  const afi::Work w = work_of(c, g, ws);
   hipError_t e = launch_stage(g, physics(c->p), w, k, Un, Uk, Uout, dt_dev, dt_host,
                               (hipStream_t)stream, c->timer, false);
   if (e != hipSuccess) return hip_fail(e, "af_rk_stage launch");
@@ -415,8 +444,7 @@ af_status af_cfl_dt(af_ctx* c, const double* U, double t, double t_final, double
   if (!c || !U || !ws || !dt_dev) return fail(AF_E_ARG, "af_cfl_dt: NULL argument");
   afi::Geo g;
   if (!geometry(c, &g)) return AF_E_ARG;
-  afi::Work w;
-  afi::workspace_layout(g, &w, (char*)ws);
+  const afi::Work w = work_of(c, g, ws);
   hipError_t e = launch_cfl(c, g, w, U, t, nullptr, t_final, dt_dev, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "af_cfl_dt launch");
   return AF_OK;
@@ -426,8 +454,7 @@ af_status af_read_flags(af_ctx* c, const void* ws, int* flags, void* stream) {
   if (!c || !ws || !flags) return fail(AF_E_ARG, "af_read_flags: NULL argument");
   afi::Geo g;
   if (!geometry(c, &g)) return AF_E_ARG;
-  afi::Work w;
-  afi::workspace_layout(g, &w, (char*)ws);
+  const afi::Work w = work_of(c, g, ws);
   unsigned f = 0;
   af_status st = read_flags(w, (hipStream_t)stream, &f);
   *flags = (int)f;
@@ -438,8 +465,7 @@ af_status af_reset_flags(af_ctx* c, void* ws, void* stream) {
   if (!c || !ws) return fail(AF_E_ARG, "af_reset_flags: NULL argument");
   afi::Geo g;
   if (!geometry(c, &g)) return AF_E_ARG;
-  afi::Work w;
-  afi::workspace_layout(g, &w, (char*)ws);
+  const afi::Work w = work_of(c, g, ws);
   AF_HIP(afi::clear_flags(w, (hipStream_t)stream));
   return AF_OK;
 }
@@ -447,11 +473,11 @@ af_status af_reset_flags(af_ctx* c, void* ws, void* stream) {
 af_status af_step(af_ctx* c, double* U, void* ws, void* stream, double dt, double t,
                   double t_final, double* dt_used, int* halvings) {
   if (!c || !U || !ws) return fail(AF_E_ARG, "af_step: NULL argument");
+  if (!net_ready(c)) return AF_E_ARG;
   if (!(t_final >= t)) return fail(AF_E_ARG, "t_final < t");
   afi::Geo g;
   if (!geometry(c, &g)) return AF_E_ARG;
-  afi::Work w;
-  afi::workspace_layout(g, &w, (char*)ws);
+  const afi::Work w = work_of(c, g, ws);
   const hipStream_t s = (hipStream_t)stream;
   const afd::Phys ph = physics(c->p);
   AF_HIP(afi::copy_state(w.SAVE, U, g.state_len, s));
@@ -486,12 +512,12 @@ af_status af_step(af_ctx* c, double* U, void* ws, void* stream, double dt, doubl
 af_status af_run(af_ctx* c, double* U, void* ws, void* stream, double t0, double t_final,
                  long max_steps, int check_every, long* nsteps_out, double* t_out) {
   if (!c || !U || !ws) return fail(AF_E_ARG, "af_run: NULL argument");
+  if (!net_ready(c)) return AF_E_ARG;
   if (check_every < 1) return fail(AF_E_ARG, "check_every must be >= 1");
   if (max_steps < 0) return fail(AF_E_ARG, "max_steps must be >= 0");
   afi::Geo g;
   if (!geometry(c, &g)) return AF_E_ARG;
-  afi::Work w;
-  afi::workspace_layout(g, &w, (char*)ws);
+  const afi::Work w = work_of(c, g, ws);
   const hipStream_t s = (hipStream_t)stream;
   const afd::Phys ph = physics(c->p);
   // the current state rotates through U, S1, S2: a step reads `cur` and
@@ -710,6 +736,113 @@ af_status af_batch_run(af_batch* b, double* const* U, void* ws, void* stream, do
     if (t_out) t_out[i] = h[i].t;
     if (status) status[i] = h[i].status;
     if (attempts) attempts[i] = h[i].attempts;
+  }
+  return AF_OK;
+}
+
+long af_face_count(const af_ctx* c) {
+  if (!c) return 0;
+  const long n1 = c->p.n1, n2 = c->p.dim == 2 ? c->p.n2 : 0;
+  return c->p.dim == 1 ? n1 + 1 : n2 * (n1 + 1) + (n2 + 1) * n1;
+}
+
+size_t af_mlp_param_count(void) { return (size_t)afi::kMlpParams; }
+
+af_status af_blend_features(af_ctx* c, const double* U, float* feat, void* stream) {
+  if (!c || !U || !feat) return fail(AF_E_ARG, "af_blend_features: NULL argument");
+  if (c->p.dim != 2) return fail(AF_E_ARG, "af_blend_features: 2D only");
+  afi::Geo g;
+  if (!geometry(c, &g)) return AF_E_ARG;
+  AF_HIP(afi::blend_features(g, physics(c->p), U, feat, (hipStream_t)stream));
+  return AF_OK;
+}
+
+af_status af_set_blend_net(af_ctx* c, const float* params) {
+  if (!c) return fail(AF_E_ARG, "af_set_blend_net: NULL context");
+  if (c->p.dim != 2 && params) return fail(AF_E_ARG, "af_set_blend_net: 2D only");
+  c->net = params;
+  return AF_OK;
+}
+
+af_status af_blend_infer(af_ctx* c, const double* U, float* theta, void* ws, void* stream) {
+  if (!c || !U || !theta || !ws) return fail(AF_E_ARG, "af_blend_infer: NULL argument");
+  if (c->p.dim != 2) return fail(AF_E_ARG, "af_blend_infer: 2D only");
+  if (!c->net) return fail(AF_E_ARG, "af_blend_infer: no network set (af_set_blend_net)");
+  afi::Geo g;
+  if (!geometry(c, &g)) return AF_E_ARG;
+  const afi::Work w = work_of(c, g, ws);
+  const hipStream_t s = (hipStream_t)stream;
+  AF_HIP(afi::mlp_pack(c->net, w.mlp, s));
+  AF_HIP(afi::blend_infer(g, physics(c->p), U, w.mlp, theta, s, c->timer));
+  return AF_OK;
+}
+
+af_status af_rk_stage_blend(af_ctx* c, int k, const double* dt_dev, double dt_host,
+                            const double* Un, const double* Uk, double* Uout, const float* theta,
+                            float* theta_s_out, void* ws, void* stream) {
+  if (!c || !Uk || !Uout || !ws) return fail(AF_E_ARG, "af_rk_stage_blend: NULL argument");
+  if (c->p.dim != 2) return fail(AF_E_ARG, "af_rk_stage_blend: 2D only");
+  if (k < 0 || k > 2) return fail(AF_E_ARG, "stage index must be 0..2 (got %d)", k);
+  if (k > 0 && !Un) return fail(AF_E_ARG, "stage %d needs Un", k);
+  if (Uout == Uk || (Un && Uout == Un)) return fail(AF_E_ARG, "Uout aliases an input");
+  if (!dt_dev && !(dt_host >= 0.0)) return fail(AF_E_ARG, "dt must be >= 0");
+  if (!theta && !net_ready(c)) return AF_E_ARG;
+  afi::Geo g;
+  if (!geometry(c, &g)) return AF_E_ARG;
+  const afi::Work w = work_of(c, g, ws);
+  afd::Phys ph = physics(c->p);
+  if (theta) ph.lim &= ~afd::LIM_LEARNED;  // the given blend, no inference
+  if (!Un) Un = Uk;
+  afi::StageCoef sc = kCoef[k];
+  sc.skip_flagged = 0;
+  sc.ts_out = theta_s_out;
+  const hipStream_t s = (hipStream_t)stream;
+  if (theta) {
+    sc.blend = theta;
+  } else if (ph.lim & afd::LIM_LEARNED) {
+    AF_HIP(afi::mlp_pack(c->net, w.mlp, s));
+    AF_HIP(afi::blend_infer(g, ph, Uk, w.mlp, w.blend, s, c->timer));
+    sc.blend = w.blend;
+  }
+  AF_HIP(afi::stage2d(g, ph, w, Un, Uk, Uout, dt_dev, dt_host, sc, s, c->timer));
+  return AF_OK;
+}
+
+size_t af_mlp_grad_workspace_bytes(long n) { return afi::mlp_grad_workspace(n); }
+
+af_status af_mlp_grad(const float* X, const float* y, long n, const float* params, float* grad,
+                      float* loss, void* gws, void* stream) {
+  if (!X || !y || !params || !grad || !gws) return fail(AF_E_ARG, "af_mlp_grad: NULL argument");
+  if (n < 1) return fail(AF_E_ARG, "af_mlp_grad: n must be >= 1");
+  AF_HIP(afi::mlp_grad(X, y, n, params, grad, loss, gws, (hipStream_t)stream));
+  return AF_OK;
+}
+
+af_status af_mlp_adam(float* params, const float* grad, float* m, float* v, long step, float lr,
+                      void* stream) {
+  if (!params || !grad || !m || !v) return fail(AF_E_ARG, "af_mlp_adam: NULL argument");
+  if (step < 1) return fail(AF_E_ARG, "af_mlp_adam: step counts from 1");
+  AF_HIP(afi::mlp_adam(params, grad, m, v, step, lr, (hipStream_t)stream));
+  return AF_OK;
+}
+
+af_status af_mlp_train(const float* X, const float* y, long n, float* params, float* grad,
+                       float* m, float* v, long step0, int steps, int batch, float lr,
+                       float* loss_out, void* gws, void* stream) {
+  if (!X || !y || !params || !grad || !m || !v || !gws)
+    return fail(AF_E_ARG, "af_mlp_train: NULL argument");
+  if (n < 1 || steps < 0 || batch < 1 || step0 < 0)
+    return fail(AF_E_ARG, "af_mlp_train: bad sizes");
+  const hipStream_t s = (hipStream_t)stream;
+  long row = 0;
+  for (int k = 0; k < steps; ++k) {
+    // the next minibatch in order; a batch that would cross the end starts
+    // over from the first row
+    long nb = batch < n ? batch : n;
+    if (row + nb > n) row = 0;
+    AF_HIP(afi::mlp_grad(X + row * afi::kMlpIn, y + row, nb, params, grad, loss_out, gws, s));
+    AF_HIP(afi::mlp_adam(params, grad, m, v, step0 + k + 1, lr, s));
+    row += nb;
   }
   return AF_OK;
 }

@@ -286,6 +286,10 @@ size_t workspace_layout(const Geo& g, Work* w, char* base) {
   r.S1 = (double*)take(sizeof(double) * g.state_len);
   r.S2 = (double*)take(sizeof(double) * g.state_len);
   r.SAVE = (double*)take(sizeof(double) * g.state_len);
+  if (g.dim == 2) {
+    r.blend = (float*)take(sizeof(float) * (nfx + nfy));
+    r.mlp = (void*)take(kMlpPackedBytes);
+  }
   r.bytes = off;
   if (w) *w = r;
   return off;

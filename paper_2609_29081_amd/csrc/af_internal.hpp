@@ -95,6 +95,12 @@ struct Work {
   double* S1;        // stage buffers and checkpoint (one state each)
   double* S2;
   double* SAVE;
+  // 2D learned blend: one coefficient per face, and the network's weights as
+  // the inference kernel reads them (bfloat16 W1, W2, w3; FP32 biases)
+  float* blend;
+  void* mlp;
+  // host-side: the context's learned-blend network (device parameters), or NULL
+  const float* net;
   size_t bytes;      // total
 };
 
@@ -105,6 +111,12 @@ struct StageCoef {
   // 1: the stage belongs to a step attempt and stops as soon as the attempt's
   // flag word is set (the attempt is rejected, so its output is never used)
   int skip_flagged;
+  // 2D only: a blend coefficient per face that takes the place of theta^s
+  // (the density/pressure limiter then clamps it as it clamps theta^s), or
+  // NULL; and an array that receives the coefficient used in theta^s's
+  // place per face, or NULL
+  const float* blend;
+  float* ts_out;
 };
 
 size_t workspace_layout(const Geo& g, Work* w, char* base);
@@ -122,6 +134,22 @@ struct Timer {
     launch;                            \
     if (tm) (tm)->end(s);              \
   } while (0)
+
+// the learned blend (af_learn.hip)
+constexpr int kMlpIn = 40, kMlpHidden = 64;
+constexpr long kMlpParams = (long)kMlpHidden * kMlpIn + kMlpHidden + (long)kMlpHidden * kMlpHidden +
+                            kMlpHidden + kMlpHidden + 1;
+constexpr size_t kMlpPackedBytes = 14336;
+hipError_t blend_features(const Geo& g, const afd::Phys& ph, const double* U, float* feat,
+                          hipStream_t s);
+hipError_t mlp_pack(const float* params, void* packed, hipStream_t s);
+hipError_t blend_infer(const Geo& g, const afd::Phys& ph, const double* U, const void* packed,
+                       float* theta, hipStream_t s, Timer* tm);
+size_t mlp_grad_workspace(long n);
+hipError_t mlp_grad(const float* X, const float* y, long n, const float* params, float* grad,
+                    float* loss, void* ws, hipStream_t s);
+hipError_t mlp_adam(float* params, const float* grad, float* m, float* v, long step, float lr,
+                    hipStream_t s);
 
 // launchers (enqueue on stream; return the first HIP error)
 // the 2D stage of one instance, with its precision's default variant

@@ -1,0 +1,573 @@
+// af_learn.hip -- the learned blend coefficient of the 2D cell-average fluxes
+// on gfx950: face features, inference of the 40-64-64-1 network on the MFMA
+// units, and the network's training (loss gradient and Adam).
+//
+// The network proposes, per face, the coefficient that blends the low- and
+// high-order cell-average fluxes in place of the smoothness blend theta^s of
+// Sec. 3.2; the density/pressure limiter of Sec. 3.3 then clamps it as it
+// clamps theta^s (the coefficient used is theta_nn theta^rho theta^p, never
+// above theta_nn nor the admissible bound), and the face flux stays
+// single-valued (conservative).
+//
+// Features of a face (a, b its minus and plus cells): in the face's frame
+// (normal n along its axis, tangent t along the other) the 4 x 3 block of
+// cell averages at normal offsets -2, -1 (a), +1 (b), +2 and tangential
+// offsets -1, 0, +1, ghost cells being boundary images.  With face values
+// rho_f = (rho_a + rho_b)/2, p_f, u_nf, u_tf likewise and
+// c_f = sqrt(gamma p_f / rho_f): for s = -1, 0, +1 and m = -2, -1, +1, +2 the
+// triple [ln(p / p_f), (u_n - u_nf) / c_f, (u_t - u_tf) / c_f], then
+// ln(rho / rho_f) for m = -2, -1, +1, +2 at s = 0 (40 values).
+//
+// Network: h1 = tanh(W1 x + b1), h2 = tanh(W2 h1 + b2), z = w3.h2 + b3,
+// theta_nn = min(max(z, 0), 1); parameters as one FP32 vector
+// [W1 (64 x 40, row-major), b1, W2 (64 x 64), b2, w3, b3].  Inference keeps
+// W1, W2, w3 and the layer inputs x, h1 in bfloat16 (round to nearest even)
+// and accumulates in FP32 (MFMA 32x32x8 bf16); training runs in FP32.
+#include "af_device.hpp"
+#include "af_internal.hpp"
+#include "af_lattice.hpp"
+
+using namespace afd;
+
+namespace {
+
+constexpr int NIN = afi::kMlpIn, NH = afi::kMlpHidden;
+constexpr int OFF_W1 = 0, OFF_B1 = NH * NIN, OFF_W2 = OFF_B1 + NH, OFF_B2 = OFF_W2 + NH * NH,
+              OFF_W3 = OFF_B2 + NH, OFF_B3 = OFF_W3 + NH;
+static_assert(OFF_B3 + 1 == afi::kMlpParams, "parameter layout");
+
+// packed inference weights: bfloat16 W1 [64][40], W2 [64][64], w3 [64], then
+// FP32 b1 [64], b2 [64], b3
+constexpr int PK_W1 = 0, PK_W2 = PK_W1 + 2 * NH * NIN, PK_W3 = PK_W2 + 2 * NH * NH,
+              PK_B1 = PK_W3 + 2 * NH, PK_B2 = PK_B1 + 4 * NH, PK_B3 = PK_B2 + 4 * NH;
+static_assert(PK_B3 + 4 <= (int)afi::kMlpPackedBytes, "packed weights");
+
+__device__ __forceinline__ unsigned short to_bf16(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(unsigned short h) {
+  return __uint_as_float((unsigned)h << 16);
+}
+
+// face f -> direction d, face (i, j); x-faces [n2][n1+1] first
+__device__ __forceinline__ void face_of(const G2& g, long f, int& d, int& i, int& j) {
+  const long nfx = (long)g.n2 * (g.n1 + 1);
+  if (f < nfx) {
+    d = 0;
+    j = (int)(f / (g.n1 + 1));
+    i = (int)(f % (g.n1 + 1));
+  } else {
+    d = 1;
+    const long r = f - nfx;
+    j = (int)(r / g.n1);
+    i = (int)(r % g.n1);
+  }
+}
+
+// (rho, u, v, p) of the cell average of cell (ci, cj), ci in [-2, n1+1]
+__device__ __forceinline__ void cell_prims(const G2& g, double gm1, const double* U, int ci, int cj,
+                                           float* P) {
+  double V[4];
+  raw_value(g, U, 2 * ci + 1, 2 * cj + 1, V);
+  const double u = V[1] / V[0], v = V[2] / V[0];
+  P[0] = float(V[0]);
+  P[1] = float(u);
+  P[2] = float(v);
+  P[3] = float(gm1 * (V[3] - 0.5 * V[0] * (u * u + v * v)));
+}
+
+__device__ __forceinline__ float pos_or_tiny(float v) { return v > 1e-30f ? v : 1e-30f; }
+
+// the 40 features of face (d, i, j) from the primitives of its stencil cells:
+// cell(s, q, P) fills the (rho, u, v, p) of tangential offset s-1 and normal
+// offset q in (-2, -1, +1, +2)
+template <typename CellFn>
+__device__ __forceinline__ void features_of(int d, float gam, CellFn cell, float* o) {
+  float rho[3][4], un[3][4], ut[3][4], p[3][4];
+#pragma unroll
+  for (int s = 0; s < 3; ++s)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      float P[4];
+      cell(s, q, P);
+      rho[s][q] = P[0];
+      un[s][q] = d == 0 ? P[1] : P[2];
+      ut[s][q] = d == 0 ? P[2] : P[1];
+      p[s][q] = P[3];
+    }
+  const float rf = 0.5f * (rho[1][1] + rho[1][2]), pf = 0.5f * (p[1][1] + p[1][2]);
+  const float unf = 0.5f * (un[1][1] + un[1][2]), utf = 0.5f * (ut[1][1] + ut[1][2]);
+  const float icf = 1.0f / sqrtf(gam * pos_or_tiny(pf) / pos_or_tiny(rf));
+  const float ipf = 1.0f / pos_or_tiny(pf), irf = 1.0f / pos_or_tiny(rf);
+#pragma unroll
+  for (int s = 0; s < 3; ++s)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int n = 3 * (4 * s + q);
+      o[n] = logf(pos_or_tiny(p[s][q]) * ipf);
+      o[n + 1] = (un[s][q] - unf) * icf;
+      o[n + 2] = (ut[s][q] - utf) * icf;
+    }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) o[36 + q] = logf(pos_or_tiny(rho[1][q]) * irf);
+}
+
+// stencil cell (ci, cj) of face (d, i, j) at tangential offset s-1, normal
+// offset index q
+__device__ __forceinline__ void stencil_cell(int d, int i, int j, int s, int q, int& ci, int& cj) {
+  const int m = q - 2;  // -2, -1, 0, +1 relative to cell b
+  if (d == 0) {
+    ci = i + m;
+    cj = j + s - 1;
+  } else {
+    ci = i + s - 1;
+    cj = j + m;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// features of every face (training data), one thread per face
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_features(G2 g, double gm1, float gam,
+                                                  const double* __restrict__ U,
+                                                  float* __restrict__ out, long nf) {
+  for (long f = blockIdx.x * (long)blockDim.x + threadIdx.x; f < nf;
+       f += (long)gridDim.x * blockDim.x) {
+    int d, i, j;
+    face_of(g, f, d, i, j);
+    float o[NIN];
+    features_of(d, gam,
+                [&](int s, int q, float* P) {
+                  int ci, cj;
+                  stencil_cell(d, i, j, s, q, ci, cj);
+                  cell_prims(g, gm1, U, ci, cj, P);
+                },
+                o);
+#pragma unroll
+    for (int n = 0; n < NIN; ++n) out[f * NIN + n] = o[n];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// inference.  A workgroup (four wave64s) takes 128 consecutive faces of one
+// row of one direction: it stages the primitives of their stencil cells in
+// LDS, writes the features as bfloat16, and each wave runs the network on
+// 32 faces with MFMA 32x32x8 bf16 (A: faces x inputs from LDS, B: weights
+// held in registers for the whole kernel).
+// ---------------------------------------------------------------------------
+constexpr int IB = 128;                 // faces per block
+constexpr int IPAD = 8;                 // bf16 padding of LDS rows
+constexpr int FROW = NIN + IPAD;        // feature row (bf16)
+constexpr int HROW = NH + IPAD;         // hidden row (bf16)
+constexpr int CW = IB + 4;              // stencil cells per row
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+struct InferShared {
+  float cell[4][4][CW];                 // [component][row][column]
+  unsigned short feat[IB * FROW];
+  unsigned short hid[IB * HROW];
+};
+
+__device__ __forceinline__ bf16x4 load4(const unsigned short* p) {
+  bf16x4 r;
+  r[0] = (short)p[0];
+  r[1] = (short)p[1];
+  r[2] = (short)p[2];
+  r[3] = (short)p[3];
+  return r;
+}
+
+__global__ void __launch_bounds__(256) k_infer(G2 g, double gm1, float gam,
+                                               const double* __restrict__ U,
+                                               const unsigned char* __restrict__ pk,
+                                               float* __restrict__ theta, int nsegx, int nsegy,
+                                               long nblocks) {
+  __shared__ InferShared S;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int h = lane >> 5, c32 = lane & 31;
+  const unsigned short* W1 = (const unsigned short*)(pk + PK_W1);
+  const unsigned short* W2 = (const unsigned short*)(pk + PK_W2);
+  const unsigned short* w3 = (const unsigned short*)(pk + PK_W3);
+  const float* b1 = (const float*)(pk + PK_B1);
+  const float* b2 = (const float*)(pk + PK_B2);
+  const float b3 = *(const float*)(pk + PK_B3);
+  // B operands: lane holds W[n = 32 nb + c32][k = 8 kb + 4 h + 0..3]
+  bf16x4 B1[5][2], B2[8][2];
+#pragma unroll
+  for (int kb = 0; kb < 5; ++kb)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) B1[kb][nb] = load4(W1 + (32 * nb + c32) * NIN + 8 * kb + 4 * h);
+#pragma unroll
+  for (int kb = 0; kb < 8; ++kb)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) B2[kb][nb] = load4(W2 + (32 * nb + c32) * NH + 8 * kb + 4 * h);
+  float bias1[2], bias2[2], ow[2];
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) {
+    bias1[nb] = b1[32 * nb + c32];
+    bias2[nb] = b2[32 * nb + c32];
+    ow[nb] = from_bf16(w3[32 * nb + c32]);
+  }
+  const long nfx = (long)g.n2 * (g.n1 + 1);
+  const long nbx = (long)g.n2 * nsegx;
+  for (long blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+    // the block: direction, row, first face along the row, face count
+    int d, row, i0, cnt;
+    if (blk < nbx) {
+      d = 0;
+      row = (int)(blk / nsegx);
+      i0 = (int)(blk % nsegx) * IB;
+      cnt = min(IB, g.n1 + 1 - i0);
+    } else {
+      d = 1;
+      const long r = blk - nbx;
+      row = (int)(r / nsegy);
+      i0 = (int)(r % nsegy) * IB;
+      cnt = min(IB, g.n1 - i0);
+    }
+    // stencil cells: x-faces need columns i0-2 .. i0+cnt and rows row-1..row+1;
+    // y-faces columns i0-1 .. i0+cnt and rows row-2..row+1
+    const int ncol = d == 0 ? cnt + 3 : cnt + 2, nrow = d == 0 ? 3 : 4;
+    const int c0 = d == 0 ? i0 - 2 : i0 - 1, r0 = d == 0 ? row - 1 : row - 2;
+    __syncthreads();  // the previous block is done with the LDS
+    for (int e = tid; e < ncol * nrow; e += 256) {
+      const int rr = e / ncol, cc = e % ncol;
+      float P[4];
+      cell_prims(g, gm1, U, c0 + cc, r0 + rr, P);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) S.cell[k][rr][cc] = P[k];
+    }
+    __syncthreads();
+    if (tid < IB) {
+      unsigned short* fo = S.feat + tid * FROW;
+      if (tid < cnt) {
+        const int i = i0 + tid;
+        float o[NIN];
+        features_of(d, gam,
+                    [&](int s, int q, float* P) {
+                      int ci, cj;
+                      stencil_cell(d, i, row, s, q, ci, cj);
+#pragma unroll
+                      for (int k = 0; k < 4; ++k) P[k] = S.cell[k][cj - r0][ci - c0];
+                    },
+                    o);
+#pragma unroll
+        for (int n = 0; n < NIN; ++n) fo[n] = to_bf16(o[n]);
+      } else {
+#pragma unroll
+        for (int n = 0; n < NIN; ++n) fo[n] = 0;
+      }
+    }
+    __syncthreads();
+    // the wave's 32 faces
+    const unsigned short* fa = S.feat + (32 * wave) * FROW;
+    unsigned short* hw = S.hid + (32 * wave) * HROW;
+    f32x16 acc[2];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[nb][r] = 0.0f;
+#pragma unroll
+    for (int kb = 0; kb < 5; ++kb) {
+      const bf16x4 a = load4(fa + c32 * FROW + 8 * kb + 4 * h);
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, B1[kb][nb], acc[nb], 0, 0, 0);
+    }
+    // h1 = tanh(.) as bfloat16 rows of the next layer's A operand; D element
+    // r of this lane is row 8 (r/4) + 4 h + r%4, column 32 nb + c32
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = 8 * (r >> 2) + 4 * h + (r & 3);
+        hw[m * HROW + 32 * nb + c32] = to_bf16(tanhf(acc[nb][r] + bias1[nb]));
+      }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[nb][r] = 0.0f;
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) {
+      const bf16x4 a = load4(hw + c32 * HROW + 8 * kb + 4 * h);
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, B2[kb][nb], acc[nb], 0, 0, 0);
+    }
+    // z = w3 . tanh(.) + b3: lane sums its two columns, then the 32 lanes of
+    // its half (same rows) reduce
+    float zp[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      zp[r] = ow[0] * tanhf(acc[0][r] + bias2[0]) + ow[1] * tanhf(acc[1][r] + bias2[1]);
+#pragma unroll
+    for (int off = 16; off >= 1; off >>= 1)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) zp[r] += __shfl_xor(zp[r], off, 64);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int m = 32 * wave + 8 * (r >> 2) + 4 * h + (r & 3);
+      if (c32 == r && m < cnt) {
+        const float z = zp[r] + b3;
+        const long f = (d == 0 ? 0 : nfx) + (long)row * (d == 0 ? g.n1 + 1 : g.n1) + i0 + m;
+        theta[f] = fminf(fmaxf(z, 0.0f), 1.0f);
+      }
+    }
+  }
+}
+
+__global__ void k_pack(const float* __restrict__ p, unsigned char* __restrict__ pk) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < NH * NIN) ((unsigned short*)(pk + PK_W1))[t] = to_bf16(p[OFF_W1 + t]);
+  if (t < NH * NH) ((unsigned short*)(pk + PK_W2))[t] = to_bf16(p[OFF_W2 + t]);
+  if (t < NH) {
+    ((unsigned short*)(pk + PK_W3))[t] = to_bf16(p[OFF_W3 + t]);
+    ((float*)(pk + PK_B1))[t] = p[OFF_B1 + t];
+    ((float*)(pk + PK_B2))[t] = p[OFF_B2 + t];
+  }
+  if (t == 0) *(float*)(pk + PK_B3) = p[OFF_B3];
+}
+
+// ---------------------------------------------------------------------------
+// training: gradient of the mean squared error over n samples, FP32.  Each
+// workgroup takes chunks of 64 samples, runs forward and backward through
+// LDS and accumulates its share of the gradient in registers; partial
+// gradients are then summed in a fixed order (deterministic).
+// ---------------------------------------------------------------------------
+constexpr int GC = 64;          // samples per chunk
+constexpr int GT = 256;         // threads per workgroup
+constexpr int kGradBlocks = 128;
+
+struct GradShared {
+  float W1[NH * NIN], W2[NH * NH], w3[NH], b1[NH], b2[NH];
+  float X[GC * NIN], H1[GC * NH], H2[GC * NH], A[GC * NH], dz[GC], red[GT];
+};
+
+__global__ void __launch_bounds__(GT) k_grad(const float* __restrict__ X,
+                                             const float* __restrict__ y, long n,
+                                             const float* __restrict__ p,
+                                             float* __restrict__ part, float inv_n) {
+  __shared__ GradShared S;
+  const int t = threadIdx.x;
+  for (int e = t; e < NH * NIN; e += GT) S.W1[e] = p[OFF_W1 + e];
+  for (int e = t; e < NH * NH; e += GT) S.W2[e] = p[OFF_W2 + e];
+  if (t < NH) {
+    S.w3[t] = p[OFF_W3 + t];
+    S.b1[t] = p[OFF_B1 + t];
+    S.b2[t] = p[OFF_B2 + t];
+  }
+  const float b3 = p[OFF_B3];
+  float gW1[10], gW2[16], gb1 = 0.f, gb2 = 0.f, gw3 = 0.f, gb3 = 0.f, loss = 0.f;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) gW1[r] = 0.f;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) gW2[r] = 0.f;
+  const int nu = t & 63, mg = t >> 6;  // unit and sample group of this thread
+  const long nchunk = (n + GC - 1) / GC;
+  for (long c = blockIdx.x; c < nchunk; c += gridDim.x) {
+    const long base = c * GC;
+    __syncthreads();
+    for (int e = t; e < GC * NIN; e += GT) {
+      const long row = base + e / NIN;
+      S.X[e] = row < n ? X[row * NIN + e % NIN] : 0.f;
+    }
+    __syncthreads();
+    // layer 1
+#pragma unroll 1
+    for (int r = 0; r < 16; ++r) {
+      const int m = 16 * mg + r;
+      float a = S.b1[nu];
+#pragma unroll 8
+      for (int k = 0; k < NIN; ++k) a += S.W1[nu * NIN + k] * S.X[m * NIN + k];
+      S.H1[m * NH + nu] = tanhf(a);
+    }
+    __syncthreads();
+    // layer 2
+#pragma unroll 1
+    for (int r = 0; r < 16; ++r) {
+      const int m = 16 * mg + r;
+      float a = S.b2[nu];
+#pragma unroll 8
+      for (int k = 0; k < NH; ++k) a += S.W2[nu * NH + k] * S.H1[m * NH + k];
+      S.H2[m * NH + nu] = tanhf(a);
+    }
+    __syncthreads();
+    // output, residual, dL/dz
+    if (t < GC) {
+      float z = b3;
+      for (int k = 0; k < NH; ++k) z += S.w3[k] * S.H2[t * NH + k];
+      const bool valid = base + t < n;
+      const float res = valid ? z - y[base + t] : 0.f;
+      loss += res * res;
+      S.dz[t] = 2.f * res * inv_n;
+    }
+    __syncthreads();
+    // dL/d(layer-2 pre-activation)
+#pragma unroll 1
+    for (int r = 0; r < 16; ++r) {
+      const int m = 16 * mg + r;
+      const float h2 = S.H2[m * NH + nu];
+      S.A[m * NH + nu] = S.dz[m] * S.w3[nu] * (1.f - h2 * h2);
+    }
+    __syncthreads();
+    if (t < NH) {
+      float s3 = 0.f, s2 = 0.f;
+      for (int m = 0; m < GC; ++m) {
+        s3 += S.dz[m] * S.H2[m * NH + t];
+        s2 += S.A[m * NH + t];
+      }
+      gw3 += s3;
+      gb2 += s2;
+    }
+    if (t == 0) {
+      float s = 0.f;
+#pragma unroll 8
+      for (int m = 0; m < GC; ++m) s += S.dz[m];
+      gb3 += s;
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int e = t + GT * r, o = e / NH, k = e % NH;
+      float s = 0.f;
+#pragma unroll 8
+      for (int m = 0; m < GC; ++m) s += S.A[m * NH + o] * S.H1[m * NH + k];
+      gW2[r] += s;
+    }
+    // dL/d(layer-1 pre-activation), into H2 (no longer needed)
+#pragma unroll 1
+    for (int r = 0; r < 16; ++r) {
+      const int m = 16 * mg + r;
+      float s = 0.f;
+#pragma unroll 8
+      for (int o = 0; o < NH; ++o) s += S.A[m * NH + o] * S.W2[o * NH + nu];
+      const float h1 = S.H1[m * NH + nu];
+      S.H2[m * NH + nu] = s * (1.f - h1 * h1);
+    }
+    __syncthreads();
+    if (t < NH) {
+      float s1 = 0.f;
+      for (int m = 0; m < GC; ++m) s1 += S.H2[m * NH + t];
+      gb1 += s1;
+    }
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+      const int e = t + GT * r, o = e / NIN, k = e % NIN;
+      float s = 0.f;
+#pragma unroll 8
+      for (int m = 0; m < GC; ++m) s += S.H2[m * NH + o] * S.X[m * NIN + k];
+      gW1[r] += s;
+    }
+  }
+  // this workgroup's partial gradient and loss sum
+  float* q = part + (long)blockIdx.x * (afi::kMlpParams + 1);
+#pragma unroll
+  for (int r = 0; r < 10; ++r) q[OFF_W1 + t + GT * r] = gW1[r];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) q[OFF_W2 + t + GT * r] = gW2[r];
+  if (t < NH) {
+    q[OFF_B1 + t] = gb1;
+    q[OFF_B2 + t] = gb2;
+    q[OFF_W3 + t] = gw3;
+  }
+  if (t == 0) q[OFF_B3] = gb3;
+  S.red[t] = t < GC ? loss : 0.f;
+  __syncthreads();
+  if (t == 0) {
+    float s = 0.f;
+    for (int k = 0; k < GC; ++k) s += S.red[k];
+    q[afi::kMlpParams] = s;
+  }
+}
+
+__global__ void k_grad_sum(const float* __restrict__ part, int nparts, float* __restrict__ grad,
+                           float* __restrict__ loss, float inv_n) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e > afi::kMlpParams) return;
+  float s = 0.f;
+  for (int b = 0; b < nparts; ++b) s += part[(long)b * (afi::kMlpParams + 1) + e];
+  if (e < afi::kMlpParams)
+    grad[e] = s;
+  else if (loss)
+    *loss = s * inv_n;
+}
+
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, float lr, float c1, float c2) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= afi::kMlpParams) return;
+  const float ge = g[e];
+  const float me = 0.9f * m[e] + 0.1f * ge;
+  const float ve = 0.999f * v[e] + 0.001f * ge * ge;
+  m[e] = me;
+  v[e] = ve;
+  p[e] -= lr * (me * c1) / (sqrtf(ve * c2) + 1e-8f);
+}
+
+}  // namespace
+
+namespace afi {
+
+hipError_t blend_features(const Geo& geo, const Phys& ph, const double* U, float* feat,
+                          hipStream_t s) {
+  const G2 g = stage_geo(geo);
+  const long nf = (long)g.n2 * (g.n1 + 1) + (long)(g.n2 + 1) * g.n1;
+  long nb = (nf + 255) / 256;
+  if (nb > 65536) nb = 65536;
+  hipLaunchKernelGGL(k_features, dim3((unsigned)nb), dim3(256), 0, s, g, ph.gm1, float(ph.gam), U,
+                     feat, nf);
+  return hipGetLastError();
+}
+
+hipError_t mlp_pack(const float* params, void* packed, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack, dim3((NH * NH + 255) / 256), dim3(256), 0, s, params,
+                     (unsigned char*)packed);
+  return hipGetLastError();
+}
+
+hipError_t blend_infer(const Geo& geo, const Phys& ph, const double* U, const void* packed,
+                       float* theta, hipStream_t s, Timer* tm) {
+  const G2 g = stage_geo(geo);
+  const int nsegx = (g.n1 + 1 + IB - 1) / IB, nsegy = (g.n1 + IB - 1) / IB;
+  const long nblocks = (long)g.n2 * nsegx + (long)(g.n2 + 1) * nsegy;
+  long grid = nblocks < 4096 ? nblocks : 4096;
+  AFI_TIMED(tm, 8, s,
+            hipLaunchKernelGGL(k_infer, dim3((unsigned)grid), dim3(256), 0, s, g, ph.gm1,
+                               float(ph.gam), U, (const unsigned char*)packed, theta, nsegx,
+                               nsegy, nblocks));
+  return hipGetLastError();
+}
+
+size_t mlp_grad_workspace(long n) {
+  (void)n;
+  return sizeof(float) * (size_t)kGradBlocks * (kMlpParams + 1);
+}
+
+hipError_t mlp_grad(const float* X, const float* y, long n, const float* params, float* grad,
+                    float* loss, void* ws, hipStream_t s) {
+  const long nchunk = (n + GC - 1) / GC;
+  const int nb = (int)(nchunk < kGradBlocks ? nchunk : kGradBlocks);
+  float* part = (float*)ws;
+  const float inv_n = 1.0f / float(n);
+  hipLaunchKernelGGL(k_grad, dim3(nb), dim3(GT), 0, s, X, y, n, params, part, inv_n);
+  hipLaunchKernelGGL(k_grad_sum, dim3((kMlpParams + 1 + 255) / 256), dim3(256), 0, s,
+                     (const float*)part, nb, grad, loss, inv_n);
+  return hipGetLastError();
+}
+
+hipError_t mlp_adam(float* params, const float* grad, float* m, float* v, long step, float lr,
+                    hipStream_t s) {
+  const double c1 = 1.0 / (1.0 - pow(0.9, (double)step));
+  const double c2 = 1.0 / (1.0 - pow(0.999, (double)step));
+  hipLaunchKernelGGL(k_adam, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, params, grad, m, v,
+                     lr, float(c1), float(c2));
+  return hipGetLastError();
+}
+
+}  // namespace afi

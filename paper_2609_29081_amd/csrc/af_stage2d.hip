@@ -31,6 +31,7 @@
 
 #include "af_device.hpp"
 #include "af_internal.hpp"
+#include "af_lattice.hpp"
 
 using namespace afd;
 
@@ -66,41 +67,8 @@ constexpr int NCEN = (TX + 4) * (TY + 4);  // centre sites of the lattice region
 constexpr int NPT = 3 * TX * TY;           // point DOF sites of a tile
 constexpr int kStage = 9 * NCEN > 4 * NPT ? 9 * NCEN : 4 * NPT;
 
-using G2 = afi::StageGeo;
-
 template <typename R>
 constexpr bool kFP64 = std::is_same<R, double>::value;
-
-// offset of interior lattice site (X, Y) in a state (its first component;
-// centre sites hold the cell average, the periodic seam is folded) and the
-// distance between its component planes.  Plane indices fit 32 bits (the
-// grid size is bounded at init).
-__device__ __forceinline__ void site_ofs(const G2& g, int X, int Y, long& o, int& st) {
-  if (X == 2 * g.n1 && g.n1x == g.n1) X = 0;
-  if (Y == 2 * g.n2 && g.n2y == g.n2) Y = 0;
-  const bool xo = X & 1, yo = Y & 1;
-  const int ncol = xo ? g.n1 : g.n1x;
-  const long base = xo ? (yo ? 0L : g.off_ye) : (yo ? g.off_xe : g.off_co);
-  st = xo ? (yo ? g.st_avg : g.st_ye) : (yo ? g.st_xe : g.st_co);
-  o = base + (long)((Y >> 1) * ncol + (X >> 1));
-}
-
-// FP64 value of lattice site (X, Y), X in [-4, 2n1+4], read from the state:
-// ghosts are images of interior sites (centre sites hold the average)
-__device__ __forceinline__ void raw_value(const G2& g, const double* __restrict__ U, int X, int Y,
-                                          double* V) {
-  int kx, ky;
-  const int Xi = axis_image(X, 2 * g.n1, g.bc0, g.bc1, kx);
-  const int Yi = axis_image(Y, 2 * g.n2, g.bc2, g.bc3, ky);
-  const Signs sg = image_signs(kx, ky);
-  long o;
-  int st;
-  site_ofs(g, Xi, Yi, o, st);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) V[k] = U[o + (long)k * st];
-  V[1] *= sg.sx;
-  V[2] *= sg.sy;
-}
 
 // (u, v, p, T, c) of state V, given 1/rho
 template <typename R>
@@ -492,6 +460,10 @@ struct StageArgs {
   double dt_host;
   unsigned* flags;
   int ntx;
+  // learned blend (one instance): a blend coefficient per face replacing
+  // theta^s, or NULL; and where to write theta^s per face, or NULL
+  const float* blend;
+  float* ts_out;
   // a batch: its instances (stage k reads and writes their rotating buffers)
   afi::BatchInst* inst;
   int ninst, k;
@@ -777,7 +749,13 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
   __syncthreads();
 
   // ---- phase 3: limited face fluxes of the tile's cells ----
-  const int limc = ph.lim & (LIM_SMOOTH | LIM_PP | LIM_LOWONLY);
+  const float* blend = nullptr;
+  float* ts_out = nullptr;
+  if constexpr (!BATCH) {
+    blend = sa.blend;
+    ts_out = sa.ts_out;
+  }
+  const int limc = (ph.lim & (LIM_SMOOTH | LIM_PP | LIM_LOWONLY)) | (blend ? 1 : 0);
   for (int s = tid; s < NFX + NFY; s += NT) {
     const int d = s < NFX ? 0 : 1;
     int ff, jj, i, j, X, Y;  // face (i,j) between cells a (minus) and b (plus)
@@ -832,12 +810,22 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
       }
       R ts = R(1.0);
       double tpp = 1.0;
+      // the face's entries in per-face arrays: x-faces [n2][n1+1], then
+      // y-faces [n2+1][n1]; a periodic axis's last face is its first again
+      const bool use_blend = blend != nullptr;
       if (ph.lim & LIM_LOWONLY) {
         ts = R(0.0);
         tpp = 0.0;
       } else {
-        if (ph.lim & LIM_SMOOTH)
+        if (use_blend) {
+          // the given coefficient takes the place of theta^s
+          const long nfx = (long)g.n2 * (g.n1 + 1);
+          const int fi = (d == 0 && i == g.n1 && g.n1x == g.n1) ? 0 : i;
+          const int fj = (d == 1 && j == g.n2 && g.n2y == g.n2) ? 0 : j;
+          ts = R(blend[d == 0 ? (long)fj * (g.n1 + 1) + fi : nfx + (long)fj * g.n1 + fi]);
+        } else if (ph.lim & LIM_SMOOTH) {
           ts = exp(-ph.Cs * mx(T.C[12][cax], T.C[12][cbx]) * mx(T.C[13][cax], T.C[13][cbx]));
+        }
         if (ph.lim & LIM_PP) {
           // the density and pressure blend in FP64 (Sec. 3.3)
           const double m4 = 4.0 * dt / (d == 0 ? g.dx : g.dy);
@@ -876,6 +864,10 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
         }
       }
       const double th = double(ts) * tpp;
+      if (ts_out) {
+        const long nfx = (long)g.n2 * (g.n1 + 1);
+        ts_out[d == 0 ? (long)j * (g.n1 + 1) + i : nfx + (long)j * g.n1 + i] = float(ts);
+      }
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const double fl = FL[k], fh = FH[k];
@@ -1117,6 +1109,8 @@ hipError_t launch(const G2& g, const Phys& ph, const afi::Work& w, const double*
   sa.cb = sc.b;
   sa.first = sc.first;
   sa.skip_flagged = sc.skip_flagged;
+  sa.blend = sc.blend;
+  sa.ts_out = sc.ts_out;
   sa.ntiles = ntiles;
   AFI_TIMED(tm, 7, s,
             hipLaunchKernelGGL((k_stage<R, false>), dim3((unsigned)nwg), dim3(NT), 0, s, sa));

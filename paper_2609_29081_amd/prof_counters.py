@@ -4,6 +4,7 @@ from rocprofv3 counters.
     python -m paper_2609_29081_amd.prof_counters [--mixed]            # driver (GPU machine)
     python -m paper_2609_29081_amd.prof_counters --target [--mixed]   # profiled program
     python -m paper_2609_29081_amd.prof_counters --target-batch       # batched sweep
+    python -m paper_2609_29081_amd.prof_counters --target-learned     # learned blend
 
 The driver runs three counter passes (FETCH_SIZE; WRITE_SIZE; the FP64 and
 LDS instruction counters) over the target, which launches the stage kernel on the 1000 x 500 shock tube (the
@@ -89,6 +90,28 @@ def target_batch(steps: int = 3) -> None:
     assert st == [af.AF_OK] * len(insts)
     print("target done: variant", af.stage_variants()[B.variant][0], "attempts", sum(att),
           flush=True)
+
+
+def target_learned(steps: int = 3) -> None:
+    """the learned form's launches: `steps` steps of the 2048 x 1024 shock
+    tube (FP64) with the learned blend (seeded initial network: inference
+    costs the same for any weights), for a kernel trace of the blend
+    inference beside the stage kernel"""
+    sys.path.insert(0, ROOT)
+    import torch
+
+    from paper_2609_29081_amd import af
+    from paper_2609_29081_amd import workloads as W
+
+    g, f = W.shock_tube_2d(2048, 1024)
+    S = af.Solver(g, mu=0.005, Pr=0.73, cfl_c=0.2, cfl_v=0.075,
+                  limiter=af.LIM_ALL | af.LIM_LEARNED)
+    P = torch.as_tensor(W.mlp_init(0), device=S.device)
+    S.af_set_blend_net(P)
+    U = S.to_device(W.make_state(g, f, 1.4))
+    st, n, t = S.af_run(U, 0.0, 1e30, steps, check_every=1)
+    torch.cuda.synchronize()
+    print("target done: status", st, "steps", n, flush=True)
 
 
 FP64_COUNTERS = ["SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_ADD_F64",
@@ -198,9 +221,12 @@ if __name__ == "__main__":
     ap.add_argument("--target", action="store_true")
     ap.add_argument("--mixed", action="store_true")
     ap.add_argument("--target-batch", action="store_true")
+    ap.add_argument("--target-learned", action="store_true")
     ap.add_argument("--out", default=os.path.join(ROOT, "gpurun_out", "traffic"))
     a = ap.parse_args()
-    if a.target_batch:
+    if a.target_learned:
+        target_learned()
+    elif a.target_batch:
         target_batch()
     elif a.target:
         target(mixed=a.mixed)

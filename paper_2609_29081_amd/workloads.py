@@ -233,6 +233,21 @@ def mlp_init(seed: int = 0, nin: int = 40, nh: int = 64) -> np.ndarray:
     return np.concatenate(parts).astype(np.float32)
 
 
+def balanced_rows(y: np.ndarray, seed: int = 0, ratio: float = 3.0, below: float = 0.999) -> np.ndarray:
+    """Row indices of a training set for the blend network: every row whose
+    target is below `below` (the faces where the smoothness blend acts, a
+    few per cent of a shock-tube grid) and `ratio` times as many of the
+    other rows, drawn without replacement from default_rng(seed), in a
+    shuffled order."""
+    rng = np.random.default_rng(seed)
+    y = np.asarray(y)
+    lo = np.flatnonzero(y < below)
+    hi = np.flatnonzero(~(y < below))
+    k = min(len(hi), int(ratio * max(len(lo), 1)))
+    idx = np.concatenate([lo, rng.choice(hi, size=k, replace=False)])
+    return idx[rng.permutation(len(idx))]
+
+
 def leblanc_1d(n: int = 800):
     """LeBlanc-type near-vacuum Riemann problem on [-0.5,0.5], outflow."""
     g = Grid(dim=1, n1=n, x0=-0.5, x1=0.5, bc=(OUTFLOW, OUTFLOW, OUTFLOW, OUTFLOW))

@@ -204,3 +204,16 @@ def test_any_blend_conserves_and_keeps_averages_admissible(seed):
     r = P1[0]
     p = (GAMMA - 1.0) * (P1[3] - 0.5 * (P1[1] ** 2 + P1[2] ** 2) / r)
     assert r.min() > 0.0 and p.min() > 0.0
+
+
+def test_blend_equal_to_theta_s_is_the_plain_stage():
+    g, f = W.shock_tube_2d(18, 12, rho_left=40.0)
+    U = W.make_state(g, f, GAMMA)
+    cfg = O.make_cfg(g, gamma=GAMMA, mu=0.005, Pr=0.73)
+    for _ in range(4):  # the gas at rest has no compression yet
+        assert O.step(cfg, U)[0] == 0
+    dt = 0.5 * O.dt(cfg, U)
+    plain, fl, ts, _ = O.fe(cfg, U, dt, want_theta=True)
+    assert (ts < 0.999).any()  # the smoothness blend acts somewhere
+    out, fb = O.fe_blend(cfg, U, dt, ts)
+    assert fb == fl and np.array_equal(out, plain)
