@@ -87,7 +87,7 @@ def main() -> int:
                     help="accepted steps per instance of the batched sweep")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-blend form")
-    ap.add_argument("--learned-train-steps", type=int, default=3000,
+    ap.add_argument("--learned-train-steps", type=int, default=20000,
                     help="Adam steps of the learned blend's training")
     args = ap.parse_args()
 

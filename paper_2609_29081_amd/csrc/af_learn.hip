@@ -42,10 +42,9 @@ constexpr int PK_W1 = 0, PK_W2 = PK_W1 + 2 * NH * NIN, PK_W3 = PK_W2 + 2 * NH * 
               PK_B1 = PK_W3 + 2 * NH, PK_B2 = PK_B1 + 4 * NH, PK_B3 = PK_B2 + 4 * NH;
 static_assert(PK_B3 + 4 <= (int)afi::kMlpPackedBytes, "packed weights");
 
+// round to nearest even (one hardware conversion on gfx950)
 __device__ __forceinline__ unsigned short to_bf16(float x) {
-  unsigned u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
-  return (unsigned short)(u >> 16);
+  return __builtin_bit_cast(unsigned short, (__bf16)x);
 }
 __device__ __forceinline__ float from_bf16(unsigned short h) {
   return __uint_as_float((unsigned)h << 16);
@@ -66,52 +65,68 @@ __device__ __forceinline__ void face_of(const G2& g, long f, int& d, int& i, int
   }
 }
 
-// (rho, u, v, p) of the cell average of cell (ci, cj), ci in [-2, n1+1]
-__device__ __forceinline__ void cell_prims(const G2& g, double gm1, const double* U, int ci, int cj,
-                                           float* P) {
-  double V[4];
-  raw_value(g, U, 2 * ci + 1, 2 * cj + 1, V);
-  const double u = V[1] / V[0], v = V[2] / V[0];
+// (rho, u, v, p) as FP32 from a cell average (FP64 arithmetic)
+__device__ __forceinline__ void prims_of(double gm1, const double* V, float* P) {
+  const double ir = 1.0 / V[0], u = V[1] * ir, v = V[2] * ir;
   P[0] = float(V[0]);
   P[1] = float(u);
   P[2] = float(v);
   P[3] = float(gm1 * (V[3] - 0.5 * V[0] * (u * u + v * v)));
 }
 
+// (rho, u, v, p) of the cell average of cell (ci, cj), ci in [-2, n1+1]
+__device__ __forceinline__ void cell_prims(const G2& g, double gm1, const double* U, int ci, int cj,
+                                           float* P) {
+  double V[4];
+  raw_value(g, U, 2 * ci + 1, 2 * cj + 1, V);
+  prims_of(gm1, V, P);
+}
+
 __device__ __forceinline__ float pos_or_tiny(float v) { return v > 1e-30f ? v : 1e-30f; }
 
-// the 40 features of face (d, i, j) from the primitives of its stencil cells:
+// features of face (d, i, j) from the primitives of its stencil cells:
 // cell(s, q, P) fills the (rho, u, v, p) of tangential offset s-1 and normal
-// offset q in (-2, -1, +1, +2)
-template <typename CellFn>
-__device__ __forceinline__ void features_of(int d, float gam, CellFn cell, float* o) {
-  float rho[3][4], un[3][4], ut[3][4], p[3][4];
-#pragma unroll
-  for (int s = 0; s < 3; ++s)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      float P[4];
-      cell(s, q, P);
-      rho[s][q] = P[0];
-      un[s][q] = d == 0 ? P[1] : P[2];
-      ut[s][q] = d == 0 ? P[2] : P[1];
-      p[s][q] = P[3];
-    }
-  const float rf = 0.5f * (rho[1][1] + rho[1][2]), pf = 0.5f * (p[1][1] + p[1][2]);
-  const float unf = 0.5f * (un[1][1] + un[1][2]), utf = 0.5f * (ut[1][1] + ut[1][2]);
+// offset q in (-2, -1, +1, +2).  Half h of the features (h = 0, 1; -1 for
+// all) is the triples of stencil cells 6h .. 6h+5 (cell 4s+q) and the
+// density ratios of q = 2h, 2h+1; put(n, value) receives feature n.
+template <typename CellFn, typename PutFn>
+__device__ __forceinline__ void features_of(int d, float gam, CellFn cell, PutFn put,
+                                            int h = -1) {
+  const int c0 = h < 0 ? 0 : 6 * h, c1 = h < 0 ? 12 : 6 * h + 6;
+  const int q0 = h < 0 ? 0 : 2 * h, q1 = h < 0 ? 4 : 2 * h + 2;
+  // face values from the two cells that adjoin the face
+  float A[4], B[4];
+  cell(1, 1, A);
+  cell(1, 2, B);
+  const float rf = 0.5f * (A[0] + B[0]), pf = 0.5f * (A[3] + B[3]);
+  const float unf = 0.5f * (d == 0 ? A[1] + B[1] : A[2] + B[2]);
+  const float utf = 0.5f * (d == 0 ? A[2] + B[2] : A[1] + B[1]);
   const float icf = 1.0f / sqrtf(gam * pos_or_tiny(pf) / pos_or_tiny(rf));
   const float ipf = 1.0f / pos_or_tiny(pf), irf = 1.0f / pos_or_tiny(rf);
 #pragma unroll
-  for (int s = 0; s < 3; ++s)
+  for (int c = 0; c < 12; ++c) {
+    if (c < c0 || c >= c1) continue;
+    float P[4];
+    cell(c / 4, c % 4, P);
+    const float un = d == 0 ? P[1] : P[2], ut = d == 0 ? P[2] : P[1];
+    put(3 * c, __logf(pos_or_tiny(P[3]) * ipf));
+    put(3 * c + 1, (un - unf) * icf);
+    put(3 * c + 2, (ut - utf) * icf);
+  }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int n = 3 * (4 * s + q);
-      o[n] = logf(pos_or_tiny(p[s][q]) * ipf);
-      o[n + 1] = (un[s][q] - unf) * icf;
-      o[n + 2] = (ut[s][q] - utf) * icf;
-    }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) o[36 + q] = logf(pos_or_tiny(rho[1][q]) * irf);
+  for (int q = 0; q < 4; ++q) {
+    if (q < q0 || q >= q1) continue;
+    float P[4];
+    cell(1, q, P);
+    put(36 + q, __logf(pos_or_tiny(P[0]) * irf));
+  }
+}
+
+// tanh from the exponential: 1 - 2 / (1 + e^{2x}), with the hardware
+// exponential and reciprocal (the result feeds bfloat16 operands; its error
+// is far below their rounding)
+__device__ __forceinline__ float tanh_fast(float x) {
+  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + __expf(2.0f * x));
 }
 
 // stencil cell (ci, cj) of face (d, i, j) at tangential offset s-1, normal
@@ -137,16 +152,13 @@ __global__ void __launch_bounds__(256) k_features(G2 g, double gm1, float gam,
        f += (long)gridDim.x * blockDim.x) {
     int d, i, j;
     face_of(g, f, d, i, j);
-    float o[NIN];
     features_of(d, gam,
                 [&](int s, int q, float* P) {
                   int ci, cj;
                   stencil_cell(d, i, j, s, q, ci, cj);
                   cell_prims(g, gm1, U, ci, cj, P);
                 },
-                o);
-#pragma unroll
-    for (int n = 0; n < NIN; ++n) out[f * NIN + n] = o[n];
+                [&](int n, float v) { out[f * NIN + n] = v; });
   }
 }
 
@@ -162,6 +174,9 @@ constexpr int IPAD = 8;                 // bf16 padding of LDS rows
 constexpr int FROW = NIN + IPAD;        // feature row (bf16)
 constexpr int HROW = NH + IPAD;         // hidden row (bf16)
 constexpr int CW = IB + 4;              // stencil cells per row
+constexpr int RROW = 33;                // FP32 row of the output reduction
+constexpr int W2ROW = NH + 4;           // padded LDS row of W2 (no bank conflicts)
+static_assert(32 * RROW * 4 <= 32 * HROW * 2, "the reduction fits a wave's hidden rows");
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -170,15 +185,12 @@ struct InferShared {
   float cell[4][4][CW];                 // [component][row][column]
   unsigned short feat[IB * FROW];
   unsigned short hid[IB * HROW];
+  unsigned short w2[NH * W2ROW];        // layer-2 weights (bfloat16, padded rows)
 };
 
+// four consecutive bfloat16 values, 8-byte aligned (one 64-bit load)
 __device__ __forceinline__ bf16x4 load4(const unsigned short* p) {
-  bf16x4 r;
-  r[0] = (short)p[0];
-  r[1] = (short)p[1];
-  r[2] = (short)p[2];
-  r[3] = (short)p[3];
-  return r;
+  return *reinterpret_cast<const bf16x4*>(p);
 }
 
 __global__ void __launch_bounds__(256) k_infer(G2 g, double gm1, float gam,
@@ -196,15 +208,16 @@ __global__ void __launch_bounds__(256) k_infer(G2 g, double gm1, float gam,
   const float* b2 = (const float*)(pk + PK_B2);
   const float b3 = *(const float*)(pk + PK_B3);
   // B operands: lane holds W[n = 32 nb + c32][k = 8 kb + 4 h + 0..3]
-  bf16x4 B1[5][2], B2[8][2];
+  // W1 stays in registers (20 VGPRs); W2 is read from LDS per use, which
+  // keeps the kernel at three waves per SIMD
+  bf16x4 B1[5][2];
 #pragma unroll
   for (int kb = 0; kb < 5; ++kb)
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb) B1[kb][nb] = load4(W1 + (32 * nb + c32) * NIN + 8 * kb + 4 * h);
-#pragma unroll
-  for (int kb = 0; kb < 8; ++kb)
-#pragma unroll
-    for (int nb = 0; nb < 2; ++nb) B2[kb][nb] = load4(W2 + (32 * nb + c32) * NH + 8 * kb + 4 * h);
+  for (int e = tid; e < NH * NH / 4; e += 256)
+    *reinterpret_cast<bf16x4*>(S.w2 + (e / (NH / 4)) * W2ROW + 4 * (e % (NH / 4))) =
+        reinterpret_cast<const bf16x4*>(W2)[e];
   float bias1[2], bias2[2], ow[2];
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) {
@@ -214,39 +227,68 @@ __global__ void __launch_bounds__(256) k_infer(G2 g, double gm1, float gam,
   }
   const long nfx = (long)g.n2 * (g.n1 + 1);
   const long nbx = (long)g.n2 * nsegx;
-  for (long blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
-    // the block: direction, row, first face along the row, face count
-    int d, row, i0, cnt;
+  // block blk: direction, row, first face along the row, face count, and its
+  // stencil cells: x-faces need columns i0-2 .. i0+cnt and rows row-1..row+1,
+  // y-faces columns i0-1 .. i0+cnt and rows row-2..row+1
+  struct Blk {
+    int d, row, i0, cnt, ncol, nrow, c0, r0;
+  };
+  auto block_of = [&](long blk) {
+    Blk b;
     if (blk < nbx) {
-      d = 0;
-      row = (int)(blk / nsegx);
-      i0 = (int)(blk % nsegx) * IB;
-      cnt = min(IB, g.n1 + 1 - i0);
+      b.d = 0;
+      b.row = (int)(blk / nsegx);
+      b.i0 = (int)(blk % nsegx) * IB;
+      b.cnt = min(IB, g.n1 + 1 - b.i0);
     } else {
-      d = 1;
+      b.d = 1;
       const long r = blk - nbx;
-      row = (int)(r / nsegy);
-      i0 = (int)(r % nsegy) * IB;
-      cnt = min(IB, g.n1 - i0);
+      b.row = (int)(r / nsegy);
+      b.i0 = (int)(r % nsegy) * IB;
+      b.cnt = min(IB, g.n1 - b.i0);
     }
-    // stencil cells: x-faces need columns i0-2 .. i0+cnt and rows row-1..row+1;
-    // y-faces columns i0-1 .. i0+cnt and rows row-2..row+1
-    const int ncol = d == 0 ? cnt + 3 : cnt + 2, nrow = d == 0 ? 3 : 4;
-    const int c0 = d == 0 ? i0 - 2 : i0 - 1, r0 = d == 0 ? row - 1 : row - 2;
-    __syncthreads();  // the previous block is done with the LDS
-    for (int e = tid; e < ncol * nrow; e += 256) {
-      const int rr = e / ncol, cc = e % ncol;
-      float P[4];
-      cell_prims(g, gm1, U, c0 + cc, r0 + rr, P);
+    b.ncol = b.d == 0 ? b.cnt + 3 : b.cnt + 2;
+    b.nrow = b.d == 0 ? 3 : 4;
+    b.c0 = b.d == 0 ? b.i0 - 2 : b.i0 - 1;
+    b.r0 = b.d == 0 ? b.row - 1 : b.row - 2;
+    return b;
+  };
+  // the FP64 averages of a block's stencil cells, three per thread at most
+  // (4 x 130 cells), loaded one block ahead so that the loads complete while
+  // the previous block runs through the network
+  constexpr int CPT = (4 * (IB + 2) + 255) / 256;
+  static_assert(3 * (IB + 3) <= CPT * 256, "cells per thread");
+  double pre[CPT][4];
+  auto fetch = [&](const Blk& b) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) S.cell[k][rr][cc] = P[k];
+    for (int r = 0; r < CPT; ++r) {
+      const int e = tid + 256 * r;
+      if (e < b.ncol * b.nrow) raw_value(g, U, 2 * (b.c0 + e % b.ncol) + 1, 2 * (b.r0 + e / b.ncol) + 1, pre[r]);
+    }
+  };
+  long blk = blockIdx.x;
+  if (blk < nblocks) fetch(block_of(blk));
+  for (; blk < nblocks; blk += gridDim.x) {
+    const Blk B = block_of(blk);
+    const int d = B.d, row = B.row, i0 = B.i0, cnt = B.cnt, c0 = B.c0, r0 = B.r0;
+    __syncthreads();  // the previous block is done with the cell and feature arrays
+#pragma unroll
+    for (int r = 0; r < CPT; ++r) {
+      const int e = tid + 256 * r;
+      if (e < B.ncol * B.nrow) {
+        float P[4];
+        prims_of(gm1, pre[r], P);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) S.cell[k][e / B.ncol][e % B.ncol] = P[k];
+      }
     }
     __syncthreads();
-    if (tid < IB) {
-      unsigned short* fo = S.feat + tid * FROW;
-      if (tid < cnt) {
-        const int i = i0 + tid;
-        float o[NIN];
+    {
+      // two threads per face, one half of its features each
+      const int fl = tid & (IB - 1), half = tid / IB;
+      unsigned short* fo = S.feat + fl * FROW;
+      if (fl < cnt) {
+        const int i = i0 + fl;
         features_of(d, gam,
                     [&](int s, int q, float* P) {
                       int ci, cj;
@@ -254,15 +296,13 @@ __global__ void __launch_bounds__(256) k_infer(G2 g, double gm1, float gam,
 #pragma unroll
                       for (int k = 0; k < 4; ++k) P[k] = S.cell[k][cj - r0][ci - c0];
                     },
-                    o);
-#pragma unroll
-        for (int n = 0; n < NIN; ++n) fo[n] = to_bf16(o[n]);
+                    [&](int n, float v) { fo[n] = to_bf16(v); }, half);
       } else {
-#pragma unroll
-        for (int n = 0; n < NIN; ++n) fo[n] = 0;
+        for (int n = half; n < NIN; n += 2) fo[n] = 0;
       }
     }
     __syncthreads();
+    if (blk + gridDim.x < nblocks) fetch(block_of(blk + gridDim.x));
     // the wave's 32 faces
     const unsigned short* fa = S.feat + (32 * wave) * FROW;
     unsigned short* hw = S.hid + (32 * wave) * HROW;
@@ -285,7 +325,7 @@ __global__ void __launch_bounds__(256) k_infer(G2 g, double gm1, float gam,
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int m = 8 * (r >> 2) + 4 * h + (r & 3);
-        hw[m * HROW + 32 * nb + c32] = to_bf16(tanhf(acc[nb][r] + bias1[nb]));
+        hw[m * HROW + 32 * nb + c32] = to_bf16(tanh_fast(acc[nb][r] + bias1[nb]));
       }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
@@ -299,23 +339,28 @@ __global__ void __launch_bounds__(256) k_infer(G2 g, double gm1, float gam,
       const bf16x4 a = load4(hw + c32 * HROW + 8 * kb + 4 * h);
 #pragma unroll
       for (int nb = 0; nb < 2; ++nb)
-        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, B2[kb][nb], acc[nb], 0, 0, 0);
+        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(
+            a, load4(S.w2 + (32 * nb + c32) * W2ROW + 8 * kb + 4 * h), acc[nb], 0, 0, 0);
     }
-    // z = w3 . tanh(.) + b3: lane sums its two columns, then the 32 lanes of
-    // its half (same rows) reduce
-    float zp[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r)
-      zp[r] = ow[0] * tanhf(acc[0][r] + bias2[0]) + ow[1] * tanhf(acc[1][r] + bias2[1]);
-#pragma unroll
-    for (int off = 16; off >= 1; off >>= 1)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) zp[r] += __shfl_xor(zp[r], off, 64);
+    // z = w3 . tanh(.) + b3: each lane sums its two columns of its 16 rows
+    // into an FP32 table in the wave's (now consumed) hidden rows, then lane
+    // m < 32 adds up row m
+    float* red = reinterpret_cast<float*>(hw);  // [32][RROW]
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int m = 32 * wave + 8 * (r >> 2) + 4 * h + (r & 3);
-      if (c32 == r && m < cnt) {
-        const float z = zp[r] + b3;
+      const int m = 8 * (r >> 2) + 4 * h + (r & 3);
+      red[m * RROW + c32] =
+          ow[0] * tanh_fast(acc[0][r] + bias2[0]) + ow[1] * tanh_fast(acc[1][r] + bias2[1]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    if (h == 0) {
+      float z = b3;
+#pragma unroll
+      for (int k = 0; k < 32; ++k) z += red[c32 * RROW + k];
+      const int m = 32 * wave + c32;
+      if (m < cnt) {
         const long f = (d == 0 ? 0 : nfx) + (long)row * (d == 0 ? g.n1 + 1 : g.n1) + i0 + m;
         theta[f] = fminf(fmaxf(z, 0.0f), 1.0f);
       }
@@ -531,12 +576,31 @@ hipError_t mlp_pack(const float* params, void* packed, hipStream_t s) {
   return hipGetLastError();
 }
 
+// persistent workgroups of the inference kernel: as many as are resident
+static int infer_workgroups() {
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  if (cache[dev] == 0) {
+    int cus = 0, per = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_infer, 256, 0) != hipSuccess ||
+        per <= 0)
+      per = 1;
+    cache[dev] = cus * per;
+  }
+  return cache[dev];
+}
+
 hipError_t blend_infer(const Geo& geo, const Phys& ph, const double* U, const void* packed,
                        float* theta, hipStream_t s, Timer* tm) {
   const G2 g = stage_geo(geo);
   const int nsegx = (g.n1 + 1 + IB - 1) / IB, nsegy = (g.n1 + IB - 1) / IB;
   const long nblocks = (long)g.n2 * nsegx + (long)(g.n2 + 1) * nsegy;
-  long grid = nblocks < 4096 ? nblocks : 4096;
+  const long nwg = infer_workgroups();
+  const long grid = nblocks < nwg ? nblocks : nwg;
   AFI_TIMED(tm, 8, s,
             hipLaunchKernelGGL(k_infer, dim3((unsigned)grid), dim3(256), 0, s, g, ph.gm1,
                                float(ph.gam), U, (const unsigned char*)packed, theta, nsegx,
