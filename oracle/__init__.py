@@ -34,7 +34,8 @@ class Cfg(C.Structure):
                 ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
                 ("gamma", C.c_double), ("mu", C.c_double), ("Pr", C.c_double),
                 ("Cs", C.c_double), ("cfl_c", C.c_double), ("cfl_v", C.c_double),
-                ("limiter", C.c_int), ("bc", C.c_int * 4), ("max_halvings", C.c_int)]
+                ("limiter", C.c_int), ("bc", C.c_int * 4), ("max_halvings", C.c_int),
+                ("rk", C.c_int)]
 
 
 _lib = None
@@ -91,7 +92,7 @@ def _p(a: np.ndarray):
 
 
 def make_cfg(grid, gamma=1.4, mu=1e-3, Pr=0.72, limiter=LIM_ALL, cfl_c=0.2, cfl_v=0.075,
-             Cs=1.0, max_halvings=40) -> Cfg:
+             Cs=1.0, max_halvings=40, rk=3) -> Cfg:
     c = Cfg()
     c.dim, c.n1, c.n2 = grid.dim, grid.n1, grid.n2
     c.x0, c.x1, c.y0, c.y1 = grid.x0, grid.x1, grid.y0, grid.y1
@@ -101,6 +102,7 @@ def make_cfg(grid, gamma=1.4, mu=1e-3, Pr=0.72, limiter=LIM_ALL, cfl_c=0.2, cfl_
     for k in range(4):
         c.bc[k] = int(grid.bc[k])
     c.max_halvings = max_halvings
+    c.rk = rk
     return c
 
 
@@ -162,7 +164,8 @@ def dt(cfg: Cfg, U: np.ndarray) -> float:
 
 
 def step(cfg: Cfg, U: np.ndarray, dt: float = 0.0, t: float = 0.0, t_final: float = 1e30):
-    """one SSP-RK3 step in place; returns (status, dt_used, halvings, flags)"""
+    """one step in place (SSP-RK3, or SSP-RK54 when cfg.rk == 54); returns
+    (status, dt_used, halvings, flags)"""
     assert U.dtype == np.float64 and U.flags.c_contiguous
     dtu = C.c_double()
     h = C.c_int()

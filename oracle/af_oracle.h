@@ -58,6 +58,7 @@ typedef struct orc_cfg {
   int limiter;          /* ORC_LIM_* bits */
   int bc[4];            /* x-low, x-high, y-low, y-high */
   int max_halvings;
+  int rk;               /* time integrator: 3 (SSP-RK3) or 54 (SSP-RK54) */
 } orc_cfg;
 
 /* sizes (in doubles) */
@@ -94,8 +95,10 @@ void orc_rhs(const orc_cfg* c, const double* U, double* dUdt);
 /* CFL time step over cell averages */
 double orc_dt(const orc_cfg* c, const double* U);
 
-/* one SSP-RK3 step with the halving retry.  dt<=0 -> CFL dt.  dt is clipped
- * to t_final - t.  Returns 0 on success, nonzero if max_halvings exceeded. */
+/* one step with the halving retry, by SSP-RK3 or (c->rk == 54) the
+ * five-stage fourth-order SSP method Sec. 2.3 names.  dt<=0 -> CFL dt.  dt is
+ * clipped to t_final - t.  Returns 0 on success, nonzero if max_halvings
+ * exceeded. */
 int orc_step(const orc_cfg* c, double* U, double dt, double t, double t_final,
              double* dt_used, int* halvings, int* flags_out);
 
