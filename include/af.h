@@ -99,6 +99,10 @@ typedef struct af_params {
   int limiter;          /* AF_LIM_* bits                                          */
   int max_halvings;     /* retries of a step with halved dt (>= 0)               */
   int precision;        /* AF_PREC_FP64, or AF_PREC_MIXED (2D only)               */
+  int rk;               /* time integrator of af_step / af_run: 3 (SSP-RK3) or 54
+                           (SSP-RK54, the five-stage fourth-order SSP method of
+                           Sec. 2.3; the paper pairs it with cfl_c = 1.04/d and
+                           cfl_v = 0.33/d)                                        */
 } af_params;
 
 /* arithmetic of the 2D stage.  AF_PREC_MIXED: the stencils, fluxes and
@@ -111,7 +115,8 @@ enum { AF_PREC_FP64 = 0, AF_PREC_MIXED = 1 };
 typedef struct af_ctx af_ctx;
 
 /* Fill p with defaults: 2D 64x64 on [0,1]^2, gamma 1.4, mu 1e-3, Pr 0.72,
- * cfl_c 0.2, cfl_v 0.075, Cs 1, all limiters, max_halvings 40, FP64. */
+ * cfl_c 0.2, cfl_v 0.075, Cs 1, all limiters, max_halvings 40, FP64,
+ * SSP-RK3. */
 af_status af_default_params(af_params* p);
 
 /* Validate p and create a context (host memory only; no device work).
@@ -159,7 +164,9 @@ af_status af_rk_stage(af_ctx* ctx, int k, const double* dt_dev, double dt_host,
 af_status af_cfl_dt(af_ctx* ctx, const double* U, double t, double t_final, double* dt_dev,
                     void* ws, void* stream);
 
-/* One full SSP-RK3 step of U in place, synchronous.  dt <= 0 selects the CFL
+/* One full step of U in place (SSP-RK3, or SSP-RK54 when params.rk is 54:
+ * five forward-Euler stages with their own fractions of dt and two state
+ * combinations), synchronous.  dt <= 0 selects the CFL
  * step.  dt is clipped to t_final - t.  If any flag is raised the state is
  * restored and the step recomputed with dt/2, up to max_halvings times
  * (Remark on the time step, Sec. 3.4): then AF_E_PP (or AF_E_NONFINITE) is

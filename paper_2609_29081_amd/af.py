@@ -35,7 +35,8 @@ class Params(C.Structure):
                 ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
                 ("gamma", C.c_double), ("mu", C.c_double), ("Pr", C.c_double),
                 ("cfl_c", C.c_double), ("cfl_v", C.c_double), ("Cs", C.c_double),
-                ("limiter", C.c_int), ("max_halvings", C.c_int), ("precision", C.c_int)]
+                ("limiter", C.c_int), ("max_halvings", C.c_int), ("precision", C.c_int),
+                ("rk", C.c_int)]
 
 
 _lib = None
@@ -147,14 +148,14 @@ class Solver:
     workspace.  States are flat float64 CUDA tensors of length state_len."""
 
     def __init__(self, grid: W.Grid, gamma=1.4, mu=1e-3, Pr=0.72, cfl_c=0.2, cfl_v=0.075,
-                 limiter=LIM_ALL, Cs=1.0, max_halvings=40, precision=0, device="cuda:0"):
+                 limiter=LIM_ALL, Cs=1.0, max_halvings=40, precision=0, rk=3, device="cuda:0"):
         p = Params()
         _check(lib().af_default_params(C.byref(p)))
         p.dim, p.n1, p.n2 = grid.dim, grid.n1, grid.n2
         p.x0, p.x1, p.y0, p.y1 = grid.x0, grid.x1, grid.y0, grid.y1
         p.gamma, p.mu, p.Pr = gamma, mu, Pr
         p.cfl_c, p.cfl_v, p.Cs = cfl_c, cfl_v, Cs
-        p.limiter, p.max_halvings, p.precision = limiter, max_halvings, precision
+        p.limiter, p.max_halvings, p.precision, p.rk = limiter, max_halvings, precision, rk
         self.grid = grid
         self.params = p
         h = C.c_void_p()

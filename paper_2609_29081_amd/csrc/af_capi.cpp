@@ -172,12 +172,21 @@ const afi::StageCoef kCoef[3] = {{0.0, 1.0, 1, 0}, {0.75, 0.25, 0, 0}, {1.0 / 3.
 
 // in_step: the stage is part of a step attempt (af_step, af_run), whose
 // output is discarded once a flag is raised, so it may stop early
-hipError_t launch_stage(const afi::Geo& g, const afd::Phys& ph, const afi::Work& w, int k,
-                        const double* Un, const double* Uk, double* Uout, const double* dt_dev,
-                        double dt_host, hipStream_t s, afi::Timer* tm, bool in_step = true) {
+// one stage with coefficients sc: Uout = sc.a Un + sc.b FE(Uk, sc.dt_mul dt)
+hipError_t launch_coef(const afi::Geo& g, const afd::Phys& ph, const afi::Work& w,
+                       afi::StageCoef sc, const double* Un, const double* Uk, double* Uout,
+                       const double* dt_dev, double dt_host, hipStream_t s, afi::Timer* tm) {
   if (!Un) Un = Uk;
-  afi::StageCoef sc = kCoef[k];
-  sc.skip_flagged = in_step ? 1 : 0;
+  if (sc.dt_mul != 1.0) {
+    // the stage's step as its own device scalar (the spare workspace slot)
+    if (dt_dev) {
+      hipError_t e = afi::scaled_scalar(w.scal + 3, dt_dev, sc.dt_mul, s);
+      if (e != hipSuccess) return e;
+      dt_dev = w.scal + 3;
+    } else {
+      dt_host *= sc.dt_mul;
+    }
+  }
   if (g.dim == 2 && (ph.lim & afd::LIM_LEARNED)) {
     // the network's blend from this stage's input, then the stage
     if (!w.net) return hipErrorInvalidValue;
@@ -188,6 +197,59 @@ hipError_t launch_stage(const afi::Geo& g, const afd::Phys& ph, const afi::Work&
   }
   return g.dim == 1 ? afi::stage1d(g, ph, w, Un, Uk, Uout, dt_dev, dt_host, sc, s, tm)
                     : afi::stage2d(g, ph, w, Un, Uk, Uout, dt_dev, dt_host, sc, s, tm);
+}
+
+hipError_t launch_stage(const afi::Geo& g, const afd::Phys& ph, const afi::Work& w, int k,
+                        const double* Un, const double* Uk, double* Uout, const double* dt_dev,
+                        double dt_host, hipStream_t s, afi::Timer* tm, bool in_step = true) {
+  afi::StageCoef sc = kCoef[k];
+  sc.skip_flagged = in_step ? 1 : 0;
+  return launch_coef(g, ph, w, sc, Un, Uk, Uout, dt_dev, dt_host, s, tm);
+}
+
+// SSP-RK54 (Sec. 2.3 names the five-stage, fourth-order SSP method; these
+// are Spiteri and Ruuth's SSPRK(5,4) coefficients in Shu-Osher form).  With
+// E_k = FE(u_k, c_k dt): u1 = E0, u2 = a20 u0 + a21 E1, u3 = a30 u0 + a32 E2,
+// u4 = a40 u0 + a43 E3, u5 = a52 u2 + a53 E3 + a54 E4, where c_3 = b43/a43
+// = b53/a53 makes E3 one evaluation shared by u4 and u5.
+constexpr double kA20 = 0.444370493651235, kA21 = 0.555629506348765;
+constexpr double kA30 = 0.620101851488403, kA32 = 0.379898148511597;
+constexpr double kA40 = 0.178079954393132, kA43 = 0.821920045606868;
+constexpr double kA52 = 0.517231671970585, kA53 = 0.096059710526147;
+constexpr double kA54 = 0.386708617503269;
+constexpr double kB10 = 0.391752226571890, kB21 = 0.368410593050371;
+constexpr double kB32 = 0.251891774271694, kB43 = 0.544974750228521;
+constexpr double kB54 = 0.226007483236906;
+
+// one SSP-RK54 attempt from u0 (kept) through buffers A, B into X
+hipError_t rk54(const afi::Geo& g, const afd::Phys& ph, const afi::Work& w, const double* u0,
+                double* A, double* B, double* X, const double* dt_dev, double dt, hipStream_t s,
+                afi::Timer* tm) {
+  auto coef = [](double a, double b, double mul) {
+    afi::StageCoef c{};
+    c.a = a;
+    c.b = b;
+    c.first = a == 0.0 ? 1 : 0;
+    c.skip_flagged = 1;
+    c.dt_mul = mul;
+    return c;
+  };
+  const long n = g.state_len;
+  hipError_t e;
+  if ((e = launch_coef(g, ph, w, coef(0.0, 1.0, kB10), u0, u0, A, dt_dev, dt, s, tm)) != hipSuccess)
+    return e;  // A = u1
+  if ((e = launch_coef(g, ph, w, coef(kA20, kA21, kB21 / kA21), u0, A, B, dt_dev, dt, s, tm)) !=
+      hipSuccess)
+    return e;  // B = u2
+  if ((e = launch_coef(g, ph, w, coef(kA30, kA32, kB32 / kA32), u0, B, A, dt_dev, dt, s, tm)) !=
+      hipSuccess)
+    return e;  // A = u3
+  if ((e = launch_coef(g, ph, w, coef(0.0, 1.0, kB43 / kA43), u0, A, X, dt_dev, dt, s, tm)) !=
+      hipSuccess)
+    return e;  // X = E3
+  if ((e = afi::lincomb(A, kA40, u0, kA43, X, n, s)) != hipSuccess) return e;   // A = u4
+  if ((e = afi::lincomb(B, kA52, B, kA53, X, n, s)) != hipSuccess) return e;    // B = a52 u2 + a53 E3
+  return launch_coef(g, ph, w, coef(1.0, kA54, kB54 / kA54), B, A, X, dt_dev, dt, s, tm);
 }
 
 hipError_t launch_cfl(const af_ctx* c, const afi::Geo& g, const afi::Work& w, const double* U,
@@ -290,6 +352,7 @@ af_status af_default_params(af_params* p) {
   p->limiter = AF_LIM_ALL;
   p->max_halvings = 40;
   p->precision = AF_PREC_FP64;
+  p->rk = 3;
   return AF_OK;
 }
 
@@ -314,6 +377,7 @@ af_status af_init_grid(const af_params* p, af_ctx** out) {
   if (p->max_halvings < 0) return fail(AF_E_ARG, "max_halvings must be >= 0");
   if (p->precision != AF_PREC_FP64 && p->precision != AF_PREC_MIXED)
     return fail(AF_E_ARG, "precision must be AF_PREC_FP64 or AF_PREC_MIXED");
+  if (p->rk != 3 && p->rk != 54) return fail(AF_E_ARG, "rk must be 3 or 54 (got %d)", p->rk);
   if (p->precision == AF_PREC_MIXED && p->dim != 2)
     return fail(AF_E_ARG, "the mixed-precision stage exists for 2D only");
   af_ctx* c = new (std::nothrow) af_ctx;
@@ -492,7 +556,10 @@ af_status af_step(af_ctx* c, double* U, void* ws, void* stream, double dt, doubl
   int h;
   for (h = 0; h <= c->p.max_halvings; ++h) {
     AF_HIP(afi::clear_flags(w, s));
-    AF_HIP(rk3(g, ph, w, w.SAVE, U, nullptr, dt, s, c->timer));
+    if (c->p.rk == 54)
+      AF_HIP(rk54(g, ph, w, w.SAVE, w.S1, w.S2, U, nullptr, dt, s, c->timer));
+    else
+      AF_HIP(rk3(g, ph, w, w.SAVE, U, nullptr, dt, s, c->timer));
     af_status st = read_flags(w, s, &fl);
     if (st != AF_OK) return st;
     if (fl == 0) break;
@@ -520,9 +587,12 @@ af_status af_run(af_ctx* c, double* U, void* ws, void* stream, double t0, double
   const afi::Work w = work_of(c, g, ws);
   const hipStream_t s = (hipStream_t)stream;
   const afd::Phys ph = physics(c->p);
-  // the current state rotates through U, S1, S2: a step reads `cur` and
-  // writes its stages to the other two, so `cur` survives a rejected step
-  double* bufs[3] = {U, w.S1, w.S2};
+  // the current state rotates through U, S1, S2 (and S3 for SSP-RK54): a
+  // step reads `cur` and writes its stages to the others, so `cur`
+  // survives a rejected step
+  const bool rk54s = c->p.rk == 54;
+  double* bufs[4] = {U, w.S1, w.S2, w.S3};
+  auto next = [&](int from) { return rk54s ? (from + 3) % 4 : (from + 1) % 3; };
   int cur = 0;
   double t = t0;
   long done = 0;
@@ -536,6 +606,9 @@ af_status af_run(af_ctx* c, double* U, void* ws, void* stream, double t0, double
     return AF_OK;
   };
   auto three_stages = [&](int from) -> hipError_t {
+    if (rk54s)
+      return rk54(g, ph, w, bufs[from], bufs[(from + 1) % 4], bufs[(from + 2) % 4],
+                  bufs[(from + 3) % 4], w.scal, 0.0, s, c->timer);
     const int a = (from + 1) % 3, b = (from + 2) % 3;
     hipError_t e;
     if ((e = launch_stage(g, ph, w, 0, bufs[from], bufs[from], bufs[a], w.scal, 0.0, s,
@@ -559,7 +632,7 @@ af_status af_run(af_ctx* c, double* U, void* ws, void* stream, double t0, double
         AF_HIP(launch_cfl(c, g, w, bufs[c2], 0.0, w.scal + 1, t_final, w.scal, s));
         AF_HIP(three_stages(c2));
         AF_HIP(afi::advance_time(w, s));
-        c2 = (c2 + 1) % 3;
+        c2 = next(c2);
       }
       if ((status = read_back()) != AF_OK) break;
       if (fl == 0) {
@@ -594,7 +667,7 @@ af_status af_run(af_ctx* c, double* U, void* ws, void* stream, double t0, double
       AF_HIP(afi::set_scalar(w.scal + 2, 0.0, s));
       AF_HIP(afi::advance_time(w, s));
       t = sc[1] + sc[0];
-      cur = (cur + 1) % 3;
+      cur = next(cur);
       ++done;
     }
     if (status != AF_OK) break;

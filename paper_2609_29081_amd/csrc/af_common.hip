@@ -137,6 +137,16 @@ __global__ void k_set(double* p, double v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = v;
 }
 
+__global__ void __launch_bounds__(kBlock) k_lincomb(double* out, double a, const double* x,
+                                                   double b, const double* y, long n) {
+  for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x)
+    out[q] = a * x[q] + b * y[q];
+}
+
+__global__ void k_scaled(double* dst, const double* src, double f) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = f * src[0];
+}
+
 __global__ void k_scale(double* p, double f) {
   if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = p[0] * f;
 }
@@ -285,6 +295,7 @@ size_t workspace_layout(const Geo& g, Work* w, char* base) {
   }
   r.S1 = (double*)take(sizeof(double) * g.state_len);
   r.S2 = (double*)take(sizeof(double) * g.state_len);
+  r.S3 = (double*)take(sizeof(double) * g.state_len);
   r.SAVE = (double*)take(sizeof(double) * g.state_len);
   if (g.dim == 2) {
     r.blend = (float*)take(sizeof(float) * (nfx + nfy));
@@ -382,6 +393,20 @@ hipError_t batch_open(BatchInst* inst, int n, const double* partial, int* n_acti
 
 hipError_t batch_decide(BatchInst* inst, int n, int* n_active, hipStream_t s) {
   hipLaunchKernelGGL(k_batch_decide, dim3(1), dim3(kBlock), 0, s, inst, n, n_active);
+  return hipGetLastError();
+}
+
+hipError_t lincomb(double* out, double a, const double* x, double b, const double* y, long n,
+                   hipStream_t s) {
+  long nb = (n + kBlock - 1) / kBlock;
+  if (nb > 4096) nb = 4096;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(k_lincomb, dim3((unsigned)nb), dim3(kBlock), 0, s, out, a, x, b, y, n);
+  return hipGetLastError();
+}
+
+hipError_t scaled_scalar(double* dst, const double* src, double f, hipStream_t s) {
+  hipLaunchKernelGGL(k_scaled, dim3(1), dim3(64), 0, s, dst, src, f);
   return hipGetLastError();
 }
 

@@ -94,6 +94,7 @@ struct Work {
   double* FY;        // limited y-face fluxes (2D)
   double* S1;        // stage buffers and checkpoint (one state each)
   double* S2;
+  double* S3;        // fourth stage buffer of SSP-RK54
   double* SAVE;
   // 2D learned blend: one coefficient per face, and the network's weights as
   // the inference kernel reads them (bfloat16 W1, W2, w3; FP32 biases)
@@ -117,6 +118,8 @@ struct StageCoef {
   // place per face, or NULL
   const float* blend;
   float* ts_out;
+  // the forward-Euler step is dt_mul * dt (the stages of SSP-RK54)
+  double dt_mul = 1.0;
 };
 
 size_t workspace_layout(const Geo& g, Work* w, char* base);
@@ -166,6 +169,11 @@ hipError_t cfl_dt(const Geo& g, const afd::Phys& ph, double cfl_c, double cfl_v,
 hipError_t advance_time(const Work& w, hipStream_t s);
 hipError_t clear_flags(const Work& w, hipStream_t s);
 hipError_t copy_state(double* dst, const double* src, long n, hipStream_t s);
+// out = a x + b y over n values (out may be x or y)
+hipError_t lincomb(double* out, double a, const double* x, double b, const double* y, long n,
+                   hipStream_t s);
+// *dst = f * *src (device scalars)
+hipError_t scaled_scalar(double* dst, const double* src, double f, hipStream_t s);
 hipError_t set_scalar(double* dst, double v, hipStream_t s);
 hipError_t scale_scalar(double* dst, double f, hipStream_t s);
 // number of DOF sites of state U whose density or pressure is not positive
