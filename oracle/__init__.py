@@ -16,6 +16,7 @@ SRC = os.path.join(HERE, "af_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 LIM_SMOOTH, LIM_PP, LIM_POINT, LIM_CENTRE, LIM_LOWONLY = 1, 2, 4, 8, 16
+DIRICHLET = 4
 LIM_ALL = LIM_SMOOTH | LIM_PP | LIM_POINT | LIM_CENTRE
 FLAG_CELL_LOW, FLAG_POINT_LOW, FLAG_NONFINITE = 1, 2, 4
 
@@ -35,7 +36,7 @@ class Cfg(C.Structure):
                 ("gamma", C.c_double), ("mu", C.c_double), ("Pr", C.c_double),
                 ("Cs", C.c_double), ("cfl_c", C.c_double), ("cfl_v", C.c_double),
                 ("limiter", C.c_int), ("bc", C.c_int * 4), ("max_halvings", C.c_int),
-                ("rk", C.c_int)]
+                ("rk", C.c_int), ("bcstate", (C.c_double * 3) * 2)]
 
 
 _lib = None
@@ -92,7 +93,7 @@ def _p(a: np.ndarray):
 
 
 def make_cfg(grid, gamma=1.4, mu=1e-3, Pr=0.72, limiter=LIM_ALL, cfl_c=0.2, cfl_v=0.075,
-             Cs=1.0, max_halvings=40, rk=3) -> Cfg:
+             Cs=1.0, max_halvings=40, rk=3, bcstate=None) -> Cfg:
     c = Cfg()
     c.dim, c.n1, c.n2 = grid.dim, grid.n1, grid.n2
     c.x0, c.x1, c.y0, c.y1 = grid.x0, grid.x1, grid.y0, grid.y1
@@ -103,6 +104,10 @@ def make_cfg(grid, gamma=1.4, mu=1e-3, Pr=0.72, limiter=LIM_ALL, cfl_c=0.2, cfl_
         c.bc[k] = int(grid.bc[k])
     c.max_halvings = max_halvings
     c.rk = rk
+    if bcstate is not None:
+        for side in range(2):
+            for k in range(3):
+                c.bcstate[side][k] = float(bcstate[side][k])
     return c
 
 

@@ -411,9 +411,15 @@ static void build1(lat1* L) {
     }
     for (int k = 0; k < 3; ++k) L1(L->LU, k, X) = U[k];
   }
-  /* ghost sites as images */
+  /* ghost sites as images; beyond a Dirichlet side, its state (the paper
+     prescribes boundary values there, Sec. 4) */
   for (int X = -GM; X <= 2 * n + GM; ++X) {
     if (X >= 0 && X <= 2 * n) continue;
+    const int side = X < 0 ? 0 : 1;
+    if (c->bc[side] == ORC_DIRICHLET) {
+      for (int k = 0; k < 3; ++k) L1(L->LU, k, X) = c->bcstate[side][k];
+      continue;
+    }
     int kind;
     int Xi = axis_image(X, n, c->bc[0], c->bc[1], &kind);
     double sg[4] = {1.0, 1.0, 1.0};
@@ -439,6 +445,11 @@ static void build1(lat1* L) {
     }
   /* cell averages with two ghost cells */
   for (int i = -2; i <= n + 1; ++i) {
+    const int side = i < 0 ? 0 : 1;
+    if ((i < 0 || i >= n) && c->bc[side] == ORC_DIRICHLET) {
+      for (int k = 0; k < 3; ++k) C1(k, i) = c->bcstate[side][k];
+      continue;
+    }
     int kind;
     int Xi = axis_image(2 * i + 1, n, c->bc[0], c->bc[1], &kind);
     double sg[4] = {1.0, 1.0, 1.0};
@@ -596,6 +607,11 @@ static int fe1(const orc_cfg* c, const double* U, double dt, double* Ufe, double
     }
     if (k == 0) project_wall(c, 0, wall_kind(c->bc[0]), out);
     if (k == n) project_wall(c, 0, wall_kind(c->bc[1]), out);
+    /* a point on a Dirichlet side keeps the prescribed state */
+    if (k == 0 && c->bc[0] == ORC_DIRICHLET)
+      for (int q = 0; q < 3; ++q) out[q] = c->bcstate[0][q];
+    if (k == n && c->bc[1] == ORC_DIRICHLET)
+      for (int q = 0; q < 3; ++q) out[q] = c->bcstate[1][q];
     for (int r = 0; r < 3; ++r) Pfe[r * L->np + k] = out[r];
   }
 

@@ -29,7 +29,8 @@ extern "C" {
 #endif
 
 /* boundary kinds (per side: x-low, x-high, y-low, y-high) */
-enum { ORC_PERIODIC = 0, ORC_OUTFLOW = 1, ORC_NOSLIP = 2, ORC_SYMMETRY = 3 };
+enum { ORC_PERIODIC = 0, ORC_OUTFLOW = 1, ORC_NOSLIP = 2, ORC_SYMMETRY = 3,
+       ORC_DIRICHLET = 4 /* 1D only: ghost cells and the boundary point hold bcstate */ };
 
 /* limiter switches */
 enum {
@@ -59,6 +60,7 @@ typedef struct orc_cfg {
   int bc[4];            /* x-low, x-high, y-low, y-high */
   int max_halvings;
   int rk;               /* time integrator: 3 (SSP-RK3) or 54 (SSP-RK54) */
+  double bcstate[2][3]; /* 1D Dirichlet states (rho, rho u, E), x-low and x-high */
 } orc_cfg;
 
 /* sizes (in doubles) */

@@ -18,7 +18,7 @@ from typing import Callable, Sequence
 
 import numpy as np
 
-PERIODIC, OUTFLOW, NOSLIP, SYMMETRY = 0, 1, 2, 3
+PERIODIC, OUTFLOW, NOSLIP, SYMMETRY, DIRICHLET = 0, 1, 2, 3, 4
 
 
 @dataclass
@@ -246,6 +246,58 @@ def balanced_rows(y: np.ndarray, seed: int = 0, ratio: float = 3.0, below: float
     k = min(len(hi), int(ratio * max(len(lo), 1)))
     idx = np.concatenate([lo, rng.choice(hi, size=k, replace=False)])
     return idx[rng.permutation(len(idx))]
+
+
+def becker_shock_1d(n: int, M0: float = 3.0, mu: float = 1e-2, gamma: float = 1.4,
+                    Pr: float = 0.75, u_inf: float = 0.2):
+    """The moving viscous shock of the paper's 1D accuracy test (Sec. 4; the
+    exact solution Becker derived for Pr = 3/4): domain [-1, 1.5], shock at
+    x = u_inf t, rho_L = w_L = m_0 = 1, upstream Mach number M0 in the
+    shock frame; Dirichlet sides.  w(xi) (velocity relative to the shock,
+    xi = x - u_inf t) solves
+      xi = 2 mu gamma / ((gamma+1) m0 Pr) * [wL/(wL-wR) ln((wL-w)/(wL-w0))
+                                             - wR/(wL-wR) ln((w-wR)/(w0-wR))],
+    w0 = sqrt(wL wR), wR/wL = ((gamma-1) + 2/M0^2)/(gamma+1); then
+    rho = m0/w, u = u_inf + w, e = ((gamma+1)/(gamma-1) w0^2 - w^2)/(2 gamma),
+    p = (gamma-1) rho e.  Returns (grid, prim(x, t), Dirichlet states
+    [left, right] as conservative (rho, rho u, E))."""
+    wL, m0 = 1.0, 1.0
+    wR = wL * ((gamma - 1.0) + 2.0 / M0 ** 2) / (gamma + 1.0)
+    w0 = np.sqrt(wL * wR)
+    c = 2.0 * mu * gamma / ((gamma + 1.0) * m0 * Pr)
+
+    def xi_of(w):
+        with np.errstate(divide="ignore"):  # +-inf at the end states
+            return c * (wL / (wL - wR) * np.log((wL - w) / (wL - w0))
+                        - wR / (wL - wR) * np.log((w - wR) / (w0 - wR)))
+
+    def w_of(xi):
+        # xi(w) decreases from +inf (w -> wR) to -inf (w -> wL): bisection
+        xi = np.asarray(xi, dtype=np.float64)
+        lo = np.full(xi.shape, wR)
+        hi = np.full(xi.shape, wL)
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            if np.all((mid == lo) | (mid == hi)):
+                break
+            big = xi_of(mid) > xi  # mid is too close to wR
+            lo = np.where(big, mid, lo)
+            hi = np.where(big, hi, mid)
+        return 0.5 * (lo + hi)
+
+    def prim(x, t=0.0):
+        w = w_of(np.asarray(x) - u_inf * t)
+        rho = m0 / w
+        e = ((gamma + 1.0) / (gamma - 1.0) * w0 * w0 - w * w) / (2.0 * gamma)
+        return (rho, u_inf + w, (gamma - 1.0) * rho * e)
+
+    def cons(w):
+        rho = m0 / w
+        e = ((gamma + 1.0) / (gamma - 1.0) * w0 * w0 - w * w) / (2.0 * gamma)
+        u = u_inf + w
+        return [rho, rho * u, rho * e + 0.5 * rho * u * u]
+    g = Grid(dim=1, n1=n, x0=-1.0, x1=1.5, bc=(DIRICHLET, DIRICHLET, DIRICHLET, DIRICHLET))
+    return g, prim, [cons(wL), cons(wR)]
 
 
 def leblanc_1d(n: int = 800):
