@@ -52,8 +52,14 @@ typedef enum {
  * wrap, zero-order copy, or a mirror about the wall line with the normal
  * momentum (symmetry) or both momenta (no-slip) negated; point values on a
  * wall are projected after every stage onto zero normal (symmetry) or zero
- * (no-slip) momentum at unchanged density and internal energy) */
-typedef enum { AF_PERIODIC = 0, AF_OUTFLOW = 1, AF_NOSLIP = 2, AF_SYMMETRY = 3 } af_bc;
+ * (no-slip) momentum at unchanged density and internal energy).
+ * AF_DIRICHLET (1D only; the paper prescribes boundary values in its 1D
+ * viscous-shock test, Sec. 4): the ghost cells and lattice sites hold the
+ * side's state (af_set_bc_state) and the boundary point value is set to it
+ * after every stage. */
+typedef enum {
+  AF_PERIODIC = 0, AF_OUTFLOW = 1, AF_NOSLIP = 2, AF_SYMMETRY = 3, AF_DIRICHLET = 4
+} af_bc;
 typedef enum { AF_XLO = 0, AF_XHI = 1, AF_YLO = 2, AF_YHI = 3 } af_side;
 
 /* limiter switches (Sec. 3.2-3.4) */
@@ -127,6 +133,9 @@ void af_destroy(af_ctx* ctx);
 /* Set the boundary kind of one side.  A periodic axis must be periodic on
  * both sides before any compute call (checked there: AF_E_ARG). */
 af_status af_set_bc(af_ctx* ctx, int side, int kind);
+/* The state of a Dirichlet side (1D, side AF_XLO or AF_XHI): state[3] =
+ * (rho, rho u, E) on the host, copied.  Defaults to (1, 0, 1). */
+af_status af_set_bc_state(af_ctx* ctx, int side, const double* state);
 
 /* Number of doubles in one state buffer, its size in bytes, and the bytes of
  * the workspace (0 for a NULL or inconsistent context). */

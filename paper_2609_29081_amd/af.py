@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libaf.so")
 
 AF_OK, AF_E_ARG, AF_E_HIP, AF_E_PP, AF_E_NONFINITE = 0, 1, 2, 3, 4
-PERIODIC, OUTFLOW, NOSLIP, SYMMETRY = 0, 1, 2, 3
+PERIODIC, OUTFLOW, NOSLIP, SYMMETRY, DIRICHLET = 0, 1, 2, 3, 4
 LIM_SMOOTH, LIM_PP, LIM_POINT, LIM_CENTRE, LIM_LOWONLY, LIM_LEARNED = 1, 2, 4, 8, 16, 32
 LIM_ALL = 15
 PREC_FP64, PREC_MIXED = 0, 1
@@ -41,7 +41,8 @@ class Params(C.Structure):
 
 _lib = None
 
-EXPORTS = ["af_default_params", "af_init_grid", "af_destroy", "af_set_bc", "af_state_len",
+EXPORTS = ["af_default_params", "af_init_grid", "af_destroy", "af_set_bc", "af_set_bc_state",
+           "af_state_len",
            "af_state_bytes", "af_workspace_bytes", "af_set_state", "af_get_state",
            "af_check_admissible", "af_rk_stage", "af_cfl_dt", "af_step", "af_run",
            "af_read_flags", "af_reset_flags", "af_timing", "af_timing_read", "af_last_error",
@@ -71,6 +72,7 @@ def lib():
         L.af_destroy.argtypes = [vp]
         L.af_destroy.restype = None
         L.af_set_bc.argtypes = [vp, ip, ip]
+        L.af_set_bc_state.argtypes = [vp, ip, dp]
         L.af_state_len.argtypes = [vp]
         L.af_state_len.restype = C.c_size_t
         L.af_workspace_bytes.argtypes = [vp]
@@ -148,7 +150,8 @@ class Solver:
     workspace.  States are flat float64 CUDA tensors of length state_len."""
 
     def __init__(self, grid: W.Grid, gamma=1.4, mu=1e-3, Pr=0.72, cfl_c=0.2, cfl_v=0.075,
-                 limiter=LIM_ALL, Cs=1.0, max_halvings=40, precision=0, rk=3, device="cuda:0"):
+                 limiter=LIM_ALL, Cs=1.0, max_halvings=40, precision=0, rk=3, bcstate=None,
+                 device="cuda:0"):
         p = Params()
         _check(lib().af_default_params(C.byref(p)))
         p.dim, p.n1, p.n2 = grid.dim, grid.n1, grid.n2
@@ -164,6 +167,10 @@ class Solver:
         nsides = 2 if grid.dim == 1 else 4
         for side in range(nsides):
             _check(lib().af_set_bc(self.ctx, side, int(grid.bc[side])))
+        if bcstate is not None:  # 1D Dirichlet states [x-low, x-high]
+            for side in range(2):
+                arr = (C.c_double * 3)(*[float(v) for v in bcstate[side]])
+                _check(lib().af_set_bc_state(self.ctx, side, arr))
         self.state_len = int(lib().af_state_len(self.ctx))
         self.ws_bytes = int(lib().af_workspace_bytes(self.ctx))
         if self.state_len != grid.state_len:

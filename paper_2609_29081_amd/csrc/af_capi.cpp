@@ -64,6 +64,7 @@ struct af_ctx {
   int bc[4];
   EventTimer* timer = nullptr;
   const float* net = nullptr;  // learned-blend network parameters (device), or NULL
+  double bcstate[2][3] = {{1.0, 0.0, 1.0}, {1.0, 0.0, 1.0}};  // 1D Dirichlet states
 };
 
 struct af_batch {
@@ -143,6 +144,8 @@ bool geometry(const af_ctx* c, afi::Geo* g) {
   r.dx = (p.x1 - p.x0) / p.n1;
   r.dy = p.dim == 2 ? (p.y1 - p.y0) / p.n2 : 1.0;
   r.mixed = p.precision == AF_PREC_MIXED;
+  for (int s = 0; s < 2; ++s)
+    for (int k = 0; k < 3; ++k) r.bcstate[s][k] = c->bcstate[s][k];
   if (p.dim == 1) {
     r.off_pts = 3L * p.n1;
     r.state_len = 3L * (p.n1 + r.n1x);
@@ -437,8 +440,19 @@ af_status af_set_bc(af_ctx* c, int side, int kind) {
   if (!c) return fail(AF_E_ARG, "af_set_bc: NULL context");
   if (side < 0 || side > 3) return fail(AF_E_ARG, "bad side %d", side);
   if (c->p.dim == 1 && side > 1) return fail(AF_E_ARG, "1D grid has no y sides");
-  if (kind < AF_PERIODIC || kind > AF_SYMMETRY) return fail(AF_E_ARG, "bad boundary kind %d", kind);
+  if (kind < AF_PERIODIC || kind > AF_DIRICHLET) return fail(AF_E_ARG, "bad boundary kind %d", kind);
+  if (kind == AF_DIRICHLET && c->p.dim != 1)
+    return fail(AF_E_ARG, "Dirichlet sides exist in 1D only");
   c->bc[side] = kind;
+  return AF_OK;
+}
+
+af_status af_set_bc_state(af_ctx* c, int side, const double* state) {
+  if (!c || !state) return fail(AF_E_ARG, "af_set_bc_state: NULL argument");
+  if (c->p.dim != 1 || side < 0 || side > 1)
+    return fail(AF_E_ARG, "Dirichlet states exist for the two sides of a 1D grid");
+  if (!(state[0] > 0.0)) return fail(AF_E_ARG, "Dirichlet density must be > 0");
+  for (int k = 0; k < 3; ++k) c->bcstate[side][k] = state[k];
   return AF_OK;
 }
 

@@ -16,7 +16,7 @@ constexpr int kMargin = 4;            // ghost lattice lines kept per side
 constexpr double kPPEps = 1.0e-13;    // positivity epsilon (Sec. 3.3)
 constexpr double kDucros = 1.0e-13;   // Ducros-sensor regularisation (Sec. 3.2)
 
-enum : int { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_NOSLIP = 2, BC_SYMMETRY = 3 };
+enum : int { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_NOSLIP = 2, BC_SYMMETRY = 3, BC_DIRICHLET = 4 };
 enum : int {
   LIM_SMOOTH = 1, LIM_PP = 2, LIM_POINT = 4, LIM_CENTRE = 8, LIM_LOWONLY = 16, LIM_LEARNED = 32
 };

@@ -22,6 +22,7 @@ struct Geo {
   int bc[4];
   double dx, dy;
   int mixed;  // 2D: stencils in FP32, blends and updates in FP64
+  double bcstate[2][3];  // 1D Dirichlet states of the x-low and x-high sides
 };
 
 // geometry of a 2D grid as the stage kernels read it

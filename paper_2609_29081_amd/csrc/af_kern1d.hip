@@ -17,6 +17,7 @@ struct G1 {
   long off_pts;
   int bc0, bc1;
   double dx;
+  double dl[3], dr[3];  // states of Dirichlet sides (x-low, x-high)
   // inside a step attempt: stop once the attempt's flag word is set (it is
   // rejected and the stage output is never read)
   int skip_flagged;
@@ -34,6 +35,13 @@ __device__ __forceinline__ double pt(const G1& g, const double* __restrict__ U, 
 
 __device__ __forceinline__ void cell_image1(const G1& g, const double* __restrict__ U, int i,
                                             double* V) {
+  // beyond a Dirichlet side, its state
+  if ((i < 0 && g.bc0 == BC_DIRICHLET) || (i >= g.n && g.bc1 == BC_DIRICHLET)) {
+    const double* d = i < 0 ? g.dl : g.dr;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) V[k] = d[k];
+    return;
+  }
   int kind;
   const int Xi = axis_image(2 * i + 1, 2 * g.n, g.bc0, g.bc1, kind);
   const double s = (kind == BC_NOSLIP || kind == BC_SYMMETRY) ? -1.0 : 1.0;
@@ -79,6 +87,11 @@ __global__ void __launch_bounds__(kBlock) k_lattice1(G1 g, Phys ph, const double
     for (int k = 0; k < 3; ++k) V[k] = pt(g, U, Xi, k);
   }
   V[1] *= s;
+  if ((X < 0 && g.bc0 == BC_DIRICHLET) || (X > 2 * g.n && g.bc1 == BC_DIRICHLET)) {
+    const double* d = X < 0 ? g.dl : g.dr;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) V[k] = d[k];
+  }
   const double u = V[1] / V[0];
   const double p = pressure1(V[0], V[1], V[2], ph.gm1);
 #pragma unroll
@@ -364,6 +377,12 @@ __global__ void __launch_bounds__(kBlock) k_points1(G1 g, Phys ph, const double*
     out[2] -= out[1] * out[1] / (2.0 * out[0]);
     out[1] = 0.0;
   }
+  // a point on a Dirichlet side keeps the prescribed state
+  if ((X == 0 && g.bc0 == BC_DIRICHLET) || (X == 2 * g.n && g.bc1 == BC_DIRICHLET)) {
+    const double* d = X == 0 ? g.dl : g.dr;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) out[k] = d[k];
+  }
   bool bad = false;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -392,6 +411,10 @@ hipError_t stage1d(const Geo& geo, const Phys& ph, const Work& w, const double* 
   g.bc0 = geo.bc[0];
   g.bc1 = geo.bc[1];
   g.dx = geo.dx;
+  for (int k = 0; k < 3; ++k) {
+    g.dl[k] = geo.bcstate[0][k];
+    g.dr[k] = geo.bcstate[1][k];
+  }
   g.skip_flagged = sc.skip_flagged;
   g.fl = w.flags;
   AFI_TIMED(tm, 0, s,
