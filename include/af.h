@@ -184,6 +184,20 @@ af_status af_cfl_dt(af_ctx* ctx, const double* U, double t, double t_final, doub
 af_status af_step(af_ctx* ctx, double* U, void* ws, void* stream, double dt, double t,
                   double t_final, double* dt_used, int* halvings);
 
+/* Steps with a source term (manufactured solutions: the paper's Taylor-Green
+ * test, Sec. 4, adds an energy source).  af_stage_times writes the times of
+ * the stage inputs of integrator rk (3 or 54) as fractions of dt into c
+ * (3 or 5 values) and returns their number (-1 for another rk).
+ * af_step_source takes one step of dU/dt = L(U) + S(t) with the given dt
+ * (no CFL, no halving): every forward-Euler step of the integrator is the
+ * limited update of L followed by + tau S_k, where src[k] is a device state
+ * (same layout as U) holding S at the k-th stage input's time.  nsrc must
+ * be 3 (SSP-RK3) or 5 (SSP-RK54).  Synchronous.  If a flag is raised the
+ * state is restored and AF_E_PP (or AF_E_NONFINITE) returned. */
+int af_stage_times(int rk, double* c);
+af_status af_step_source(af_ctx* ctx, double* U, void* ws, void* stream, double dt,
+                         const double* const* src, int nsrc);
+
 /* Advance U from t0 until t_final or max_steps steps.  Steps run with the
  * time step kept on the device; every check_every steps (>= 1) the stream is
  * synchronised and the flags read; a block whose flags are raised is redone

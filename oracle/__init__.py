@@ -156,6 +156,55 @@ def blend_features(cfg: Cfg, U: np.ndarray) -> np.ndarray:
     return out
 
 
+# Shu-Osher coefficients of the two integrators, for steps with a source
+# term (the C oracle's orc_step covers the source-free steps): SSP-RK3, and
+# Spiteri and Ruuth's SSPRK(5,4), the five-stage fourth-order SSP method
+# Sec. 2.3 names
+_RK54_A = dict(a20=0.444370493651235, a21=0.555629506348765, a30=0.620101851488403,
+               a32=0.379898148511597, a40=0.178079954393132, a43=0.821920045606868,
+               a52=0.517231671970585, a53=0.096059710526147, a54=0.386708617503269)
+_RK54_B = dict(b10=0.391752226571890, b21=0.368410593050371, b32=0.251891774271694,
+               b43=0.544974750228521, b54=0.226007483236906)
+
+
+def stage_times(rk: int) -> list:
+    """times of the stage inputs as fractions of dt"""
+    if rk == 3:
+        return [0.0, 1.0, 0.5]
+    A, B = _RK54_A, _RK54_B
+    c1 = B["b10"]
+    c2 = A["a21"] * c1 + B["b21"]
+    c3 = A["a32"] * c2 + B["b32"]
+    c4 = A["a43"] * c3 + B["b43"]
+    return [0.0, c1, c2, c3, c4]
+
+
+def step_source(cfg: Cfg, U: np.ndarray, dt: float, S: list):
+    """one step of dU/dt = L(U) + S(t) with a given dt and no halving:
+    every forward-Euler step is the limited FE of L followed by + tau S_k,
+    S_k (state-shaped) being the source at the k-th stage input's time
+    (stage_times).  Returns (new state, flags)."""
+    def fe_s(V, tau, Sk):
+        out, fl = fe(cfg, V, tau)
+        return out + tau * Sk, fl
+    if cfg.rk != 54:
+        u1, f0 = fe_s(U, dt, S[0])
+        e1, f1 = fe_s(u1, dt, S[1])
+        u2 = 0.75 * U + 0.25 * e1
+        e2, f2 = fe_s(u2, dt, S[2])
+        return U / 3.0 + 2.0 / 3.0 * e2, f0 | f1 | f2
+    A, B = _RK54_A, _RK54_B
+    u1, f0 = fe_s(U, B["b10"] * dt, S[0])
+    e1, f1 = fe_s(u1, B["b21"] / A["a21"] * dt, S[1])
+    u2 = A["a20"] * U + A["a21"] * e1
+    e2, f2 = fe_s(u2, B["b32"] / A["a32"] * dt, S[2])
+    u3 = A["a30"] * U + A["a32"] * e2
+    e3, f3 = fe_s(u3, B["b43"] / A["a43"] * dt, S[3])
+    u4 = A["a40"] * U + A["a43"] * e3
+    e4, f4 = fe_s(u4, B["b54"] / A["a54"] * dt, S[4])
+    return A["a52"] * u2 + A["a53"] * e3 + A["a54"] * e4, f0 | f1 | f2 | f3 | f4
+
+
 def rhs(cfg: Cfg, U: np.ndarray) -> np.ndarray:
     U = np.ascontiguousarray(U, dtype=np.float64)
     out = np.empty_like(U)

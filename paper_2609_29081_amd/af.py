@@ -50,7 +50,8 @@ EXPORTS = ["af_default_params", "af_init_grid", "af_destroy", "af_set_bc", "af_s
            "af_stage_variant_count", "af_stage_variant_info", "af_batch_variant",
            "af_batch_set_variant", "af_batch_tune", "af_face_count", "af_mlp_param_count",
            "af_blend_features", "af_set_blend_net", "af_blend_infer", "af_rk_stage_blend",
-           "af_mlp_grad_workspace_bytes", "af_mlp_grad", "af_mlp_adam", "af_mlp_train"]
+           "af_mlp_grad_workspace_bytes", "af_mlp_grad", "af_mlp_adam", "af_mlp_train",
+           "af_stage_times", "af_step_source"]
 
 # kernel kinds reported by af_timing_read
 KERNEL_KINDS = {0: "lattice", 1: "grad", 2: "cellpre", 3: "face", 4: "cells", 5: "points",
@@ -102,6 +103,8 @@ def lib():
         L.af_mlp_adam.argtypes = [vp, vp, vp, vp, C.c_long, C.c_float, vp]
         L.af_mlp_train.argtypes = [vp, vp, C.c_long, vp, vp, vp, vp, C.c_long, ip, ip, C.c_float,
                                    vp, vp, vp]
+        L.af_stage_times.argtypes = [ip, dp]
+        L.af_step_source.argtypes = [vp, vp, vp, vp, C.c_double, C.POINTER(vp), ip]
         L.af_stage_variant_count.argtypes = []
         L.af_stage_variant_info.argtypes = [ip, C.POINTER(C.c_char_p), C.POINTER(ip),
                                             C.POINTER(ip)]
@@ -254,6 +257,16 @@ class Solver:
                                          C.byref(n)))
         return n.value
 
+    def af_step_source(self, U, dt: float, sources: list, stream=None):
+        """one step with source states (device tensors) at the stage times;
+        returns the status"""
+        arr = (C.c_void_p * len(sources))(*[S.data_ptr() for S in sources])
+        st = lib().af_step_source(self.ctx, _ptr(U), _ptr(self.ws), _stream(stream), dt, arr,
+                                  len(sources))
+        if st in (AF_E_ARG, AF_E_HIP):
+            _check(st)
+        return st
+
     # -- the learned blend (2D) --------------------------------------------
     @property
     def face_count(self) -> int:
@@ -295,6 +308,14 @@ class Solver:
         ms = (C.c_double * K_COUNT)()
         _check(lib().af_timing_read(self.ctx, n, ms))
         return {KERNEL_KINDS.get(k, f"k{k}"): (n[k], ms[k]) for k in range(K_COUNT) if n[k]}
+
+
+def stage_times(rk: int) -> list:
+    c = (C.c_double * 5)()
+    n = lib().af_stage_times(rk, c)
+    if n < 0:
+        raise ValueError("rk must be 3 or 54")
+    return list(c)[:n]
 
 
 def mlp_param_count() -> int:

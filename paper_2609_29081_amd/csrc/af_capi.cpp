@@ -210,6 +210,11 @@ hipError_t launch_stage(const afi::Geo& g, const afd::Phys& ph, const afi::Work&
   return launch_coef(g, ph, w, sc, Un, Uk, Uout, dt_dev, dt_host, s, tm);
 }
 
+// a stage output plus its share of a source term: out += f S (S may be NULL)
+hipError_t add_source(const afi::Geo& g, double* out, double f, const double* S, hipStream_t s) {
+  return S ? afi::lincomb(out, 1.0, out, f, S, g.state_len, s) : hipSuccess;
+}
+
 // SSP-RK54 (Sec. 2.3 names the five-stage, fourth-order SSP method; these
 // are Spiteri and Ruuth's SSPRK(5,4) coefficients in Shu-Osher form).  With
 // E_k = FE(u_k, c_k dt): u1 = E0, u2 = a20 u0 + a21 E1, u3 = a30 u0 + a32 E2,
@@ -224,10 +229,11 @@ constexpr double kB10 = 0.391752226571890, kB21 = 0.368410593050371;
 constexpr double kB32 = 0.251891774271694, kB43 = 0.544974750228521;
 constexpr double kB54 = 0.226007483236906;
 
-// one SSP-RK54 attempt from u0 (kept) through buffers A, B into X
+// one SSP-RK54 attempt from u0 (kept) through buffers A, B into X; src as
+// for rk3 (five stage inputs)
 hipError_t rk54(const afi::Geo& g, const afd::Phys& ph, const afi::Work& w, const double* u0,
                 double* A, double* B, double* X, const double* dt_dev, double dt, hipStream_t s,
-                afi::Timer* tm) {
+                afi::Timer* tm, const double* const* src = nullptr) {
   auto coef = [](double a, double b, double mul) {
     afi::StageCoef c{};
     c.a = a;
@@ -239,20 +245,28 @@ hipError_t rk54(const afi::Geo& g, const afd::Phys& ph, const afi::Work& w, cons
   };
   const long n = g.state_len;
   hipError_t e;
+  auto S = [&](int k) { return src ? src[k] : nullptr; };
   if ((e = launch_coef(g, ph, w, coef(0.0, 1.0, kB10), u0, u0, A, dt_dev, dt, s, tm)) != hipSuccess)
     return e;  // A = u1
+  if ((e = add_source(g, A, kB10 * dt, S(0), s)) != hipSuccess) return e;
   if ((e = launch_coef(g, ph, w, coef(kA20, kA21, kB21 / kA21), u0, A, B, dt_dev, dt, s, tm)) !=
       hipSuccess)
     return e;  // B = u2
+  if ((e = add_source(g, B, kB21 * dt, S(1), s)) != hipSuccess) return e;
   if ((e = launch_coef(g, ph, w, coef(kA30, kA32, kB32 / kA32), u0, B, A, dt_dev, dt, s, tm)) !=
       hipSuccess)
     return e;  // A = u3
+  if ((e = add_source(g, A, kB32 * dt, S(2), s)) != hipSuccess) return e;
   if ((e = launch_coef(g, ph, w, coef(0.0, 1.0, kB43 / kA43), u0, A, X, dt_dev, dt, s, tm)) !=
       hipSuccess)
     return e;  // X = E3
+  if ((e = add_source(g, X, kB43 / kA43 * dt, S(3), s)) != hipSuccess) return e;
   if ((e = afi::lincomb(A, kA40, u0, kA43, X, n, s)) != hipSuccess) return e;   // A = u4
   if ((e = afi::lincomb(B, kA52, B, kA53, X, n, s)) != hipSuccess) return e;    // B = a52 u2 + a53 E3
-  return launch_coef(g, ph, w, coef(1.0, kA54, kB54 / kA54), B, A, X, dt_dev, dt, s, tm);
+  if ((e = launch_coef(g, ph, w, coef(1.0, kA54, kB54 / kA54), B, A, X, dt_dev, dt, s, tm)) !=
+      hipSuccess)
+    return e;
+  return add_source(g, X, kB54 * dt, S(4), s);
 }
 
 hipError_t launch_cfl(const af_ctx* c, const afi::Geo& g, const afi::Work& w, const double* U,
@@ -270,12 +284,20 @@ af_status read_flags(const afi::Work& w, hipStream_t s, unsigned* out) {
 }
 
 // three stages with a host-given dt; cur -> out through S1, S2
+// three stages with a host-given dt; cur -> out through S1, S2.  src, if not
+// NULL, holds a source term at each stage input's time (host dt only): each
+// forward Euler step then adds tau S_k after its limited update
 hipError_t rk3(const afi::Geo& g, const afd::Phys& ph, const afi::Work& w, const double* cur,
-               double* out, const double* dt_dev, double dt, hipStream_t s, afi::Timer* tm) {
+               double* out, const double* dt_dev, double dt, hipStream_t s, afi::Timer* tm,
+               const double* const* src = nullptr) {
   hipError_t e;
   if ((e = launch_stage(g, ph, w, 0, cur, cur, w.S1, dt_dev, dt, s, tm)) != hipSuccess) return e;
+  if (src && (e = add_source(g, w.S1, dt, src[0], s)) != hipSuccess) return e;
   if ((e = launch_stage(g, ph, w, 1, cur, w.S1, w.S2, dt_dev, dt, s, tm)) != hipSuccess) return e;
-  return launch_stage(g, ph, w, 2, cur, w.S2, out, dt_dev, dt, s, tm);
+  if (src && (e = add_source(g, w.S2, 0.25 * dt, src[1], s)) != hipSuccess) return e;
+  if ((e = launch_stage(g, ph, w, 2, cur, w.S2, out, dt_dev, dt, s, tm)) != hipSuccess) return e;
+  if (src && (e = add_source(g, out, 2.0 / 3.0 * dt, src[2], s)) != hipSuccess) return e;
+  return hipSuccess;
 }
 
 // host copies of the batch descriptors for states U, times t0..t_final and
@@ -930,6 +952,55 @@ af_status af_mlp_train(const float* X, const float* y, long n, float* params, fl
     AF_HIP(afi::mlp_grad(X + row * afi::kMlpIn, y + row, nb, params, grad, loss_out, gws, s));
     AF_HIP(afi::mlp_adam(params, grad, m, v, step0 + k + 1, lr, s));
     row += nb;
+  }
+  return AF_OK;
+}
+
+int af_stage_times(int rk, double* c) {
+  if (!c) return -1;
+  if (rk == 3) {
+    c[0] = 0.0;
+    c[1] = 1.0;
+    c[2] = 0.5;
+    return 3;
+  }
+  if (rk != 54) return -1;
+  c[0] = 0.0;
+  c[1] = kB10;
+  c[2] = kA21 * c[1] + kB21;
+  c[3] = kA32 * c[2] + kB32;
+  c[4] = kA43 * c[3] + kB43;
+  return 5;
+}
+
+af_status af_step_source(af_ctx* c, double* U, void* ws, void* stream, double dt,
+                         const double* const* src, int nsrc) {
+  if (!c || !U || !ws || !src) return fail(AF_E_ARG, "af_step_source: NULL argument");
+  if (!(dt > 0.0)) return fail(AF_E_ARG, "af_step_source: dt must be > 0");
+  if (!net_ready(c)) return AF_E_ARG;
+  const int need = c->p.rk == 54 ? 5 : 3;
+  if (nsrc != need) return fail(AF_E_ARG, "af_step_source: %d source states needed", need);
+  for (int k = 0; k < need; ++k)
+    if (!src[k]) return fail(AF_E_ARG, "af_step_source: source %d is NULL", k);
+  afi::Geo g;
+  if (!geometry(c, &g)) return AF_E_ARG;
+  const afi::Work w = work_of(c, g, ws);
+  const hipStream_t s = (hipStream_t)stream;
+  const afd::Phys ph = physics(c->p);
+  AF_HIP(afi::copy_state(w.SAVE, U, g.state_len, s));
+  AF_HIP(afi::clear_flags(w, s));
+  if (c->p.rk == 54)
+    AF_HIP(rk54(g, ph, w, w.SAVE, w.S1, w.S2, U, nullptr, dt, s, c->timer, src));
+  else
+    AF_HIP(rk3(g, ph, w, w.SAVE, U, nullptr, dt, s, c->timer, src));
+  unsigned fl = 0;
+  af_status st = read_flags(w, s, &fl);
+  if (st != AF_OK) return st;
+  if (fl != 0) {
+    AF_HIP(afi::copy_state(U, w.SAVE, g.state_len, s));
+    AF_HIP(hipStreamSynchronize(s));
+    if (fl & AF_FLAG_NONFINITE) return fail(AF_E_NONFINITE, "non-finite values (flags %u)", fl);
+    return fail(AF_E_PP, "low-order states inadmissible (flags %u)", fl);
   }
   return AF_OK;
 }

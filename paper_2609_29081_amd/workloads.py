@@ -300,6 +300,58 @@ def becker_shock_1d(n: int, M0: float = 3.0, mu: float = 1e-2, gamma: float = 1.
     return g, prim, [cons(wL), cons(wR)]
 
 
+def taylor_green_2d(n: int, p0: float = 100.0, mu: float = 1e-5, gamma: float = 1.4,
+                    Pr: float = 1.0):
+    """The paper's manufactured Taylor-Green vortex (Sec. 4): periodic
+    [0, 2 pi]^2, a(t) = exp(-2 mu t), b = cos 2x + cos 2y, rho = 1,
+    (u, v) = a (sin x cos y, -cos x sin y), p = p0/(gamma-1) + a^2 b/4, with
+    the energy source
+      S_E = (p_t + u p_x + v p_y)/(gamma-1) - 4 mu a^2 cos^2 x cos^2 y
+            - kappa lap p,
+    p_t = -mu a^2 b, p_x = -a^2 sin(2x)/2, p_y = -a^2 sin(2y)/2,
+    lap p = -a^2 b, kappa = gamma mu / ((gamma-1) Pr).  Returns (grid,
+    prim(x, y, t), source(t)), source(t) being a state-shaped array of S
+    (zero but for the energy component): cell averages by 5 x 5
+    Gauss-Legendre quadrature, point values sampled."""
+    two_pi = 2.0 * np.pi
+    g = Grid(dim=2, n1=n, n2=n, x0=0.0, x1=two_pi, y0=0.0, y1=two_pi, bc=(PERIODIC,) * 4)
+    kappa = gamma * mu / ((gamma - 1.0) * Pr)
+
+    def prim(x, y, t=0.0):
+        a = np.exp(-2.0 * mu * t)
+        b = np.cos(2.0 * x) + np.cos(2.0 * y)
+        return (np.ones_like(x), a * np.sin(x) * np.cos(y), -a * np.cos(x) * np.sin(y),
+                p0 / (gamma - 1.0) + a * a * b / 4.0)
+
+    def s_energy(x, y, t):
+        a = np.exp(-2.0 * mu * t)
+        b = np.cos(2.0 * x) + np.cos(2.0 * y)
+        u, v = a * np.sin(x) * np.cos(y), -a * np.cos(x) * np.sin(y)
+        pt, px, py = -mu * a * a * b, -a * a * np.sin(2.0 * x) / 2.0, -a * a * np.sin(2.0 * y) / 2.0
+        lap = -a * a * b
+        return ((pt + u * px + v * py) / (gamma - 1.0)
+                - 4.0 * mu * a * a * np.cos(x) ** 2 * np.cos(y) ** 2 - kappa * lap)
+
+    def source(t):
+        S = np.zeros(g.state_len)
+        parts = g.split(S)
+        gx, gw = np.polynomial.legendre.leggauss(5)
+        gx, gw = 0.5 * (gx + 1.0), 0.5 * gw
+        xl = g.x0 + np.arange(g.n1) * g.dx
+        yl = g.y0 + np.arange(g.n2) * g.dy
+        XL, YL = np.meshgrid(xl, yl)
+        acc = np.zeros((g.n2, g.n1))
+        for qa in range(5):
+            for qb in range(5):
+                acc += gw[qa] * gw[qb] * s_energy(XL + gx[qa] * g.dx, YL + gx[qb] * g.dy, t)
+        parts["avg"][3] = acc
+        for name in ("xe", "ye", "co"):
+            X, Y = g.point_coords(name)
+            parts[name][3] = s_energy(X, Y, t)
+        return S
+    return g, prim, source
+
+
 def leblanc_1d(n: int = 800):
     """LeBlanc-type near-vacuum Riemann problem on [-0.5,0.5], outflow."""
     g = Grid(dim=1, n1=n, x0=-0.5, x1=0.5, bc=(OUTFLOW, OUTFLOW, OUTFLOW, OUTFLOW))
