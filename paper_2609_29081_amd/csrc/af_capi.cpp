@@ -167,6 +167,7 @@ afd::Phys physics(const af_params& p) {
   ph.mu = p.mu;
   ph.kap = p.gamma * p.mu / ((p.gamma - 1.0) * p.Pr);
   ph.Cs = p.Cs;
+  ph.igm1 = 1.0 / (p.gamma - 1.0);
   ph.lim = p.limiter;
   return ph;
 }

@@ -27,13 +27,14 @@ enum : unsigned { FLAG_CELL_LOW = 1u, FLAG_POINT_LOW = 2u, FLAG_NONFINITE = 4u }
 template <typename R>
 struct PhysT {
   R gam, gm1, mu, kap, Cs;
+  R igm1;  // 1/(gamma-1)
   int lim;
 };
 using Phys = PhysT<double>;
 
 template <typename R>
 __host__ __device__ __forceinline__ PhysT<R> phys_as(const Phys& p) {
-  return PhysT<R>{R(p.gam), R(p.gm1), R(p.mu), R(p.kap), R(p.Cs), p.lim};
+  return PhysT<R>{R(p.gam), R(p.gm1), R(p.mu), R(p.kap), R(p.Cs), R(p.igm1), p.lim};
 }
 
 // NaN-propagating max/min: an inadmissible state anywhere in a stencil must
@@ -214,7 +215,7 @@ __device__ __forceinline__ void bvisc2_xy(R p, R T, R ux, R vx, R Tx, R uy, R vy
   const R tyy = ph.mu * (R(4.0 / 3.0) * vy - R(2.0 / 3.0) * ux);
   const R txy = ph.mu * (uy + vx);
   const R qx = ph.kap * Tx, qy = ph.kap * Ty;
-  const R e2 = R(2.0) * T / ph.gm1;
+  const R e2 = R(2.0) * T * ph.igm1;
   const R inv = R(0.5) * ph.gm1 / p;
   bx = (sqrt(qx * qx + e2 * (txx * txx + txy * txy)) + fabs(qx)) * inv;
   by = (sqrt(qy * qy + e2 * (txy * txy + tyy * tyy)) + fabs(qy)) * inv;
@@ -229,7 +230,7 @@ __device__ __forceinline__ R bvisc2_dir(int d, R p, R T, R ux, R vx, R Tx, R uy,
   const R txy = ph.mu * (uy + vx);
   const R q = ph.kap * (d == 0 ? Tx : Ty);
   const R t2 = d == 0 ? txx * txx + txy * txy : txy * txy + tyy * tyy;
-  const R e2 = R(2.0) * T / ph.gm1;
+  const R e2 = R(2.0) * T * ph.igm1;
   return (sqrt(q * q + e2 * t2) + fabs(q)) * (R(0.5) * ph.gm1 / p);
 }
 

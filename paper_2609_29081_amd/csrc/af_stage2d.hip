@@ -526,7 +526,9 @@ __device__ __forceinline__ TileArgs batch_tile(const StageArgs& sa, const int* t
   return A;
 }
 
-template <typename R, bool BATCH>
+// BLEND: the single-instance kernel with per-face blend input/output arrays
+// (its own instance, so that the plain stage carries none of that code)
+template <typename R, bool BATCH, bool BLEND = false>
 __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
   __shared__ Tile<R> T;
   __shared__ unsigned stop;  // workgroup-uniform copy of the flag word
@@ -751,7 +753,7 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
   // ---- phase 3: limited face fluxes of the tile's cells ----
   const float* blend = nullptr;
   float* ts_out = nullptr;
-  if constexpr (!BATCH) {
+  if constexpr (BLEND && !BATCH) {
     blend = sa.blend;
     ts_out = sa.ts_out;
   }
@@ -785,7 +787,7 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
     site_flux(T, ph, a, q, d, Fm);
     site_flux(T, ph, a + sa, q + sq, d, Fb);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) FH[k] = (Fa[k] + R(4.0) * Fm[k] + Fb[k]) / R(6.0);
+    for (int k = 0; k < 4; ++k) FH[k] = (Fa[k] + R(4.0) * Fm[k] + Fb[k]) * R(1.0 / 6.0);
     if (!limc) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) F[k] = FH[k];
@@ -1112,8 +1114,14 @@ hipError_t launch(const G2& g, const Phys& ph, const afi::Work& w, const double*
   sa.blend = sc.blend;
   sa.ts_out = sc.ts_out;
   sa.ntiles = ntiles;
-  AFI_TIMED(tm, 7, s,
-            hipLaunchKernelGGL((k_stage<R, false>), dim3((unsigned)nwg), dim3(NT), 0, s, sa));
+  if (sa.blend || sa.ts_out) {
+    AFI_TIMED(tm, 7, s,
+              hipLaunchKernelGGL((k_stage<R, false, true>), dim3((unsigned)nwg), dim3(NT), 0, s,
+                                 sa));
+  } else {
+    AFI_TIMED(tm, 7, s,
+              hipLaunchKernelGGL((k_stage<R, false>), dim3((unsigned)nwg), dim3(NT), 0, s, sa));
+  }
   return hipGetLastError();
 }
 
