@@ -37,6 +37,19 @@ __host__ __device__ __forceinline__ PhysT<R> phys_as(const Phys& p) {
   return PhysT<R>{R(p.gam), R(p.gm1), R(p.mu), R(p.kap), R(p.Cs), R(p.igm1), p.lim};
 }
 
+// 1/x.  FP64: the hardware reciprocal refined by two Newton steps, which is
+// as accurate as the division for the positive normal values it is used on
+// (densities, pressures) and much shorter; x = 0 or a non-finite x gives NaN,
+// which the stage flags as a non-finite result
+template <typename R>
+__device__ __forceinline__ R rcp(R x) { return R(1.0) / x; }
+template <>
+__device__ __forceinline__ double rcp<double>(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return fma(fma(-x, r, 1.0), r, r);
+}
+
 // NaN-propagating max/min: an inadmissible state anywhere in a stencil must
 // make the stage non-finite (and raise the flag), never be skipped
 template <typename R>
@@ -95,7 +108,7 @@ __device__ __forceinline__ double theta_lin(double zL, double zH, double eps) {
 }
 
 __device__ __forceinline__ double pressure2(double r, double mx, double my, double E, double gm1) {
-  return gm1 * (E - (mx * mx + my * my) / (2.0 * r));
+  return gm1 * (E - (mx * mx + my * my) * (0.5 * rcp(r)));
 }
 __device__ __forceinline__ double pressure1(double r, double m, double E, double gm1) {
   return gm1 * (E - m * m / (2.0 * r));
@@ -216,7 +229,7 @@ __device__ __forceinline__ void bvisc2_xy(R p, R T, R ux, R vx, R Tx, R uy, R vy
   const R txy = ph.mu * (uy + vx);
   const R qx = ph.kap * Tx, qy = ph.kap * Ty;
   const R e2 = R(2.0) * T * ph.igm1;
-  const R inv = R(0.5) * ph.gm1 / p;
+  const R inv = R(0.5) * ph.gm1 * rcp(p);
   bx = (sqrt(qx * qx + e2 * (txx * txx + txy * txy)) + fabs(qx)) * inv;
   by = (sqrt(qy * qy + e2 * (txy * txy + tyy * tyy)) + fabs(qy)) * inv;
 }
@@ -231,7 +244,7 @@ __device__ __forceinline__ R bvisc2_dir(int d, R p, R T, R ux, R vx, R Tx, R uy,
   const R q = ph.kap * (d == 0 ? Tx : Ty);
   const R t2 = d == 0 ? txx * txx + txy * txy : txy * txy + tyy * tyy;
   const R e2 = R(2.0) * T * ph.igm1;
-  return (sqrt(q * q + e2 * t2) + fabs(q)) * (R(0.5) * ph.gm1 / p);
+  return (sqrt(q * q + e2 * t2) + fabs(q)) * (R(0.5) * ph.gm1 * rcp(p));
 }
 
 __device__ __forceinline__ double bvisc1(double rho, double p, double ux, double Tx,

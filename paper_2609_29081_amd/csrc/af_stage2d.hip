@@ -93,7 +93,7 @@ __device__ __forceinline__ void centre_value(const PhysT<R>& ph, const Phys& phd
                                              const R* e, const R* c, R* V, R* w) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) V[k] = (R(36.0) * Ub[k] - R(4.0) * e[k] - c[k]) / R(16.0);
-  R ir = R(1.0) / V[0];
+  R ir = rcp(V[0]);
   const R p = ph.gm1 * (V[3] - R(0.5) * (V[1] * V[1] + V[2] * V[2]) * ir);
   if ((ph.lim & LIM_CENTRE) && !(Ub[0] > R(0.0) && V[0] >= R(kPPEps) && p >= R(kPPEps))) {
     if (!(Ub[0] > R(0.0))) {
@@ -113,7 +113,7 @@ __device__ __forceinline__ void centre_value(const PhysT<R>& ph, const Phys& phd
         for (int k = 0; k < 4; ++k) V[k] = R(Ud[k] + th * (Vd[k] - Ud[k]));
       }
     }
-    ir = R(1.0) / V[0];
+    ir = rcp(V[0]);
   }
   aux_of(ph, V, ir, w);
 }
@@ -168,8 +168,8 @@ __device__ __forceinline__ void cell_low(const G2& g, const PhysT<R>& ph, const 
                                          const R* Cxm, const R* Cxp, const R* Cym, const R* Cyp,
                                          R* o) {
   // one reciprocal density per cell
-  const R r0 = R(1.0) / C0[0], rxm = R(1.0) / Cxm[0], rxp = R(1.0) / Cxp[0],
-          rym = R(1.0) / Cym[0], ryp = R(1.0) / Cyp[0];
+  const R r0 = rcp(C0[0]), rxm = rcp(Cxm[0]), rxp = rcp(Cxp[0]),
+          rym = rcp(Cym[0]), ryp = rcp(Cyp[0]);
   auto pr = [&](const R* V, R ir) {
     return ph.gm1 * (V[3] - R(0.5) * (V[1] * V[1] + V[2] * V[2]) * ir);
   };
@@ -250,7 +250,7 @@ struct Tile {
 template <typename R>
 __device__ __forceinline__ void store_aux(Tile<R>& T, const PhysT<R>& ph, int s) {
   const R r = T.U[0][s], m1 = T.U[1][s], m2 = T.U[2][s], E = T.U[3][s];
-  const R ir = R(1.0) / r;
+  const R ir = rcp(r);
   const R p = ph.gm1 * (E - R(0.5) * (m1 * m1 + m2 * m2) * ir);
   const R Tt = p * ir;
   T.A[0][s] = m1 * ir;
