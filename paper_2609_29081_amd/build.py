@@ -32,6 +32,11 @@ def hip_flags():
     return ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
             # no packed-FP32 instruction selection
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # multiply-adds fused within one expression only: the rounding of
+            # every result follows from the source, so that the template
+            # instances of a kernel (single instance, batch, given blend)
+            # round alike
+            "-ffp-contract=on",
             "-Wall", "-Wno-unused-function"]
 
 

@@ -65,7 +65,12 @@ constexpr int WC = TX + 2, HC = TY + 2, NC = WC * HC;          // tile cells +- 
 constexpr int NFX = TY * (TX + 1), NFY = (TY + 1) * TX;
 constexpr int NCEN = (TX + 4) * (TY + 4);  // centre sites of the lattice region
 constexpr int NPT = 3 * TX * TY;           // point DOF sites of a tile
-constexpr int kStage = 9 * NCEN > 4 * NPT ? 9 * NCEN : 4 * NPT;
+// sites of the low-order point scheme: [X0-1, X0+2TX] x [Y0-1, Y0+2TY], the
+// tile's point sites and their lattice neighbours; x-direction data on its
+// rows Y0..Y0+2TY-1, y-direction data on its columns X0..X0+2TX-1
+constexpr int SW = 2 * TX + 2, SH = 2 * TY + 2, NSR = SW * SH;
+constexpr int NSX = SW * 2 * TY, NSY = 2 * TX * SH;
+constexpr int kStage = 9 * NCEN > 4 * NSX ? 9 * NCEN : 4 * NSX;
 
 template <typename R>
 constexpr bool kFP64 = std::is_same<R, double>::value;
@@ -235,16 +240,23 @@ struct Tile {
   R U[4][NA];   // conservative values, block +- 4
   R A[5][NA];   // u, v, p, T, c
   R G[6][NG];   // du/dx dv/dx dT/dx du/dy dv/dy dT/dy, block +- 2
-  R C[23][NC];  // cell low-order data, tile +- 1
-  // staging: centre values and their (u, v, p, T, c) in phase 2, low-order
-  // point values in phase 5
-  R STG[kStage];
+  union {
+    R C[23][NC];  // cell low-order data, tile +- 1
+    // phase 5: y-direction flux (components 1-3) and b_y of the low-order
+    // point scheme's sites, over rows 0-13 of C, which only phase 3 reads
+    R SY[4][NSY];
+  };
+  union {
+    R STG[kStage];  // phase 2: centre values and their (u, v, p, T, c)
+    R SX[4][NSX];   // phase 5: x-direction flux (components 1-3) and b_x
+  };
   R FX[4][NFX];  // limited x-face fluxes of the tile's cells
   R FY[4][NFY];  // limited y-face fluxes
   // FP64 cell averages of the tile +- 1 for the mixed-precision stage (the
   // FP64 stage reads them from C)
   double AV[4][kFP64<R> ? 1 : NC];
 };
+static_assert(4 * NSY <= 14 * NC, "the y-direction site data fit in rows 0-13 of C");
 
 // auxiliaries (u, v, p, T, c) of LDS lattice site s
 template <typename R>
@@ -345,36 +357,61 @@ __device__ __forceinline__ void lo_grad(const Tile<R>& T, int lx, int ly, R ihx,
   gr[5] = (tp - tm) * ihy;
 }
 
-// low-order point value U^L = U - sum_d (2 dt/h_d) (F^L(z, z+e_d) - F^L(z-e_d, z))
-// of the point at (lx, ly), with the LLF flux
-// F^L(a, b) = (F_a + F_b)/2 - (max(|u_d|+c) + max(b_d))/2 (U_b - U_a)
+// x- or y-direction data of the low-order point scheme at a site: the total
+// flux F_d (its density component is the momentum, not stored) and b_d, as
+// SX/SY entry o
 template <typename R>
-__device__ __forceinline__ void lo_point(const Tile<R>& T, const PhysT<R>& ph, int lx, int ly,
-                                         double dx, double dy, double dt, R* UL) {
-  const R ihx = R(1.0 / dx), ihy = R(1.0 / dy);
-  R U0[4], w0[5], g0[6];
-  lo_state(T, lx, ly, U0, w0);
-  lo_grad(T, lx, ly, ihx, ihy, g0);
-  R bx0, by0;
-  bvisc2_xy(w0[2], w0[3], g0[0], g0[1], g0[2], g0[3], g0[4], g0[5], ph, bx0, by0);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) UL[k] = U0[k];
+__device__ __forceinline__ void lo_site(Tile<R>& T, const PhysT<R>& ph, int lx, int ly, R ihx,
+                                        R ihy, bool need_x, bool need_y, int ox, int oy) {
+  R U[4], w[5], gr[6];
+  lo_state(T, lx, ly, U, w);
+  lo_grad(T, lx, ly, ihx, ihy, gr);
 #pragma unroll
   for (int d = 0; d < 2; ++d) {
-    R F0[4];
-    tot_flux(d, U0, w0[0], w0[1], w0[2], g0, ph, F0);
+    if (!(d == 0 ? need_x : need_y)) continue;
+    R F[4];
+    tot_flux(d, U, w[0], w[1], w[2], gr, ph, F);
+    const R b = bvisc2_dir(d, w[2], w[3], gr[0], gr[1], gr[2], gr[3], gr[4], gr[5], ph);
+    R* S = d == 0 ? &T.SX[0][0] : &T.SY[0][0];
+    const int n = d == 0 ? NSX : NSY, o = d == 0 ? ox : oy;
+    S[o] = F[1];
+    S[n + o] = F[2];
+    S[2 * n + o] = F[3];
+    S[3 * n + o] = b;
+  }
+}
+
+// low-order point value U^L = U - sum_d (2 dt/h_d) (F^L(z, z+e_d) - F^L(z-e_d, z))
+// of the point at (lx, ly), with the LLF flux
+// F^L(a, b) = (F_a + F_b)/2 - (max(|u_d|+c) + max(b_d))/2 (U_b - U_a),
+// from the site data of lo_site
+template <typename R>
+__device__ __forceinline__ void lo_point(const Tile<R>& T, int lx, int ly, double dx, double dy,
+                                         double dt, R* UL) {
+  const R ihx = R(1.0 / dx), ihy = R(1.0 / dy);
+  R U0[4], w0[5];
+  lo_state(T, lx, ly, U0, w0);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) UL[k] = U0[k];
+  const int sx = lx - 3, sy = ly - 3;
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+    const R* S = d == 0 ? &T.SX[0][0] : &T.SY[0][0];
+    const int n = d == 0 ? NSX : NSY;
+    const int o0 = d == 0 ? (sy - 1) * SW + sx : sy * (2 * TX) + sx - 1;
+    const int st = d == 0 ? 1 : 2 * TX;
+    const R F0[4] = {U0[1 + d], S[o0], S[n + o0], S[2 * n + o0]};
+    const R b0 = S[3 * n + o0];
     const R r0 = fabs(w0[d]) + w0[4];
-    const R b0 = d == 0 ? bx0 : by0;
     R Fp[4];
-    // the two neighbours one after the other (rolled: short live ranges)
-#pragma unroll 1
+#pragma unroll
     for (int sg = 1; sg >= -1; sg -= 2) {
       const int nx = lx + (d == 0 ? sg : 0), ny = ly + (d == 1 ? sg : 0);
-      R Un[4], wn[5], gn[6], Fn[4];
+      const int on = o0 + sg * st;
+      R Un[4], wn[5];
       lo_state(T, nx, ny, Un, wn);
-      lo_grad(T, nx, ny, ihx, ihy, gn);
-      tot_flux(d, Un, wn[0], wn[1], wn[2], gn, ph, Fn);
-      const R bn = bvisc2_dir(d, wn[2], wn[3], gn[0], gn[1], gn[2], gn[3], gn[4], gn[5], ph);
+      const R Fn[4] = {Un[1 + d], S[on], S[n + on], S[2 * n + on]};
+      const R bn = S[3 * n + on];
       const R lam = mx(r0, fabs(wn[d]) + wn[4]) + mx(b0, bn);
       if (sg == 1) {
 #pragma unroll
@@ -913,18 +950,17 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
     }
   }
 
-  // ---- phase 5a: low-order point values (Sec. 3.4), staged in LDS ----
+  // ---- phase 5a: site data of the low-order point scheme (Sec. 3.4); it
+  //      shares no LDS with phase 4, and starts on the threads phase 4 leaves
+  //      idle ----
   if (ph.lim & LIM_POINT) {
-    for (int s = tid; s < NPT; s += NT) {
-      const int t = s / (TX * TY), r = s % (TX * TY);
-      const int i = i0 + r % TX, j = j0 + r / TX;
-      if (i >= (t == 1 ? g.n1 : g.n1x) || j >= (t == 0 ? g.n2 : g.n2y)) continue;
-      const int X = t == 1 ? 2 * i + 1 : 2 * i;
-      const int Y = t == 0 ? 2 * j + 1 : 2 * j;
-      R UL[4];
-      lo_point(T, ph, X - X0 + 4, Y - Y0 + 4, g.dx, g.dy, dt, UL);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) T.STG[k * NPT + s] = UL[k];
+    const R ihx = R(1.0 / g.dx), ihy = R(1.0 / g.dy);
+    for (int s = (tid + NT - TX * TY) % NT; s < NSR; s += NT) {
+      const int sx = s % SW, sy = s / SW;
+      const bool need_x = sy >= 1 && sy <= 2 * TY, need_y = sx >= 1 && sx <= 2 * TX;
+      if (need_x || need_y)
+        lo_site(T, ph, sx + 3, sy + 3, ihx, ihy, need_x, need_y, (sy - 1) * SW + sx,
+                sy * (2 * TX) + sx - 1);
     }
     __syncthreads();
   }
@@ -1030,9 +1066,11 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
         UH[k] = U0[k] + dt * double(Rs[k]);
       }
       if (ph.lim & LIM_POINT) {
+        R ULr[4];
+        lo_point(T, X - X0 + 4, Y - Y0 + 4, g.dx, g.dy, dt, ULr);
         double UL[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) UL[k] = T.STG[k * NPT + s];
+        for (int k = 0; k < 4; ++k) UL[k] = ULr[k];
         bool lbad = false;
         double th = theta_pair2(UL, UH, phd.gm1, lbad);
         if (ph.lim & LIM_LOWONLY) th = 0.0;
