@@ -91,10 +91,15 @@ __device__ __forceinline__ int axis_image(int X, int twon, int lo, int hi, int& 
 struct Signs {
   double sx, sy;
 };
-__device__ __forceinline__ Signs image_signs(int kx, int ky) {
+// the same as bits: bit 0 negates the x momentum, bit 1 the y momentum
+__device__ __forceinline__ int image_flips(int kx, int ky) {
   const int fx = (kx == BC_NOSLIP || kx == BC_SYMMETRY) ^ (ky == BC_NOSLIP);
   const int fy = (kx == BC_NOSLIP) ^ (ky == BC_NOSLIP || ky == BC_SYMMETRY);
-  return Signs{fx ? -1.0 : 1.0, fy ? -1.0 : 1.0};
+  return fx | (fy << 1);
+}
+__device__ __forceinline__ Signs image_signs(int kx, int ky) {
+  const int f = image_flips(kx, ky);
+  return Signs{(f & 1) ? -1.0 : 1.0, (f & 2) ? -1.0 : 1.0};
 }
 
 // ---------------------------------------------------------------------------

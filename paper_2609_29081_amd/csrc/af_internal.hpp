@@ -29,7 +29,6 @@ struct Geo {
 struct StageGeo {
   int n1, n2, n1x, n2y;
   long off_xe, off_ye, off_co;
-  int st_avg, st_xe, st_ye, st_co;  // distance between component planes
   int bc0, bc1, bc2, bc3;
   double dx, dy;
 };
@@ -43,10 +42,6 @@ inline StageGeo stage_geo(const Geo& g) {
   r.off_xe = g.off_xe;
   r.off_ye = g.off_ye;
   r.off_co = g.off_co;
-  r.st_avg = g.n1 * g.n2;
-  r.st_xe = g.n2 * g.n1x;
-  r.st_ye = g.n2y * g.n1;
-  r.st_co = g.n2y * g.n1x;
   r.bc0 = g.bc[0];
   r.bc1 = g.bc[1];
   r.bc2 = g.bc[2];

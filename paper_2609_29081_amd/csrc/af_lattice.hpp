@@ -13,14 +13,18 @@ using G2 = afi::StageGeo;
 // offset of interior lattice site (X, Y) in a state (its first component;
 // centre sites hold the cell average, the periodic seam is folded) and the
 // distance between its component planes.  Plane indices fit 32 bits (the
-// grid size is bounded at init).
+// grid size is bounded at init).  The grid is the same for the whole wave:
+// its sizes are taken as wave-uniform values, so that the per-site choice
+// among them is a register select, never a per-lane load of a size.
 __device__ __forceinline__ void site_ofs(const G2& g, int X, int Y, long& o, int& st) {
-  if (X == 2 * g.n1 && g.n1x == g.n1) X = 0;
-  if (Y == 2 * g.n2 && g.n2y == g.n2) Y = 0;
+  const int n1 = __builtin_amdgcn_readfirstlane(g.n1), n1x = __builtin_amdgcn_readfirstlane(g.n1x);
+  const int n2 = __builtin_amdgcn_readfirstlane(g.n2), n2y = __builtin_amdgcn_readfirstlane(g.n2y);
+  if (X == 2 * n1 && n1x == n1) X = 0;
+  if (Y == 2 * n2 && n2y == n2) Y = 0;
   const bool xo = X & 1, yo = Y & 1;
-  const int ncol = xo ? g.n1 : g.n1x;
+  const int ncol = xo ? n1 : n1x;
   const long base = xo ? (yo ? 0L : g.off_ye) : (yo ? g.off_xe : g.off_co);
-  st = xo ? (yo ? g.st_avg : g.st_ye) : (yo ? g.st_xe : g.st_co);
+  st = ncol * (yo ? n2 : n2y);
   o = base + (long)((Y >> 1) * ncol + (X >> 1));
 }
 

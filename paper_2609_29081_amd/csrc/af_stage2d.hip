@@ -431,11 +431,14 @@ __device__ __forceinline__ void lo_point(const Tile<R>& T, int lx, int ly, doubl
 
 // raw values of the lattice region of the tile at (X0, Y0): point sites hold
 // their DOF, centre sites the cell average, ghosts as boundary images.  Each
-// thread gathers the sites tid, tid+NT, tid+2NT into registers.
+// thread gathers the sites tid, tid+NT, tid+2NT into registers, with the
+// image's momentum sign flips as bits: the loads are only issued here, and
+// nothing waits for them before the values are stored to LDS.
 constexpr int kRawPerThread = (NA + NT - 1) / NT;
 
 __device__ __forceinline__ void load_raw(const G2& g, const double* __restrict__ Uk, int X0, int Y0,
-                                         int tid, double (&pre)[kRawPerThread][4]) {
+                                         int tid, double (&pre)[kRawPerThread][4],
+                                         int (&flip)[kRawPerThread]) {
   const int Xlim = 2 * g.n1, Ylim = 2 * g.n2;
 #pragma unroll
   for (int r = 0; r < kRawPerThread; ++r) {
@@ -445,17 +448,13 @@ __device__ __forceinline__ void load_raw(const G2& g, const double* __restrict__
     int kx, ky;
     const int Xi = axis_image(X, Xlim, g.bc0, g.bc1, kx);
     const int Yi = axis_image(Y, Ylim, g.bc2, g.bc3, ky);
-    const Signs sg = image_signs(kx, ky);
-    const double sx = sg.sx, sy = sg.sy;
+    flip[r] = image_flips(kx, ky);
     long o;
     int st;
     site_ofs(g, Xi, Yi, o, st);
     const double* src = Uk + o;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const double v = src[(long)k * st];
-      pre[r][k] = k == 1 ? sx * v : (k == 2 ? sy * v : v);
-    }
+    for (int k = 0; k < 4; ++k) pre[r][k] = src[(long)k * st];
   }
 }
 
@@ -632,9 +631,10 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
   TileIter it(ntiles, blockIdx.x, gridDim.x);
   int tile = it.get();
   double pre[kRawPerThread][4];
+  int flip[kRawPerThread] = {};
   if (tile >= 0) {
     const TileArgs A = args(tile);
-    load_raw(*A.g, A.Uk, 2 * TX * (A.lt % A.ntx), 2 * TY * (A.lt / A.ntx), tid, pre);
+    load_raw(*A.g, A.Uk, 2 * TX * (A.lt % A.ntx), 2 * TY * (A.lt / A.ntx), tid, pre, flip);
   }
   while (tile >= 0) {
   const TileArgs A = args(tile);
@@ -659,7 +659,7 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
       const int nt = it.advance();
       if (nt >= 0) {
         const TileArgs An = args(nt);
-        load_raw(*An.g, An.Uk, 2 * TX * (An.lt % An.ntx), 2 * TY * (An.lt / An.ntx), tid, pre);
+        load_raw(*An.g, An.Uk, 2 * TX * (An.lt % An.ntx), 2 * TY * (An.lt / An.ntx), tid, pre, flip);
       }
       tile = nt;
       continue;
@@ -675,7 +675,10 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
     const int X = X0 - 4 + s % WA, Y = Y0 - 4 + s / WA;
     if (s >= NA || X > Xlim + kMargin || Y > Ylim + kMargin) continue;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) T.U[k][s] = R(pre[r][k]);
+    for (int k = 0; k < 4; ++k) {
+      const bool neg = (k == 1 && (flip[r] & 1)) || (k == 2 && (flip[r] & 2));
+      T.U[k][s] = R(neg ? -pre[r][k] : pre[r][k]);
+    }
   }
   __syncthreads();
 
@@ -762,7 +765,7 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
   const int next = it.advance();
   if (next >= 0) {
     const TileArgs An = args(next);
-    load_raw(*An.g, An.Uk, 2 * TX * (An.lt % An.ntx), 2 * TY * (An.lt / An.ntx), tid, pre);
+    load_raw(*An.g, An.Uk, 2 * TX * (An.lt % An.ntx), 2 * TY * (An.lt / An.ntx), tid, pre, flip);
   }
 
   // ---- phase 1: gradients on the block +- 2 ----
@@ -933,6 +936,12 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
       if (i >= g.n1 || j >= g.n2) continue;
       const int c = (jj + 1) * WC + ii + 1;
       const long gi = (long)j * g.n1 + i;
+      // U^n of the cell, all four loads in flight together
+      double un[4] = {0.0, 0.0, 0.0, 0.0};
+      if (!first) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) un[k] = Un[k * nc + gi];
+      }
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const double dfx = double(T.FX[k][jj * (TX + 1) + ii + 1]) - double(T.FX[k][jj * (TX + 1) + ii]);
@@ -943,7 +952,7 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
         else
           av = T.AV[k][c];
         const double fe = av - mxd * dfx - myd * dfy;
-        const double o = first ? fe : ca * Un[k * nc + gi] + cb * fe;
+        const double o = first ? fe : ca * un[k] + cb * fe;
         if (!isfinite(o)) nonfinite = true;
         Uout[k * nc + gi] = o;
       }
@@ -979,6 +988,15 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
       const int Y = t == 0 ? 2 * j + 1 : 2 * j;
       const int a = (Y - Y0 + 4) * WA + (X - X0 + 4);
       const int q = (Y - Y0 + 2) * WG + (X - X0 + 2);
+      const long gi = (long)j * ni + i;
+      // the point's HBM operands, loaded while the residual is computed:
+      // U^n for the RK combination and, for FP32 stencils, the FP64 value
+      double un[4] = {0.0, 0.0, 0.0, 0.0}, U0[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (!first) un[k] = Un[off + k * np + gi];
+        if constexpr (!kFP64<R>) U0[k] = Uk[off + k * np + gi];
+      }
       R Rs[4] = {R(0.0), R(0.0), R(0.0), R(0.0)};
 #pragma unroll
       for (int d = 0; d < 2; ++d) {
@@ -1054,15 +1072,11 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
         Rs[2] += dc5(m2[0], m2[1], m2[3], m2[4], i6h);
         Rs[3] += dc5(m3[0], m3[1], m3[3], m3[4], i6h);
       }
-      const long gi = (long)j * ni + i;
       // the point update and its blend in FP64, from the FP64 point value
-      double U0[4], UH[4], out[4];
+      double UH[4], out[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        if constexpr (kFP64<R>)
-          U0[k] = T.U[k][a];
-        else
-          U0[k] = Uk[off + k * np + gi];
+        if constexpr (kFP64<R>) U0[k] = T.U[k][a];
         UH[k] = U0[k] + dt * double(Rs[k]);
       }
       if (ph.lim & LIM_POINT) {
@@ -1088,7 +1102,7 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const long idx = off + k * np + gi;
-        const double o = first ? out[k] : ca * Un[idx] + cb * out[k];
+        const double o = first ? out[k] : ca * un[k] + cb * out[k];
         if (!isfinite(o)) nonfinite = true;
         Uout[idx] = o;
       }
