@@ -26,6 +26,7 @@ HBM_PEAK_GBS = 8000.0
 FP64_VALU_PEAK_TFLOPS = 78.6
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = ["paper_2609_29081_amd/csrc/af_stage2d.hip", "paper_2609_29081_amd/csrc/af_device.hpp",
+                  "paper_2609_29081_amd/csrc/af_lattice.hpp",
                   "paper_2609_29081_amd/csrc/af_internal.hpp", "paper_2609_29081_amd/build.py"]
 
 
