@@ -105,7 +105,7 @@ def main() -> int:
     from paper_2609_29081_amd import workloads as W
 
     gamma = 1.4
-    kw = dict(gamma=gamma, mu=0.005, Pr=0.73, cfl_c=0.2, cfl_v=0.075, limiter=af.LIM_ALL)
+    kw = dict(gamma=gamma, mu=0.005, Pr=0.73, cfl_c=0.2, cfl_v=0.05, limiter=af.LIM_ALL)
     g, f = W.shock_tube_2d(args.n1, args.n2, gamma=gamma)
     U0 = W.make_state(g, f, gamma)
     S = af.Solver(g, **kw)
@@ -293,7 +293,7 @@ def main() -> int:
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"2D viscous shock tube {g.n1}x{g.n2} on [0,1]x[0,0.5], "
                                "rho 120|1.2, p=rho/gamma, mu=0.005 (Re=200), Pr=0.73, "
-                               "gamma=1.4, no-slip walls + symmetry top, SSP-RK3, CFL 0.2/0.075, "
+                               "gamma=1.4, no-slip walls + symmetry top, SSP-RK3, CFL 0.2/0.05, "
                                "all limiters, FP64",
                    "n1": g.n1, "n2": g.n2, "dof_sites": dof_sites, "stages_per_step": 3},
         "cell_updates_per_s": cell_rate,
@@ -335,7 +335,7 @@ def learned_form(args, stream) -> dict:
     from paper_2609_29081_amd import workloads as W
 
     gamma = 1.4
-    kw = dict(gamma=gamma, mu=0.005, Pr=0.73, cfl_c=0.2, cfl_v=0.075)
+    kw = dict(gamma=gamma, mu=0.005, Pr=0.73, cfl_c=0.2, cfl_v=0.05)
     dev = torch.device("cuda:0")
     print("bench: learned blend, training data", file=sys.stderr, flush=True)
     g3, f3 = W.shock_tube_2d(1000, 500, gamma=gamma)
@@ -436,7 +436,7 @@ def batched_form(args, stream) -> dict:
 
     print(f"bench: batched sweep of {args.batch_n} shock tubes", file=sys.stderr, flush=True)
     insts = W.shock_tube_sweep(args.batch_n, seed=0)
-    solvers = [af.Solver(g, precision=af.PREC_MIXED, cfl_c=0.2, cfl_v=0.075,
+    solvers = [af.Solver(g, precision=af.PREC_MIXED, cfl_c=0.2, cfl_v=0.05,
                          limiter=af.LIM_ALL, **kw) for g, f, kw in insts]
     init = [S.to_device(W.make_state(g, f, kw["gamma"])) for S, (g, f, kw) in zip(solvers, insts)]
     states = [U.clone() for U in init]

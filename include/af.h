@@ -100,7 +100,11 @@ typedef struct af_params {
   double gamma;         /* ratio of specific heats, > 1                           */
   double mu;            /* dynamic viscosity, >= 0                                */
   double Pr;            /* Prandtl number, > 0                                    */
-  double cfl_c, cfl_v;  /* C^c and C^v of the CFL condition (eq. cfl), > 0        */
+  double cfl_c, cfl_v;  /* C^c and C^v of the CFL condition (eq. cfl), > 0.  Under
+                           SSP-RK3 the scheme's linearisation about a uniform
+                           state is stable for viscous numbers (dt max(4mu/3rho,
+                           gamma mu/(Pr rho))/dx^2) up to about 0.157 in 1D and
+                           0.061 in 2D, so cfl_v <= 0.15 (1D) and <= 0.06 (2D)  */
   double Cs;            /* smoothness-limiter strength (paper: 1), >= 0           */
   int limiter;          /* AF_LIM_* bits                                          */
   int max_halvings;     /* retries of a step with halved dt (>= 0)               */
@@ -108,7 +112,9 @@ typedef struct af_params {
   int rk;               /* time integrator of af_step / af_run: 3 (SSP-RK3) or 54
                            (SSP-RK54, the five-stage fourth-order SSP method of
                            Sec. 2.3; the paper pairs it with cfl_c = 1.04/d and
-                           cfl_v = 0.33/d)                                        */
+                           cfl_v = 0.33/d, which the 2D scheme's linearisation
+                           exceeds when viscosity dominates: its viscous limit
+                           under SSP-RK54 is about 0.13 in 2D)                   */
 } af_params;
 
 /* arithmetic of the 2D stage.  AF_PREC_MIXED: the stencils, fluxes and
@@ -121,7 +127,7 @@ enum { AF_PREC_FP64 = 0, AF_PREC_MIXED = 1 };
 typedef struct af_ctx af_ctx;
 
 /* Fill p with defaults: 2D 64x64 on [0,1]^2, gamma 1.4, mu 1e-3, Pr 0.72,
- * cfl_c 0.2, cfl_v 0.075, Cs 1, all limiters, max_halvings 40, FP64,
+ * cfl_c 0.2, cfl_v 0.05, Cs 1, all limiters, max_halvings 40, FP64,
  * SSP-RK3. */
 af_status af_default_params(af_params* p);
 

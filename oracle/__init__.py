@@ -92,7 +92,7 @@ def _p(a: np.ndarray):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
-def make_cfg(grid, gamma=1.4, mu=1e-3, Pr=0.72, limiter=LIM_ALL, cfl_c=0.2, cfl_v=0.075,
+def make_cfg(grid, gamma=1.4, mu=1e-3, Pr=0.72, limiter=LIM_ALL, cfl_c=0.2, cfl_v=0.05,
              Cs=1.0, max_halvings=40, rk=3, bcstate=None) -> Cfg:
     c = Cfg()
     c.dim, c.n1, c.n2 = grid.dim, grid.n1, grid.n2

@@ -152,7 +152,7 @@ class Solver:
     """One grid: wraps af_init_grid / af_set_bc and owns the torch-allocated
     workspace.  States are flat float64 CUDA tensors of length state_len."""
 
-    def __init__(self, grid: W.Grid, gamma=1.4, mu=1e-3, Pr=0.72, cfl_c=0.2, cfl_v=0.075,
+    def __init__(self, grid: W.Grid, gamma=1.4, mu=1e-3, Pr=0.72, cfl_c=0.2, cfl_v=0.05,
                  limiter=LIM_ALL, Cs=1.0, max_halvings=40, precision=0, rk=3, bcstate=None,
                  device="cuda:0"):
         p = Params()

@@ -373,7 +373,7 @@ af_status af_default_params(af_params* p) {
   p->mu = 1e-3;
   p->Pr = 0.72;
   p->cfl_c = 0.2;
-  p->cfl_v = 0.075;
+  p->cfl_v = 0.05;
   p->Cs = 1.0;
   p->limiter = AF_LIM_ALL;
   p->max_halvings = 40;

@@ -58,7 +58,7 @@ def target(reps: int = 3, mixed: bool = False) -> None:
     from paper_2609_29081_amd import workloads as W
 
     g, f = W.shock_tube_2d(N1, N2)
-    S = af.Solver(g, mu=0.005, Pr=0.73, cfl_c=0.2, cfl_v=0.075,
+    S = af.Solver(g, mu=0.005, Pr=0.73, cfl_c=0.2, cfl_v=0.05,
                   precision=af.PREC_MIXED if mixed else af.PREC_FP64)
     U0 = S.to_device(W.make_state(g, f, 1.4))
     stage_sequence(S, U0, reps)
@@ -81,7 +81,7 @@ def target_batch(steps: int = 3) -> None:
     from paper_2609_29081_amd import workloads as W
 
     insts = W.shock_tube_sweep(64, seed=0)
-    solvers = [af.Solver(g, precision=af.PREC_MIXED, cfl_c=0.2, cfl_v=0.075, **kw)
+    solvers = [af.Solver(g, precision=af.PREC_MIXED, cfl_c=0.2, cfl_v=0.05, **kw)
                for g, f, kw in insts]
     states = [S.to_device(W.make_state(g, f, kw["gamma"])) for S, (g, f, kw) in zip(solvers, insts)]
     B = af.Batch(solvers)
@@ -104,7 +104,7 @@ def target_learned(steps: int = 3) -> None:
     from paper_2609_29081_amd import workloads as W
 
     g, f = W.shock_tube_2d(2048, 1024)
-    S = af.Solver(g, mu=0.005, Pr=0.73, cfl_c=0.2, cfl_v=0.075,
+    S = af.Solver(g, mu=0.005, Pr=0.73, cfl_c=0.2, cfl_v=0.05,
                   limiter=af.LIM_ALL | af.LIM_LEARNED)
     P = torch.as_tensor(W.mlp_init(0), device=S.device)
     S.af_set_blend_net(P)

@@ -277,7 +277,7 @@ def test_training_brings_learned_runs_to_the_plain_limiter():
     P = P0.clone()
     m, v = torch.zeros_like(P), torch.zeros_like(P)
     idx = torch.as_tensor(W.balanced_rows(y.cpu().numpy(), seed=0), device=dev)
-    af.mlp_train(X[idx].contiguous(), y[idx].contiguous(), P, m, v, 0, 3000, 512, 2e-3)
+    af.mlp_train(X[idx].contiguous(), y[idx].contiguous(), P, m, v, 0, 6000, 512, 2e-3)
 
     def run(limiter, net, t_final):
         R = af.Solver(g, limiter=limiter, **kw)

@@ -285,7 +285,7 @@ def test_full_size_shock_tube_steps():
     the benchmark launches it, against the oracle over two whole steps"""
     g, f = W.shock_tube_2d(1000, 500)
     U = W.make_state(g, f, GAMMA)
-    kw = dict(mu=0.005, Pr=0.73, cfl_c=0.2, cfl_v=0.075)
+    kw = dict(mu=0.005, Pr=0.73, cfl_c=0.2, cfl_v=0.05)
     cfg = O.make_cfg(g, **kw)
     S = solver_for(g, **kw)
     Ud = S.to_device(U)
