@@ -258,18 +258,21 @@ struct Tile {
 };
 static_assert(4 * NSY <= 14 * NC, "the y-direction site data fit in rows 0-13 of C");
 
-// auxiliaries (u, v, p, T, c) of LDS lattice site s
+// auxiliaries (u, v, p, T, c) of LDS lattice site s from its FP64 value V:
+// the pressure of a state whose internal energy is a small part of its
+// total is a difference of nearly equal numbers, so it is taken in FP64
+// before the FP32 stencils see it
 template <typename R>
-__device__ __forceinline__ void store_aux(Tile<R>& T, const PhysT<R>& ph, int s) {
-  const R r = T.U[0][s], m1 = T.U[1][s], m2 = T.U[2][s], E = T.U[3][s];
-  const R ir = rcp(r);
-  const R p = ph.gm1 * (E - R(0.5) * (m1 * m1 + m2 * m2) * ir);
-  const R Tt = p * ir;
-  T.A[0][s] = m1 * ir;
-  T.A[1][s] = m2 * ir;
-  T.A[2][s] = p;
-  T.A[3][s] = Tt;
-  T.A[4][s] = sqrt(ph.gam * Tt);
+__device__ __forceinline__ void store_aux(Tile<R>& T, const PhysT<double>& pd, int s,
+                                          const double* V) {
+  const double ir = rcp(V[0]);
+  const double p = pd.gm1 * (V[3] - 0.5 * (V[1] * V[1] + V[2] * V[2]) * ir);
+  const double Tt = p * ir;
+  T.A[0][s] = R(V[1] * ir);
+  T.A[1][s] = R(V[2] * ir);
+  T.A[2][s] = R(p);
+  T.A[3][s] = R(Tt);
+  T.A[4][s] = R(sqrt(pd.gam * Tt));
 }
 
 // total flux F_d = F^c_d - F^v_d at an LDS site (a: block+-4 index, q: block+-2 index)
@@ -384,15 +387,16 @@ __device__ __forceinline__ void lo_site(Tile<R>& T, const PhysT<R>& ph, int lx, 
 // low-order point value U^L = U - sum_d (2 dt/h_d) (F^L(z, z+e_d) - F^L(z-e_d, z))
 // of the point at (lx, ly), with the LLF flux
 // F^L(a, b) = (F_a + F_b)/2 - (max(|u_d|+c) + max(b_d))/2 (U_b - U_a),
-// from the site data of lo_site
+// from the site data of lo_site.  The update is subtracted from the FP64
+// point value U0d, so that U^L tends to it as dt does
 template <typename R>
 __device__ __forceinline__ void lo_point(const Tile<R>& T, int lx, int ly, double dx, double dy,
-                                         double dt, R* UL) {
+                                         double dt, const double* U0d, double* UL) {
   const R ihx = R(1.0 / dx), ihy = R(1.0 / dy);
   R U0[4], w0[5];
   lo_state(T, lx, ly, U0, w0);
 #pragma unroll
-  for (int k = 0; k < 4; ++k) UL[k] = U0[k];
+  for (int k = 0; k < 4; ++k) UL[k] = kFP64<R> ? double(U0[k]) : U0d[k];
   const int sx = lx - 3, sy = ly - 3;
 #pragma unroll
   for (int d = 0; d < 2; ++d) {
@@ -422,7 +426,7 @@ __device__ __forceinline__ void lo_point(const Tile<R>& T, int lx, int ly, doubl
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const R Fm = R(0.5) * (Fn[k] + F0[k]) - R(0.5) * lam * (U0[k] - Un[k]);
-          UL[k] -= c * (Fp[k] - Fm);
+          UL[k] -= double(c * (Fp[k] - Fm));
         }
       }
     }
@@ -641,6 +645,7 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
   const G2& g = *A.g;
   const Phys& phd = *A.phd;
   const PhysT<R> ph = phys_as<R>(phd);
+  const PhysT<double> phd64 = phys_as<double>(phd);
   const double* __restrict__ Uk = A.Uk;
   const double* __restrict__ Un = A.Un;
   double* __restrict__ Uout = A.Uout;
@@ -674,10 +679,18 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
     const int s = tid + r * NT;
     const int X = X0 - 4 + s % WA, Y = Y0 - 4 + s / WA;
     if (s >= NA || X > Xlim + kMargin || Y > Ylim + kMargin) continue;
+    double V[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const bool neg = (k == 1 && (flip[r] & 1)) || (k == 2 && (flip[r] & 2));
-      T.U[k][s] = R(neg ? -pre[r][k] : pre[r][k]);
+      V[k] = neg ? -pre[r][k] : pre[r][k];
+      T.U[k][s] = R(V[k]);
+    }
+    // FP32 stencils: the point sites' (u, v, p, T, c) from the FP64 values
+    // (centre sites get the Simpson centre's); the FP64 stage takes them in
+    // phase 2, where they cost fewer live registers
+    if constexpr (!kFP64<R>) {
+      if (!((X & 1) && (Y & 1))) store_aux(T, phd64, s, V);
     }
   }
   __syncthreads();
@@ -744,10 +757,13 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
       for (int k = 0; k < 4; ++k) T.AV[k][s] = V[k];
     }
   }
-  for (int s = tid; s < NA; s += NT) {
-    const int X = X0 - 4 + s % WA, Y = Y0 - 4 + s / WA;
-    if (X > Xlim + kMargin || Y > Ylim + kMargin || ((X & 1) && (Y & 1))) continue;
-    store_aux(T, ph, s);
+  if constexpr (kFP64<R>) {
+    for (int s = tid; s < NA; s += NT) {
+      const int X = X0 - 4 + s % WA, Y = Y0 - 4 + s / WA;
+      if (X > Xlim + kMargin || Y > Ylim + kMargin || ((X & 1) && (Y & 1))) continue;
+      const double V[4] = {T.U[0][s], T.U[1][s], T.U[2][s], T.U[3][s]};
+      store_aux(T, phd64, s, V);
+    }
   }
   __syncthreads();
   for (int cidx = tid - NT / 2; cidx >= 0 && cidx < NCEN; cidx += NT / 2) {
@@ -1080,11 +1096,8 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
         UH[k] = U0[k] + dt * double(Rs[k]);
       }
       if (ph.lim & LIM_POINT) {
-        R ULr[4];
-        lo_point(T, X - X0 + 4, Y - Y0 + 4, g.dx, g.dy, dt, ULr);
         double UL[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) UL[k] = ULr[k];
+        lo_point(T, X - X0 + 4, Y - Y0 + 4, g.dx, g.dy, dt, U0, UL);
         bool lbad = false;
         double th = theta_pair2(UL, UH, phd.gm1, lbad);
         if (ph.lim & LIM_LOWONLY) th = 0.0;
