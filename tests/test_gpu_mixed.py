@@ -134,3 +134,20 @@ def test_mixed_full_size_shock_tube_two_steps():
     print(f"shock tube 1000x500, 2 steps: worst relative error {worst:.3e}")
     assert worst <= REL_TOL_MIXED
     assert S.af_check_admissible(Ud) == 0
+
+
+def test_mixed_cold_jet_stays_finite():
+    """a sweep instance (768x384, Re 635, density ratio 190) whose early
+    steps make a cold, fast jet where the diaphragm meets the bottom wall:
+    internal energy a fraction of a percent of the total.  The point
+    auxiliaries and low-order point values are taken from FP64 values, so
+    the FP32 stencils never see a negative pressure; before that, the run
+    ended with a non-finite state at step 80"""
+    g, f, kw = W.shock_tube_sweep(64, seed=0)[3]
+    assert (g.n1, g.n2) == (768, 384)
+    S = mixed_solver(g, **kw)
+    Ud = S.to_device(W.make_state(g, f, kw["gamma"]))
+    st, n, t = S.af_run(Ud, 0.0, 1e30, 100, check_every=1)
+    assert st == af.AF_OK and n == 100
+    assert torch.isfinite(Ud).all()
+    assert S.af_check_admissible(Ud) == 0
