@@ -16,6 +16,8 @@
 //   phase 3  limited face fluxes of the tile's cells: Simpson high-order
 //            flux, LLF low-order flux, theta^s, theta^rho theta^p (Sec. 3.3)
 //   phase 4  cell-average update and RK combination
+//   phase 5a total flux and b of every lattice site the point LLF of Sec.
+//            3.4 reads, once per site and direction (beside phase 4)
 //   phase 5  point residual (biased inviscid operators with the downwind
 //            point, compact D^2, mixed terms; Sec. 2.2), point LLF on the
 //            lattice of point values and cell averages and the scaling limiter
@@ -25,8 +27,9 @@
 // and residuals (LDS included).  R = double is the FP64 stage.  R = float is
 // the mixed-precision stage: stencils and fluxes in FP32, while the density
 // and pressure blends (the Theta rule of Sec. 3.3 and 3.4), the cell-average
-// update and the point-value update stay FP64 on FP64 data read from the
-// state; the state itself is FP64 in both.
+// update, the point-value update and the low-order point value stay FP64 on
+// FP64 data read from the state, and the point sites' (u, v, p, T, c) are
+// taken from their FP64 values; the state itself is FP64 in both.
 #include <type_traits>
 
 #include "af_device.hpp"
@@ -698,7 +701,8 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
   // ---- phase 2: centre values (Simpson + scaling; waves 4-7, compact
   //      mapping, staged until the cells have read the averages in the centre
   //      slots), cell low-order data of the tile +- 1 (waves 0-2),
-  //      auxiliaries of the point sites (all) ----
+  //      auxiliaries of the point sites (all; FP64 stage only, the FP32
+  //      stencils took theirs in phase 0a) ----
   // lattice slot of centre cidx of the region, or -1 beyond the grid's ghosts
   auto centre_slot = [&](int cidx) {
     const int X = X0 - 3 + 2 * (cidx % (TX + 4)), Y = Y0 - 3 + 2 * (cidx / (TX + 4));
