@@ -24,6 +24,8 @@ sys.path.insert(0, ROOT)
 METRIC = "cell-DOF updates/s per RK stage, 2D viscous shock tube; % peak HBM BW; L1 err"
 HBM_PEAK_GBS = 8000.0
 FP64_VALU_PEAK_TFLOPS = 78.6
+VALU_SIMDS = 1024      # 256 compute units x 4 SIMDs
+CLOCK_HZ = 2.4e9
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = ["paper_2609_29081_amd/csrc/af_stage2d.hip", "paper_2609_29081_amd/csrc/af_device.hpp",
                   "paper_2609_29081_amd/csrc/af_lattice.hpp",
@@ -182,7 +184,7 @@ def main() -> int:
     dom = max(kt.items(), key=lambda kv: kv[1][1])[0]
     dom_avg_s = kt[dom][1] / kt[dom][0] * 1e-3
     achieved = alg[dom] / dom_avg_s / 1e9
-    traffic = flops = None
+    traffic = flops = valu = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fh:
             tr = json.load(fh)
@@ -190,6 +192,7 @@ def main() -> int:
                 and tr.get("n1") == g.n1 and tr.get("n2") == g.n2:
             traffic = tr.get("bytes_per_launch")
             flops = tr.get("fp64_flops_per_launch")
+            valu = tr.get("instructions_per_launch", {}).get("SQ_INSTS_VALU")
     hbm = {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": alg[dom]}
     if flops:
@@ -204,6 +207,14 @@ def main() -> int:
                                   "instruction), an upper bound on the algorithmic count",
                     "avg_launch_us": round(dom_avg_s * 1e6, 3), "hbm": hbm,
                     "timed_window": window}
+        if valu:
+            # issue rate of all VALU wave instructions (a wave64 instruction
+            # occupies its SIMD for four cycles; 1024 SIMDs at 2.4 GHz)
+            roofline["valu_issue"] = {
+                "wave_instructions_per_launch": valu,
+                "frac": round(valu * 4.0 / (VALU_SIMDS * CLOCK_HZ * dom_avg_s), 4),
+                "what": "all VALU wave instructions (counters) x 4 cycles / (SIMDs x clock x "
+                        "launch time)"}
     else:
         roofline = dict({"bound": "hbm", "kernel": dom, "traffic": traffic,
                          "avg_launch_us": round(dom_avg_s * 1e6, 3), "timed_window": window},
