@@ -388,31 +388,35 @@ def learned_form(args, stream) -> dict:
     rmse_low = float(l_low.item()) ** 0.5
     rmse_one = float(((1.0 - yh[low]) ** 2).mean().item()) ** 0.5
 
+    t_final = 1e-4
+
+    def evaluate(gg, UU):
+        runs = {}
+        for name, lim, net in (("plain", af.LIM_ALL, None),
+                               ("learned", af.LIM_ALL | af.LIM_LEARNED, P),
+                               ("untrained", af.LIM_ALL | af.LIM_LEARNED, P0),
+                               ("no_smoothness", af.LIM_PP | af.LIM_POINT | af.LIM_CENTRE, None)):
+            S = af.Solver(gg, limiter=lim, **kw)
+            if net is not None:
+                S.af_set_blend_net(net)
+            Ud = S.to_device(UU)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            st, n, t = S.af_run(Ud, 0.0, t_final, 10 ** 6, check_every=1)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if st != af.AF_OK:
+                raise RuntimeError(f"{name} run failed: {st}")
+            ms = e0.elapsed_time(e1)
+            runs[name] = (gg.split(Ud.cpu().numpy())["avg"][0], n, ms)
+            del S, Ud
+        return runs
+
     print("bench: learned blend, 2048x1024 runs", file=sys.stderr, flush=True)
     g5, f5 = W.shock_tube_2d(2048, 1024, gamma=gamma)
-    U5 = W.make_state(g5, f5, gamma)
-    t_final = 1e-4
-    runs = {}
-    for name, lim, net in (("plain", af.LIM_ALL, None),
-                           ("learned", af.LIM_ALL | af.LIM_LEARNED, P),
-                           ("untrained", af.LIM_ALL | af.LIM_LEARNED, P0),
-                           ("no_smoothness", af.LIM_PP | af.LIM_POINT | af.LIM_CENTRE, None)):
-        S = af.Solver(g5, limiter=lim, **kw)
-        if net is not None:
-            S.af_set_blend_net(net)
-        Ud = S.to_device(U5)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        st, n, t = S.af_run(Ud, 0.0, t_final, 10 ** 6, check_every=1)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        if st != af.AF_OK:
-            raise RuntimeError(f"{name} run failed: {st}")
-        ms = e0.elapsed_time(e1)
-        runs[name] = (g5.split(Ud.cpu().numpy())["avg"][0], n, ms)
-        del S, Ud
+    runs = evaluate(g5, W.make_state(g5, f5, gamma))
     rho_plain = runs["plain"][0]
     out = {"workload": "2D viscous shock tube 2048x1024 (Re=200, FP64) from t=0 to t=1e-4; "
                        "network trained on theta^s of the 1000x500 tube after steps "
@@ -428,6 +432,10 @@ def learned_form(args, stream) -> dict:
         out[name] = {"value": g5.dof_sites * 3 * n / (ms / 1e3), "unit": "DOF-updates/s",
                      "steps": n, "ms": round(ms, 1),
                      "l1_rho_vs_plain": float(np.abs(rho - rho_plain).sum() * g5.dx * g5.dy)}
+    # the same comparison at the training grid (1000 x 500, to the same t)
+    runs3 = evaluate(g3, W.make_state(g3, f3, gamma))
+    out["at_1000x500"] = {name: {"steps": n, "l1_rho_vs_plain": float(
+        np.abs(rho - runs3["plain"][0]).sum() * g3.dx * g3.dy)} for name, (rho, n, ms) in runs3.items()}
     out["value"] = out["learned"]["value"]
     return out
 
