@@ -23,7 +23,11 @@ SOURCES = [("af_capi.cpp", "af_capi.o", []),
            ("af_kern1d.hip", "af_kern1d.o", []),
            ("af_learn.hip", "af_learn.o", [])] + [
     ("af_stage2d.hip", f"{name}.o",
-     [f"-DAF_STAGE_REAL={real}", f"-DAF_STAGE_TY={ty}", f"-DAF_STAGE_ENTRY={name}"])
+     [f"-DAF_STAGE_REAL={real}", f"-DAF_STAGE_TY={ty}", f"-DAF_STAGE_ENTRY={name}",
+      # no hoisting of loop-invariant values out of the persistent tile
+      # loop: held across all phases they spilled; recomputed, the FP64
+      # stage spills nothing and runs 2 % faster
+      "-mllvm", "--disable-machine-licm"])
     for name, real, ty in STAGE_VARIANTS]
 ARCH = "gfx950"
 
