@@ -1,7 +1,7 @@
 """HBM traffic and FP64 instruction counts of the fused 2D stage kernel
 from rocprofv3 counters.
 
-    python -m paper_2609_29081_amd.prof_counters [--mixed]            # driver (GPU machine)
+    python -m paper_2609_29081_amd.prof_counters [--mixed]            # driver (on the GPU host)
     python -m paper_2609_29081_amd.prof_counters --target [--mixed]   # profiled program
     python -m paper_2609_29081_amd.prof_counters --target-batch       # batched sweep
     python -m paper_2609_29081_amd.prof_counters --target-learned     # learned blend
@@ -30,6 +30,7 @@ import json
 import os
 import subprocess
 import sys
+import tempfile
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 COPY_BYTES = 256 * 1024 * 1024
@@ -222,7 +223,7 @@ if __name__ == "__main__":
     ap.add_argument("--mixed", action="store_true")
     ap.add_argument("--target-batch", action="store_true")
     ap.add_argument("--target-learned", action="store_true")
-    ap.add_argument("--out", default=os.path.join(ROOT, "gpurun_out", "traffic"))
+    ap.add_argument("--out", default=os.path.join(tempfile.gettempdir(), "af_counters"))
     a = ap.parse_args()
     if a.target_learned:
         target_learned()
