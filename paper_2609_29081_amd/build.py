@@ -10,12 +10,12 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libaf.so")
 # The 2D stage is compiled once per variant (arithmetic type, tile height):
 # the FP64 stage with 16x7 tiles (the largest its LDS admits) and 16x5, the
-# mixed-precision stage (FP32 stencils) with 16x10, 16x7 and 16x14.  The
+# mixed-precision stage (FP32 stencils) with 16x14, 16x10 and 16x7.  The
 # first variant of each precision is the one single-instance stages use; the
 # batch autotuner chooses among all of a precision.  (entry name, type, TY)
 STAGE_VARIANTS = [("stage2d_fp64_t7", "double", 7), ("stage2d_fp64_t5", "double", 5),
-                  ("stage2d_mixed_t10", "float", 10), ("stage2d_mixed_t7", "float", 7),
-                  ("stage2d_mixed_t14", "float", 14)]
+                  ("stage2d_mixed_t14", "float", 14), ("stage2d_mixed_t10", "float", 10),
+                  ("stage2d_mixed_t7", "float", 7)]
 # (source, object, extra flags)
 SOURCES = [("af_capi.cpp", "af_capi.o", []),
            ("af_variants.cpp", "af_variants.o", ["--cuda-host-only"]),

@@ -42,7 +42,7 @@ namespace {
 
 // One object file holds one instance: its arithmetic type and tile height
 // are set when it is compiled (the FP64 stage with 16 x 7 tiles, the mixed
-// stage with 16 x 10 tiles, which its FP32 LDS arrays leave room for), and
+// stage with 16 x 14 tiles, which its FP32 LDS arrays leave room for), and
 // its entry point is afi::AF_STAGE_ENTRY.
 #ifndef AF_STAGE_REAL
 #define AF_STAGE_REAL double

@@ -22,8 +22,8 @@ AF_DECLARE_VARIANT(stage2d_mixed_t14)
 
 const StageVariant kStageVariants[] = {
     AF_VARIANT(stage2d_fp64_t7, 0, 7),    AF_VARIANT(stage2d_fp64_t5, 0, 5),
-    AF_VARIANT(stage2d_mixed_t10, 1, 10), AF_VARIANT(stage2d_mixed_t7, 1, 7),
-    AF_VARIANT(stage2d_mixed_t14, 1, 14)};
+    AF_VARIANT(stage2d_mixed_t14, 1, 14), AF_VARIANT(stage2d_mixed_t10, 1, 10),
+    AF_VARIANT(stage2d_mixed_t7, 1, 7)};
 const int kNumStageVariants = sizeof(kStageVariants) / sizeof(kStageVariants[0]);
 
 const StageVariant* default_variant(int mixed) {
