@@ -282,6 +282,7 @@ def main() -> int:
                           "stage_us": round(stage_s_m * 1e6, 1),
                           "hbm_alg_GBs": round(alg["stage2d"] / stage_s_m / 1e9, 1),
                           "l1_rel_vs_fp64": float(np.abs(b_ - a_).sum() / np.abs(a_).sum()),
+                          "linf_rel_vs_fp64": float(np.abs(b_ - a_).max() / np.abs(a_).max()),
                           "l1_rel_vs_fp64_steps": f"10 steps of dt = CFL dt / 8 from t = 0"}
         mfile = os.path.join(ROOT, "profiles", "traffic_mixed.json")
         if os.path.exists(mfile):
