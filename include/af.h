@@ -237,7 +237,6 @@ enum {
 af_status af_timing(af_ctx* ctx, int enable);
 af_status af_timing_read(af_ctx* ctx, long* launches, double* ms);
 
-/* Message of the last error raised on the calling thread ("" if none). */
 /* ---- batches: many independent 2D instances advanced together ----
  *
  * A batch groups n contexts (2D, one precision; each with its own grid, gas,
@@ -357,6 +356,7 @@ af_status af_mlp_train(const float* X, const float* y, long n, float* params, fl
                        float* m, float* v, long step0, int steps, int batch, float lr,
                        float* loss_out, void* gws, void* stream);
 
+/* Message of the last error raised on the calling thread ("" if none). */
 const char* af_last_error(void);
 
 #ifdef __cplusplus

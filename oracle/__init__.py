@@ -64,6 +64,8 @@ def lib():
         L.orc_rhs.restype = None
         L.orc_dt.argtypes = [cp, dp]
         L.orc_dt.restype = C.c_double
+        L.orc_dt_pp.argtypes = [cp, dp]
+        L.orc_dt_pp.restype = C.c_double
         L.orc_step.argtypes = [cp, dp, C.c_double, C.c_double, C.c_double, dp,
                                C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.orc_step.restype = C.c_int
@@ -215,6 +217,14 @@ def rhs(cfg: Cfg, U: np.ndarray) -> np.ndarray:
 def dt(cfg: Cfg, U: np.ndarray) -> float:
     U = np.ascontiguousarray(U, dtype=np.float64)
     return lib().orc_dt(C.byref(cfg), _p(U))
+
+
+def dt_pp(cfg: Cfg, U: np.ndarray) -> float:
+    """the positivity theorem's sufficient time step (end of Sec. 3.4): the
+    LLF intermediate-state bound for the cell averages and for the low-order
+    point scheme"""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    return lib().orc_dt_pp(C.byref(cfg), _p(U))
 
 
 def step(cfg: Cfg, U: np.ndarray, dt: float = 0.0, t: float = 0.0, t_final: float = 1e30):

@@ -1441,6 +1441,145 @@ double orc_dt(const orc_cfg* c, const double* U) {
   return 1.0 / (a + v);
 }
 
+/* Time-step bound of the positivity theorem at the end of Sec. 3.4.  The
+ * theorem asks dt to satisfy the sufficient condition of the
+ * proposition on the intermediate states of the LLF scheme (Sec. 3.1),
+ * dt <= dx_l / (2 d max lambda_l), both for the cell averages and for the
+ * low-order point scheme, whose lattice has spacing dx_l / 2.  lambda of a
+ * face or lattice link is max varrho_l + max b_l over its two ends (eq. of
+ * the low face fluxes); here it is bounded above by the largest varrho_l
+ * plus the largest b_l over all ends in direction l, so the bound returned
+ * is sufficient for every face and link.  Only the low-order schemes that a
+ * limiter switch uses count: the cell one under ORC_LIM_PP, the point one
+ * under ORC_LIM_POINT (neither: +infinity).
+ *   cell ends: the cells on either side of every face, ghost cells being
+ *     boundary images; S by central differences of Z(average) (R-S);
+ *   point ends: every site a point DOF links to in direction l (points,
+ *     cell averages at centres, ghost images), with the gradients of R-point.
+ */
+static double dt_bound(double h, int dim, double a, double b) {
+  double lam = a + b;
+  return lam > 0.0 ? h / (2.0 * dim * lam) : HUGE_VAL;
+}
+
+static double dt_pp1(const orc_cfg* c, const double* U) {
+  lat1 Ls, *L = &Ls;
+  int n = c->n1;
+  L->c = c;
+  L->n = n;
+  L->np = (c->bc[0] == ORC_PERIODIC) ? n : n + 1;
+  L->LX = 2 * n + 1 + 2 * GM;
+  L->dx = (c->x1 - c->x0) / n;
+  L->avg = U;
+  L->pts = U + 3 * n;
+  L->LU = calloc(3 * L->LX, sizeof(double));
+  L->LW = calloc(3 * L->LX, sizeof(double));
+  L->LZ = calloc(3 * L->LX, sizeof(double));
+  L->GZ = calloc(3 * L->LX, sizeof(double));
+  L->CA = calloc(3 * (n + 4), sizeof(double));
+  build1(L);
+  double dt = HUGE_VAL;
+  if (c->limiter & ORC_LIM_PP) {
+    double a = 0.0, b = 0.0;
+    for (int i = -1; i <= n; ++i) {
+      double Ub[4], W[4], Wm[4], Wp[4], Z[4], Zm[4], Zp[4], Um[4], Up[4], S[4];
+      for (int k = 0; k < 3; ++k) {
+        Ub[k] = C1(k, i);
+        Um[k] = C1(k, i - 1);
+        Up[k] = C1(k, i + 1);
+      }
+      prim(c, Ub, W);
+      prim(c, Um, Wm);
+      prim(c, Up, Wp);
+      zvar(c, W, Z);
+      zvar(c, Wm, Zm);
+      zvar(c, Wp, Zp);
+      for (int k = 0; k < 3; ++k) S[k] = (Zp[k] - Zm[k]) / (2.0 * L->dx);
+      a = dmax(a, rho_spec(c, 0, W));
+      b = dmax(b, orc_bvisc(c, 0, Ub, S));
+    }
+    dt = dmin(dt, dt_bound(L->dx, 1, a, b));
+  }
+  if (c->limiter & ORC_LIM_POINT) {
+    double a = 0.0, b = 0.0;
+    for (int X = -1; X <= 2 * n + 1; ++X) {
+      double Us[4], W[4], S[4];
+      lo_site1(L, X, Us);
+      prim(c, Us, W);
+      lo_grad1(L, X, S);
+      a = dmax(a, rho_spec(c, 0, W));
+      b = dmax(b, orc_bvisc(c, 0, Us, S));
+    }
+    dt = dmin(dt, dt_bound(0.5 * L->dx, 1, a, b));
+  }
+  free(L->LU);
+  free(L->LW);
+  free(L->LZ);
+  free(L->GZ);
+  free(L->CA);
+  return dt;
+}
+
+static double dt_pp2(const orc_cfg* c, const double* U) {
+  lat2 Ls, *L = &Ls;
+  setup2(L, c, U);
+  int n1 = L->n1, n2 = L->n2;
+  double h[2] = {L->dx, L->dy};
+  double dt = HUGE_VAL;
+  if (c->limiter & ORC_LIM_PP) {
+    for (int d = 0; d < 2; ++d) {
+      /* cells beside the faces normal to d: one ghost layer along d */
+      int ilo = d == 0 ? -1 : 0, ihi = d == 0 ? n1 : n1 - 1;
+      int jlo = d == 1 ? -1 : 0, jhi = d == 1 ? n2 : n2 - 1;
+      double a = 0.0, b = 0.0;
+      for (int j = jlo; j <= jhi; ++j)
+        for (int i = ilo; i <= ihi; ++i) {
+          double Ub[4], W[4], S[8], Zn[4][4];
+          const int ni[4] = {i - 1, i + 1, i, i}, nj[4] = {j, j, j - 1, j + 1};
+          for (int m = 0; m < 4; ++m) {
+            double Un[4], Wn[4];
+            for (int k = 0; k < 4; ++k) Un[k] = C2(k, ni[m], nj[m]);
+            prim(c, Un, Wn);
+            zvar(c, Wn, Zn[m]);
+          }
+          for (int k = 0; k < 4; ++k) {
+            Ub[k] = C2(k, i, j);
+            S[k] = (Zn[1][k] - Zn[0][k]) / (2.0 * L->dx);
+            S[4 + k] = (Zn[3][k] - Zn[2][k]) / (2.0 * L->dy);
+          }
+          prim(c, Ub, W);
+          a = dmax(a, rho_spec(c, d, W));
+          b = dmax(b, orc_bvisc(c, d, Ub, S));
+        }
+      dt = dmin(dt, dt_bound(h[d], 2, a, b));
+    }
+  }
+  if (c->limiter & ORC_LIM_POINT) {
+    for (int d = 0; d < 2; ++d) {
+      /* ends of the links along d of every point: one ghost line along d */
+      int Xlo = d == 0 ? -1 : 0, Xhi = d == 0 ? 2 * n1 + 1 : 2 * n1;
+      int Ylo = d == 1 ? -1 : 0, Yhi = d == 1 ? 2 * n2 + 1 : 2 * n2;
+      double a = 0.0, b = 0.0;
+      for (int Y = Ylo; Y <= Yhi; ++Y)
+        for (int X = Xlo; X <= Xhi; ++X) {
+          double Us[4], W[4], S[8];
+          lo_site2(L, X, Y, Us);
+          prim(c, Us, W);
+          lo_grad2(L, X, Y, S);
+          a = dmax(a, rho_spec(c, d, W));
+          b = dmax(b, orc_bvisc(c, d, Us, S));
+        }
+      dt = dmin(dt, dt_bound(0.5 * h[d], 2, a, b));
+    }
+  }
+  free2(L);
+  return dt;
+}
+
+double orc_dt_pp(const orc_cfg* c, const double* U) {
+  return c->dim == 1 ? dt_pp1(c, U) : dt_pp2(c, U);
+}
+
 /* SSP-RK54 (Sec. 2.3 names the five-stage, fourth-order SSP Runge-Kutta
  * method; coefficients of Spiteri and Ruuth's SSPRK(5,4) in Shu-Osher form).
  * In forward-Euler steps E_k = FE(u_k, c_k dt):

@@ -97,6 +97,12 @@ void orc_rhs(const orc_cfg* c, const double* U, double* dUdt);
 /* CFL time step over cell averages */
 double orc_dt(const orc_cfg* c, const double* U);
 
+/* the positivity theorem's sufficient time step (end of Sec. 3.4): the
+ * intermediate-state bound of the low-order LLF scheme (Sec. 3.1) for the cell
+ * averages (under ORC_LIM_PP) and for the low-order point scheme on the half
+ * lattice (under ORC_LIM_POINT); +infinity if neither switch is set */
+double orc_dt_pp(const orc_cfg* c, const double* U);
+
 /* one step with the halving retry, by SSP-RK3 or (c->rk == 54) the
  * five-stage fourth-order SSP method Sec. 2.3 names.  dt<=0 -> CFL dt.  dt is
  * clipped to t_final - t.  Returns 0 on success, nonzero if max_halvings

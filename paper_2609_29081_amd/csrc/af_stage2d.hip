@@ -664,6 +664,8 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
   __syncthreads();  // the previous tile is done with the LDS; stop is visible
   if (stop) {
     if constexpr (BATCH) {
+      // every wave has read `stop` before thread 0 writes it for the next tile
+      __syncthreads();
       const int nt = it.advance();
       if (nt >= 0) {
         const TileArgs An = args(nt);
