@@ -190,6 +190,22 @@ af_status af_cfl_dt(af_ctx* ctx, const double* U, double t, double t_final, doub
 af_status af_step(af_ctx* ctx, double* U, void* ws, void* stream, double dt, double t,
                   double t_final, double* dt_used, int* halvings);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): af_step with its
+ * workspace taken from a fixed array inside the library instead of a caller
+ * buffer.  The array holds AF_NOALLOC_SCRATCH_BYTES bytes on every GPU the
+ * library runs on, for the life of the process.  A grid whose
+ * af_workspace_bytes exceeds it is rejected with AF_E_ARG before any device
+ * work (the FP64 2D workspace is about 512 bytes per cell: up to about
+ * 32,000 cells, e.g. 256 x 128).  All calls on one GPU share its array, and
+ * each call leaves its contents behind: calls that overlap on one GPU
+ * (from several host threads or on several streams) race, so the caller
+ * serialises them.  Arguments, synchronisation, halving and results are as
+ * in af_step; the call allocates nothing. */
+#define AF_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+af_status af_step_noalloc(af_ctx* ctx, double* U, void* stream, double dt, double t,
+                          double t_final, double* dt_used, int* halvings);
+
 /* Steps with a source term (manufactured solutions: the paper's Taylor-Green
  * test, Sec. 4, adds an energy source).  af_stage_times writes the times of
  * the stage inputs of integrator rk (3 or 54) as fractions of dt into c

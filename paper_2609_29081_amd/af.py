@@ -51,7 +51,7 @@ EXPORTS = ["af_default_params", "af_init_grid", "af_destroy", "af_set_bc", "af_s
            "af_batch_set_variant", "af_batch_tune", "af_face_count", "af_mlp_param_count",
            "af_blend_features", "af_set_blend_net", "af_blend_infer", "af_rk_stage_blend",
            "af_mlp_grad_workspace_bytes", "af_mlp_grad", "af_mlp_adam", "af_mlp_train",
-           "af_stage_times", "af_step_source"]
+           "af_stage_times", "af_step_source", "af_step_noalloc"]
 
 # kernel kinds reported by af_timing_read
 KERNEL_KINDS = {0: "lattice", 1: "grad", 2: "cellpre", 3: "face", 4: "cells", 5: "points",
@@ -118,6 +118,8 @@ def lib():
         L.af_cfl_dt.argtypes = [vp, vp, C.c_double, C.c_double, vp, vp, vp]
         L.af_step.argtypes = [vp, vp, vp, vp, C.c_double, C.c_double, C.c_double, dp,
                               C.POINTER(C.c_int)]
+        L.af_step_noalloc.argtypes = [vp, vp, vp, C.c_double, C.c_double, C.c_double, dp,
+                                      C.POINTER(C.c_int)]
         L.af_run.argtypes = [vp, vp, vp, vp, C.c_double, C.c_double, C.c_long, ip,
                              C.POINTER(C.c_long), dp]
         L.af_read_flags.argtypes = [vp, vp, C.POINTER(C.c_int), vp]
@@ -126,7 +128,7 @@ def lib():
         L.af_timing_read.argtypes = [vp, C.POINTER(C.c_long), dp]
         L.af_last_error.restype = C.c_char_p
         for name in ("af_default_params", "af_init_grid", "af_set_bc", "af_rk_stage", "af_cfl_dt",
-                     "af_step", "af_run", "af_read_flags", "af_reset_flags", "af_timing",
+                     "af_step", "af_step_noalloc", "af_run", "af_read_flags", "af_reset_flags", "af_timing",
                      "af_timing_read"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -211,6 +213,18 @@ class Solver:
         h = C.c_int()
         st = lib().af_step(self.ctx, _ptr(U), _ptr(self.ws), _stream(stream), dt, t, t_final,
                            C.byref(dtu), C.byref(h))
+        if st in (AF_E_ARG, AF_E_HIP):
+            _check(st)
+        return st, dtu.value, h.value
+
+    def af_step_noalloc(self, U, dt: float = 0.0, t: float = 0.0, t_final: float = 1e300,
+                        stream=None):
+        """af_step on the library's own scratch array instead of this
+        solver's workspace; returns (status, dt_used, halvings)"""
+        dtu = C.c_double()
+        h = C.c_int()
+        st = lib().af_step_noalloc(self.ctx, _ptr(U), _stream(stream), dt, t, t_final,
+                                   C.byref(dtu), C.byref(h))
         if st in (AF_E_ARG, AF_E_HIP):
             _check(st)
         return st, dtu.value, h.value

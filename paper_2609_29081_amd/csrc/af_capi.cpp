@@ -11,6 +11,7 @@
 
 #include <string.h>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -18,6 +19,12 @@
 
 #include "af_device.hpp"
 #include "af_internal.hpp"
+
+// workspace of af_step_noalloc: one copy per GPU, resident for the life of
+// the process.  Host code never uses this name as an address (on the host it
+// is only a stand-in for the device symbol): the device address comes from
+// hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[AF_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -284,7 +291,27 @@ af_status read_flags(const afi::Work& w, hipStream_t s, unsigned* out) {
   return AF_OK;
 }
 
-// three stages with a host-given dt; cur -> out through S1, S2
+// device address of the scratch array on the current device, looked up once
+// per device (each GPU holds its own copy at its own address)
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+af_status scratch_on_current_device(void** out) {
+  int dev = 0;
+  AF_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(AF_E_ARG, "device %d: too many devices", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    AF_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(AF_E_HIP, "hipGetSymbolAddress: NULL address of the scratch array");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return AF_OK;
+}
+
 // three stages with a host-given dt; cur -> out through S1, S2.  src, if not
 // NULL, holds a source term at each stage input's time (host dt only): each
 // forward Euler step then adds tau S_k after its limited update
@@ -611,6 +638,23 @@ af_status af_step(af_ctx* c, double* U, void* ws, void* stream, double dt, doubl
     return fail(AF_E_PP, "low-order states inadmissible after %d halvings (flags %u)", h - 1, fl);
   }
   return AF_OK;
+}
+
+af_status af_step_noalloc(af_ctx* c, double* U, void* stream, double dt, double t,
+                          double t_final, double* dt_used, int* halvings) {
+  if (!c || !U) return fail(AF_E_ARG, "af_step_noalloc: NULL argument");
+  afi::Geo g;
+  if (!geometry(c, &g)) return AF_E_ARG;
+  const size_t need = afi::workspace_layout(g, nullptr, nullptr);
+  if (need > (size_t)AF_NOALLOC_SCRATCH_BYTES)
+    return fail(AF_E_ARG,
+                "af_step_noalloc: this grid needs %zu workspace bytes, more than the %zu of "
+                "the library's scratch array",
+                need, (size_t)AF_NOALLOC_SCRATCH_BYTES);
+  void* ws = nullptr;
+  const af_status st = scratch_on_current_device(&ws);
+  if (st != AF_OK) return st;
+  return af_step(c, U, ws, stream, dt, t, t_final, dt_used, halvings);
 }
 
 af_status af_run(af_ctx* c, double* U, void* ws, void* stream, double t0, double t_final,
