@@ -25,6 +25,12 @@ METRIC = "cell-DOF updates/s per RK stage, 2D viscous shock tube; % peak HBM BW;
 HBM_PEAK_GBS = 8000.0
 FP64_VALU_PEAK_TFLOPS = 78.6
 VALU_SIMDS = 1024      # 256 compute units x 4 SIMDs
+# the method's FP64 operations per cell and RK stage in 2D, counted once per
+# lattice site from the operators' formulas (primitives, centres, gradients,
+# point residual with D^2 and mixed terms, face fluxes, low-order fluxes,
+# blends, point low-order update, RK combination): a range, see the design
+# notes
+ALG_FLOPS_PER_CELL_STAGE = (2600.0, 3300.0)
 CLOCK_HZ = 2.4e9
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = ["paper_2609_29081_amd/csrc/af_stage2d.hip", "paper_2609_29081_amd/csrc/af_device.hpp",
@@ -76,8 +82,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n1", type=int, default=1000)
     ap.add_argument("--n2", type=int, default=500)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="budget of the CPU-oracle baseline sample (0 disables it)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="budget of the all-thread CPU-oracle sample (0 disables the baseline)")
+    ap.add_argument("--cpu-seconds-1t", type=float, default=10.0,
+                    help="budget of the single-thread CPU-oracle sample (one step at least)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision form")
     ap.add_argument("--roofline-reps", type=int, default=10,
@@ -88,6 +96,18 @@ def main() -> int:
                     help="instances of the batched shock-tube sweep")
     ap.add_argument("--batch-steps", type=int, default=100,
                     help="accepted steps per instance of the batched sweep")
+    ap.add_argument("--no-vortex", action="store_true",
+                    help="skip the smooth vortex-wave form (256^2 to 2048^2)")
+    ap.add_argument("--vortex-steps", type=int, default=100,
+                    help="RK3 steps of each vortex-wave run")
+    ap.add_argument("--vortex-sizes", default="256,512,1024,2048",
+                    help="vortex-wave grid sizes")
+    ap.add_argument("--whole-run", default="",
+                    help="also run the 1000 x 500 tube to t = 1 in the listed precisions "
+                         "(fp64,mixed; off by default: minutes) and write a summary to "
+                         "--whole-run-out")
+    ap.add_argument("--whole-run-out", default="",
+                    help="markdown file for the whole-run summary")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-blend form")
     ap.add_argument("--learned-train-steps", type=int, default=20000,
@@ -193,58 +213,43 @@ def main() -> int:
             traffic = tr.get("bytes_per_launch")
             flops = tr.get("fp64_flops_per_launch")
             valu = tr.get("instructions_per_launch", {}).get("SQ_INSTS_VALU")
-    hbm = {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(achieved / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": alg[dom]}
+    # the roof: algorithmic HBM bytes of the dominant kernel per launch (each
+    # input read once, each output written once) over its mean launch time.
+    # Beside it, the method's algorithmic FP64 flops per cell-stage (the
+    # operator-count estimate of the design notes, a range) against the FP64
+    # vector peak, and, while the counter file matches the kernel sources, the
+    # executed FP64 flops and VALU issue rate from the counters (which include
+    # the halo recomputation of the tiles).
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "alg_bytes_per_launch": alg[dom],
+                "avg_launch_us": round(dom_avg_s * 1e6, 3), "timed_window": window}
+    if dom == "stage2d":
+        ncell = g.n1 * g.n2
+        lo, hi = (ALG_FLOPS_PER_CELL_STAGE[0] * ncell / dom_avg_s / 1e12,
+                  ALG_FLOPS_PER_CELL_STAGE[1] * ncell / dom_avg_s / 1e12)
+        roofline["fp64_algorithmic"] = {
+            "flops_per_cell_stage": list(ALG_FLOPS_PER_CELL_STAGE),
+            "achieved_TFLOPs": [round(lo, 2), round(hi, 2)], "peak": FP64_VALU_PEAK_TFLOPS,
+            "frac": [round(lo / FP64_VALU_PEAK_TFLOPS, 4), round(hi / FP64_VALU_PEAK_TFLOPS, 4)]}
     if flops:
-        # the stage executes ~20 FP64 flops per algorithmic byte, twice the
-        # FP64 ridge: the FP64 VALU is the binding roof
         tf = flops / dom_avg_s / 1e12
-        roofline = {"bound": "alu", "kernel": dom, "achieved": round(tf, 2),
-                    "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(tf / FP64_VALU_PEAK_TFLOPS, 4), "traffic": traffic,
-                    "flops_per_launch": flops,
-                    "flops_kind": "executed FP64 flops (rocprofv3 counters, 64 lanes per wave "
-                                  "instruction), an upper bound on the algorithmic count",
-                    "avg_launch_us": round(dom_avg_s * 1e6, 3), "hbm": hbm,
-                    "timed_window": window}
+        ex = {"fp64_flops_per_launch": flops, "TFLOPs": round(tf, 2),
+              "frac_of_fp64_peak": round(tf / FP64_VALU_PEAK_TFLOPS, 4),
+              "what": "executed FP64 flops (rocprofv3 counters, 64 lanes per wave instruction, "
+                      "2 per FMA), halo recomputation included"}
         if valu:
-            # issue rate of all VALU wave instructions (a wave64 instruction
-            # occupies its SIMD for four cycles; 1024 SIMDs at 2.4 GHz)
-            roofline["valu_issue"] = {
-                "wave_instructions_per_launch": valu,
-                "frac": round(valu * 4.0 / (VALU_SIMDS * CLOCK_HZ * dom_avg_s), 4),
-                "what": "all VALU wave instructions (counters) x 4 cycles / (SIMDs x clock x "
-                        "launch time)"}
-    else:
-        roofline = dict({"bound": "hbm", "kernel": dom, "traffic": traffic,
-                         "avg_launch_us": round(dom_avg_s * 1e6, 3), "timed_window": window},
-                        **hbm)
+            # a wave64 VALU instruction occupies its SIMD for four cycles
+            ex["valu_issue_frac"] = round(valu * 4.0 / (VALU_SIMDS * CLOCK_HZ * dom_avg_s), 4)
+            ex["valu_wave_instructions_per_launch"] = valu
+        roofline["executed"] = ex
 
     # CPU baseline: the FP64 oracle on the host cores, first steps of the same
     # workload, and the L1 difference of the GPU after the same steps
     cpu = None
     l1 = None
     if args.cpu_seconds > 0:
-        import oracle as O
-        cfg = O.make_cfg(g, **{k: v for k, v in kw.items()})
-        Uc = U0.copy()
-        n_cpu, t_cpu, t_sim = 0, 0.0, 0.0
-        while t_cpu < args.cpu_seconds and n_cpu < 50:
-            c0 = time.perf_counter()
-            stc, dtu, h, fl = O.step(cfg, Uc, 0.0, t_sim)
-            t_cpu += time.perf_counter() - c0
-            t_sim += dtu
-            n_cpu += 1
-        cpu = {"value": dof_sites * 3 * n_cpu / t_cpu, "unit": "DOF-updates/s",
-               "cores": O.threads(), "kind": "oracle",
-               "sample": f"first {n_cpu} RK3 steps of the {g.n1}x{g.n2} shock tube from t=0 "
-                         f"(whole grid, {t_cpu:.1f} s)"}
-        Ug = dev_U0.clone()
-        st, ns2, _ = S.af_run(Ug, 0.0, 1e30, n_cpu, check_every=1)
-        Pg, Pc = g.split(Ug.cpu().numpy()), g.split(Uc)
-        l1 = float(np.abs(Pg["avg"][0] - Pc["avg"][0]).sum() * g.dx * g.dy)
-        linf = max(float(np.abs(Pg[n][k] - Pc[n][k]).max() / np.abs(Pc[n][k]).max())
-                   for n in Pg for k in range(4))
+        cpu, l1, linf = cpu_baseline(args, g, kw, U0, S, dev_U0, K, dof_sites)
     # the mixed-precision form (FP32 stencils, FP64 blends and updates): the
     # same K steps from t = 0, timed the same way, and its difference from
     # the FP64 form over fixed-dt steps (no halving, equal times)
@@ -295,6 +300,8 @@ def main() -> int:
                     "traffic": trm["bytes_per_launch"],
                     "executed_TFLOPs": {"fp32": round(f32 / stage_s_m / 1e12, 2),
                                         "fp64": round(f64 / stage_s_m / 1e12, 2)}})
+    if not args.no_vortex:
+        forms["vortex_wave"] = vortex_form(args, stream)
     if not args.no_batched:
         forms["batched"] = batched_form(args, stream)
     if not args.no_learned:
@@ -322,8 +329,200 @@ def main() -> int:
         "linf_rel_vs_oracle": linf if cpu else None,
         "wall_s": wall,
     }
+    if args.whole_run:
+        out["whole_run"] = whole_run(args, g, U0, kw)
     print(json.dumps(out))
     return 0
+
+
+def vortex_form(args, stream) -> dict:
+    """The smooth density/vortex wave (periodic [0,1]^2, mu = 1e-3,
+    Pr = 0.72, all limiters) on n^2 grids, FP64 and mixed precision: K RK3
+    steps from t = 0 timed with HIP events (value = DOF sites x 3 x K /
+    second), and the stage kernel's mean launch time over complete stage
+    launches with its algorithmic HBM bytes (8/3 states per launch) as a
+    fraction of the HBM peak.  From 1024^2 on, three states no longer fit in
+    the 256 MB last-level cache."""
+    import torch
+
+    from paper_2609_29081_amd import af
+    from paper_2609_29081_amd import workloads as W
+    from paper_2609_29081_amd.prof_counters import stage_sequence
+
+    out = {"workload": f"2D vortex wave (periodic, mu=1e-3, Pr=0.72), {args.vortex_steps} "
+                       "RK3 steps from t=0 per run"}
+    for n in [int(v) for v in args.vortex_sizes.split(",") if v]:
+        print(f"bench: vortex wave {n}^2", file=sys.stderr, flush=True)
+        g, f = W.vortex_wave_2d(n)
+        U0 = W.make_state(g, f, 1.4)
+        rec = {}
+        for prec, pname in ((af.PREC_FP64, "fp64"), (af.PREC_MIXED, "mixed")):
+            S = af.Solver(g, mu=1e-3, Pr=0.72, cfl_c=0.2, cfl_v=0.05, precision=prec)
+            d0 = S.to_device(U0)
+            U = d0.clone()
+            S.af_run(U, 0.0, 1e30, 2, check_every=1)
+            U.copy_(d0)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            st, ns, _ = S.af_run(U, 0.0, 1e30, args.vortex_steps, check_every=1)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if st != af.AF_OK or ns != args.vortex_steps:
+                raise RuntimeError(f"vortex {n} {pname}: status {st}, {ns} steps")
+            ms = e0.elapsed_time(e1)
+            S.af_timing(True)
+            S.af_timing_read()
+            stage_sequence(S, d0, 5)
+            kt = S.af_timing_read()
+            S.af_timing(False)
+            st_s = kt["stage2d"][1] / kt["stage2d"][0] * 1e-3
+            alg = 8.0 * g.state_len * 8.0 / 3.0
+            gbs = alg / st_s / 1e9
+            rec[pname] = {"value": g.dof_sites * 3 * args.vortex_steps / (ms / 1e3),
+                          "ms_per_step": round(ms / args.vortex_steps, 4),
+                          "stage_us": round(st_s * 1e6, 1),
+                          "hbm_alg_GBs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+            del S, U, d0
+        out[f"{n}x{n}"] = rec
+    return out
+
+
+def whole_run(args, g, U0, kw) -> dict:
+    """The 1000 x 500 tube from t = 0 to t = 1 (the configuration's end
+    time), once per listed precision: steps, RK3 attempts per step (stage
+    launches / 3), GPU time (HIP events around each chunk of af_run), DOF
+    updates per second over the whole run, the admissibility count at the
+    end, and the density along the bottom wall (y = 0) at t = 1."""
+    import numpy as np
+    import torch
+
+    from paper_2609_29081_amd import af
+
+    res = {}
+    lines = []
+    for pname in [v for v in args.whole_run.split(",") if v]:
+        prec = af.PREC_MIXED if pname == "mixed" else af.PREC_FP64
+        S = af.Solver(g, precision=prec, **kw)
+        U = S.to_device(U0)
+        stream = torch.cuda.current_stream()
+        t, steps, launches, gpu_ms = 0.0, 0, 0, 0.0
+        S.af_timing(True)
+        w0 = time.perf_counter()
+        last = w0
+        status = af.AF_OK
+        while t < 1.0:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            status, ns, t = S.af_run(U, t, 1.0, 2000, check_every=1)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            gpu_ms += e0.elapsed_time(e1)
+            steps += ns
+            launches += S.af_timing_read().get("stage2d", (0, 0.0))[0]
+            if status != af.AF_OK or ns == 0:
+                break
+            if time.perf_counter() - last > 20:
+                last = time.perf_counter()
+                print(f"bench: whole run {pname}: step {steps} t {t:.4f} "
+                      f"{last - w0:.0f} s", file=sys.stderr, flush=True)
+        S.af_timing(False)
+        wall = time.perf_counter() - w0
+        bad = S.af_check_admissible(U)
+        P = g.split(U.cpu().numpy())
+        rho_wall = np.empty(2 * g.n1 + 1)
+        rho_wall[0::2] = P["co"][0, 0, :]
+        rho_wall[1::2] = P["ye"][0, 0, :]
+        r = {"status": int(status), "t_end": t, "steps": steps,
+             "rk3_attempts_per_step": round(launches / 3.0 / max(steps, 1), 3),
+             "gpu_s": round(gpu_ms / 1e3, 2), "wall_s": round(wall, 1),
+             "value": g.dof_sites * 3 * steps / (gpu_ms / 1e3), "unit": "DOF-updates/s",
+             "inadmissible_dofs_at_end": int(bad),
+             "wall_density_min_max": [float(rho_wall.min()), float(rho_wall.max())],
+             "mass_rel_change": float(P["avg"][0].sum() / g.split(U0)["avg"][0].sum() - 1.0)}
+        res[pname] = r
+        lines.append(f"| {pname} | {r['status']} | {t:.6f} | {steps} | "
+                     f"{r['rk3_attempts_per_step']} | {r['gpu_s']} | {r['wall_s']} | "
+                     f"{r['value']:.3e} | {bad} | {r['mass_rel_change']:.2e} |")
+        del S, U
+    if args.whole_run_out:
+        with open(args.whole_run_out, "w") as fh:
+            fh.write("# The 2D viscous shock tube 1000x500 (Re = 200) from t = 0 to t = 1\n\n")
+            argv = " ".join(a if a != args.whole_run_out else "<file>" for a in sys.argv[1:])
+            fh.write(f"Command: `python bench.py {argv}`\n\n")
+            fh.write("| precision | status | t reached | steps | RK3 attempts per step | GPU s "
+                     "| wall s | DOF-updates/s | inadmissible DOFs at end | mass change |\n")
+            fh.write("|---|---|---|---|---|---|---|---|---|---|\n")
+            fh.write("\n".join(lines) + "\n")
+    return res
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(args, g, kw, U0, S, dev_U0, K, dof_sites):
+    """The FP64 oracle on the host: on all its threads over the first steps
+    of the timed window (all K of them when they fit in --cpu-seconds), and
+    on one thread over as many of those steps as fit in --cpu-seconds-1t
+    (at least one).  Returns the record, and the L1 / relative L-inf
+    difference of the GPU state after the same all-thread steps."""
+    import numpy as np
+
+    import oracle as O
+    cfg = O.make_cfg(g, **{k: v for k, v in kw.items()})
+    nthreads = O.threads()
+
+    def sample(budget, max_steps):
+        Uc = U0.copy()
+        n, spent, t_sim = 0, 0.0, 0.0
+        while n < max_steps and (n == 0 or spent < budget):
+            c0 = time.perf_counter()
+            _, dtu, _, _ = O.step(cfg, Uc, 0.0, t_sim)
+            spent += time.perf_counter() - c0
+            t_sim += dtu
+            n += 1
+        return Uc, n, spent
+
+    print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
+    Uc, n_all, t_all = sample(args.cpu_seconds, K)
+    O.set_threads(1)
+    try:
+        _, n_one, t_one = sample(args.cpu_seconds_1t, K)
+    finally:
+        O.set_threads(nthreads)
+    # the GPU over the same steps, for the comparison and its rate there
+    import torch
+    Ug = dev_U0.clone()
+    torch.cuda.synchronize()
+    g0 = time.perf_counter()
+    st, ns2, _ = S.af_run(Ug, 0.0, 1e30, n_all, check_every=1)
+    torch.cuda.synchronize()
+    g_s = time.perf_counter() - g0
+    Pg, Pc = g.split(Ug.cpu().numpy()), g.split(Uc)
+    l1 = float(np.abs(Pg["avg"][0] - Pc["avg"][0]).sum() * g.dx * g.dy)
+    linf = max(float(np.abs(Pg[n][k] - Pc[n][k]).max() / np.abs(Pc[n][k]).max())
+               for n in Pg for k in range(4))
+    cpu = {"value": dof_sites * 3 * n_all / t_all, "unit": "DOF-updates/s",
+           "cores": nthreads, "kind": "oracle",
+           "sample": f"steps 1-{n_all} of the timed window ({g.n1}x{g.n2} shock tube from t=0, "
+                     f"whole grid) on {nthreads} threads, {t_all:.1f} s",
+           "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+           "single_thread": {"value": dof_sites * 3 * n_one / t_one, "unit": "DOF-updates/s",
+                             "sample": f"steps 1-{n_one} on one thread, {t_one:.1f} s"},
+           "gpu_same_steps_wall": {"value": dof_sites * 3 * n_all / g_s,
+                                   "what": f"the GPU over the same {n_all} steps, host wall "
+                                           "clock around af_run"}}
+    return cpu, l1, linf
 
 
 def learned_form(args, stream) -> dict:

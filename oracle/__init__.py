@@ -86,6 +86,8 @@ def lib():
         L.orc_op_d2.argtypes = [dp, dp, C.c_double]
         L.orc_op_d2.restype = C.c_double
         L.orc_threads.restype = C.c_int
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -289,3 +291,8 @@ def op_d2(k, z, dx: float) -> float:
 
 def threads() -> int:
     return lib().orc_threads()
+
+
+def set_threads(n: int) -> None:
+    """threads of the oracle's OpenMP loops from now on"""
+    lib().orc_set_threads(int(n))

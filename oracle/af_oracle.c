@@ -71,6 +71,14 @@ int orc_threads(void) {
 #endif
 }
 
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* finite-difference operators on one lattice line, offsets -2..2 -> z[0..4] */
 /* (Sec. 2.1: biased D+, D-, central D_c, compact D^2)                       */

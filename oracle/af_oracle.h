@@ -126,6 +126,8 @@ double orc_op_dminus(const double* z, double dx);
 double orc_op_dc(const double* z, double dx);
 double orc_op_d2(const double* k, const double* z, double dx);
 int orc_threads(void);
+/* threads of the OpenMP loops of later calls (n >= 1) */
+void orc_set_threads(int n);
 
 #ifdef __cplusplus
 }

@@ -51,16 +51,28 @@ def stage_sequence(S, U0, reps: int) -> None:
         S.af_rk_stage(2, U0, U2, U1, dt_dev=dt_dev)
 
 
-def target(reps: int = 3, mixed: bool = False) -> None:
+def workload(name: str, n1: int, n2: int):
+    """(grid, initial data, physics keywords) of a profiled workload: the
+    viscous shock tube (Re = 200) or the smooth vortex wave (n1 x n1)"""
+    from paper_2609_29081_amd import workloads as W
+    if name == "vortex":
+        g, f = W.vortex_wave_2d(n1)
+        return g, f, dict(mu=1e-3, Pr=0.72)
+    g, f = W.shock_tube_2d(n1, n2)
+    return g, f, dict(mu=0.005, Pr=0.73)
+
+
+def target(reps: int = 3, mixed: bool = False, wl: str = "tube", n1: int = N1,
+           n2: int = N2) -> None:
     sys.path.insert(0, ROOT)
     import torch
 
     from paper_2609_29081_amd import af
     from paper_2609_29081_amd import workloads as W
 
-    g, f = W.shock_tube_2d(N1, N2)
-    S = af.Solver(g, mu=0.005, Pr=0.73, cfl_c=0.2, cfl_v=0.05,
-                  precision=af.PREC_MIXED if mixed else af.PREC_FP64)
+    g, f, phys = workload(wl, n1, n2)
+    S = af.Solver(g, cfl_c=0.2, cfl_v=0.05, precision=af.PREC_MIXED if mixed else af.PREC_FP64,
+                  **phys)
     U0 = S.to_device(W.make_state(g, f, 1.4))
     stage_sequence(S, U0, reps)
     torch.cuda.synchronize()
@@ -122,12 +134,18 @@ MIXED_COUNTERS = ["SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_MUL_F32", "SQ_INSTS_VA
                   "SQ_INSTS_VALU", "SQ_INSTS_LDS"]
 
 
-def _pass(counters: list, outdir: str, mixed: bool = False) -> dict:
+def _target_args(mixed: bool, wl: str, n1: int, n2: int) -> list:
+    return ["--target", "--workload", wl, "--n1", str(n1), "--n2", str(n2)] + \
+        (["--mixed"] if mixed else [])
+
+
+def _pass(counters: list, outdir: str, mixed: bool = False, wl: str = "tube", n1: int = N1,
+          n2: int = N2) -> dict:
     """one rocprofv3 run collecting `counters`; returns
     {counter: {"stage": [per launch], "copy": [per launch]}}"""
     cmd = ["timeout", "-s", "KILL", "120", "rocprofv3", "--pmc", " ".join(counters),
            "--output-format", "csv", "-d", outdir, "-o", "run", "--", sys.executable, "-m",
-           "paper_2609_29081_amd.prof_counters", "--target"] + (["--mixed"] if mixed else [])
+           "paper_2609_29081_amd.prof_counters"] + _target_args(mixed, wl, n1, n2)
     env = dict(os.environ, TMPDIR="/tmp",
                PYTHONPATH=ROOT + os.pathsep + os.environ.get("PYTHONPATH", ""))
     subprocess.run(cmd, check=True, cwd="/tmp", env=env)
@@ -146,15 +164,18 @@ def _pass(counters: list, outdir: str, mixed: bool = False) -> dict:
     return vals
 
 
-def driver(outroot: str, mixed: bool = False) -> None:
+def driver(outroot: str, mixed: bool = False, wl: str = "tube", n1: int = N1,
+           n2: int = N2) -> None:
     sys.path.insert(0, ROOT)
     import bench
 
+    if wl == "vortex":
+        n2 = n1
     res = {}
     for c in ("FETCH_SIZE", "WRITE_SIZE"):
-        res[c] = _pass([c], os.path.join(outroot, c.lower()), mixed)[c]
+        res[c] = _pass([c], os.path.join(outroot, c.lower()), mixed, wl, n1, n2)[c]
     ilist = MIXED_COUNTERS if mixed else FP64_COUNTERS
-    isa = _pass(ilist, os.path.join(outroot, "isa"), mixed)
+    isa = _pass(ilist, os.path.join(outroot, "isa"), mixed, wl, n1, n2)
     per = {c: sum(isa[c]["stage"]) / len(isa[c]["stage"]) for c in ilist}
     flops = 64.0 * (2.0 * per["SQ_INSTS_VALU_FMA_F64"] + per["SQ_INSTS_VALU_MUL_F64"]
                     + per["SQ_INSTS_VALU_ADD_F64"])
@@ -168,7 +189,8 @@ def driver(outroot: str, mixed: bool = False) -> None:
     w_scale = COPY_BYTES / copy_write      # bytes per counter unit, writes
     fetch_b = fetch_kib * f_scale
     write_b = write_kib * w_scale
-    out = {"kernel": "stage2d", "precision": "mixed" if mixed else "fp64", "n1": N1, "n2": N2,
+    out = {"kernel": "stage2d", "precision": "mixed" if mixed else "fp64", "n1": n1, "n2": n2,
+           "workload": wl,
            "kernel_source_hash": bench.kernel_source_hash(),
            "fetch_counter_kib": fetch_kib, "write_counter_kib": write_kib,
            "copy_fetch_counter": copy_fetch, "copy_write_counter": copy_write,
@@ -182,15 +204,20 @@ def driver(outroot: str, mixed: bool = False) -> None:
     prof = outroot
     os.makedirs(prof, exist_ok=True)
     tag = "_mixed" if mixed else ""
-    with open(os.path.join(prof, f"traffic{tag}.json"), "w") as fh:
+    wname = "shock_tube" if wl == "tube" else "vortex_wave"
+    base = wl == "tube" and (n1, n2) == (N1, N2)
+    jname = f"traffic{tag}.json" if base else f"traffic{tag}_{wname}_{n1}x{n2}.json"
+    with open(os.path.join(prof, jname), "w") as fh:
         json.dump(out, fh, indent=1)
-    cmdline = "python -m paper_2609_29081_amd.prof_counters" + (" --mixed" if mixed else "")
-    alg = 8.0 * 8.0 / 3.0 * (4 * (N1 * N2 + (N1 + 1) * N2 + N1 * (N2 + 1) + (N1 + 1) * (N2 + 1)))
+    cmdline = "python -m paper_2609_29081_amd.prof_counters" + (" --mixed" if mixed else "") + \
+        ("" if base else f" --workload {wl} --n1 {n1} --n2 {n2}")
+    g, _, _ = workload(wl, n1, n2)
+    alg = 8.0 * 8.0 / 3.0 * g.state_len
     what = "mixed-precision (FP32 stencils, FP64 blends and updates)" if mixed else "FP64"
-    md = [f"# Counters of the fused 2D stage kernel, {what} (shock tube {N1}x{N2})", "",
+    md = [f"# Counters of the fused 2D stage kernel, {what} ({wname.replace('_', ' ')} {n1}x{n2})", "",
           f"Command: `{cmdline}` (three rocprofv3 passes, `--pmc FETCH_SIZE`,",
           f"`--pmc WRITE_SIZE`, `--pmc {' '.join(ilist)}`, each over",
-          f"`python -m paper_2609_29081_amd.prof_counters --target{' --mixed' if mixed else ''}`: "
+          f"`python -m paper_2609_29081_amd.prof_counters {' '.join(_target_args(mixed, wl, n1, n2))}`: "
           "three RK3 steps' worth of",
           "complete stage launches at the CFL dt of the initial state, then a 256 MiB device copy",
           "for calibration).", "",
@@ -211,7 +238,7 @@ def driver(outroot: str, mixed: bool = False) -> None:
     md += [f"| executed FP64 flops per launch (64 lanes x (2 FMA + MUL + ADD)) | {flops:.4g} |"]
     if mixed:
         md += [f"| executed FP32 flops per launch (64 lanes x (2 FMA + MUL + ADD)) | {flops32:.4g} |"]
-    name = f"stage2d{tag}_shock_tube_1000x500_counters.md"
+    name = f"stage2d{tag}_{wname}_{n1}x{n2}_counters.md"
     with open(os.path.join(prof, name), "w") as fh:
         fh.write("\n".join(md) + "\n")
     print(json.dumps(out))
@@ -223,6 +250,9 @@ if __name__ == "__main__":
     ap.add_argument("--mixed", action="store_true")
     ap.add_argument("--target-batch", action="store_true")
     ap.add_argument("--target-learned", action="store_true")
+    ap.add_argument("--workload", choices=["tube", "vortex"], default="tube")
+    ap.add_argument("--n1", type=int, default=N1)
+    ap.add_argument("--n2", type=int, default=N2)
     ap.add_argument("--out", default=os.path.join(tempfile.gettempdir(), "af_counters"))
     a = ap.parse_args()
     if a.target_learned:
@@ -230,6 +260,6 @@ if __name__ == "__main__":
     elif a.target_batch:
         target_batch()
     elif a.target:
-        target(mixed=a.mixed)
+        target(mixed=a.mixed, wl=a.workload, n1=a.n1, n2=a.n1 if a.workload == "vortex" else a.n2)
     else:
-        driver(a.out, mixed=a.mixed)
+        driver(a.out, mixed=a.mixed, wl=a.workload, n1=a.n1, n2=a.n2)
