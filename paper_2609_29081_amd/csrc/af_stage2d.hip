@@ -258,6 +258,10 @@ struct Tile {
   // FP64 cell averages of the tile +- 1 for the mixed-precision stage (the
   // FP64 stage reads them from C)
   double AV[4][kFP64<R> ? 1 : NC];
+  // mixed-precision stage: the low part V - float(V) of the FP64 value V of
+  // each of the tile's point DOFs, so that phase 5 has V to 48 bits from
+  // U (the high part) without reading the state again
+  float PL[4][kFP64<R> ? 1 : NPT];
 };
 static_assert(4 * NSY <= 14 * NC, "the y-direction site data fit in rows 0-13 of C");
 
@@ -693,9 +697,27 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
     }
     // FP32 stencils: the point sites' (u, v, p, T, c) from the FP64 values
     // (centre sites get the Simpson centre's); the FP64 stage takes them in
-    // phase 2, where they cost fewer live registers
+    // phase 2, where they cost fewer live registers.  The FP64 averages of
+    // the tile's cells +- 1 go to AV, and the low parts of the FP64 values
+    // of the tile's own points to PL, for the FP64 updates
     if constexpr (!kFP64<R>) {
-      if (!((X & 1) && (Y & 1))) store_aux(T, phd64, s, V);
+      const int lx = X - X0, ly = Y - Y0;
+      if ((X & 1) && (Y & 1)) {
+        const int ci = (lx + 1) >> 1, cj = (ly + 1) >> 1;  // cell offset + 1
+        if (lx >= -1 && ly >= -1 && ci <= TX + 1 && cj <= TY + 1) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) T.AV[k][cj * WC + ci] = V[k];
+        }
+      } else {
+        store_aux(T, phd64, s, V);
+        if (lx >= 0 && ly >= 0 && lx < 2 * TX && ly < 2 * TY) {
+          // point type 0 x-edge (X even, Y odd), 1 y-edge, 2 corner
+          const int pt = (X & 1) ? 1 : ((Y & 1) ? 0 : 2);
+          const int pi = pt * (TX * TY) + (ly >> 1) * TX + (lx >> 1);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) T.PL[k][pi] = float(V[k] - double(float(V[k])));
+        }
+      }
     }
   }
   __syncthreads();
@@ -756,12 +778,6 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
     cell_low(g, ph, C0, Cxm, Cxp, Cym, Cyp, o);
 #pragma unroll
     for (int k = 0; k < 23; ++k) T.C[k][s] = o[k];
-    if constexpr (!kFP64<R>) {
-      double V[4];
-      raw_value(g, Uk, 2 * i + 1, 2 * j + 1, V);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) T.AV[k][s] = V[k];
-    }
   }
   if constexpr (kFP64<R>) {
     for (int s = tid; s < NA; s += NT) {
@@ -1011,14 +1027,11 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
       const int a = (Y - Y0 + 4) * WA + (X - X0 + 4);
       const int q = (Y - Y0 + 2) * WG + (X - X0 + 2);
       const long gi = (long)j * ni + i;
-      // the point's HBM operands, loaded while the residual is computed:
-      // U^n for the RK combination and, for FP32 stencils, the FP64 value
+      // U^n for the RK combination, loaded while the residual is computed
       double un[4] = {0.0, 0.0, 0.0, 0.0}, U0[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < 4; ++k)
         if (!first) un[k] = Un[off + k * np + gi];
-        if constexpr (!kFP64<R>) U0[k] = Uk[off + k * np + gi];
-      }
       R Rs[4] = {R(0.0), R(0.0), R(0.0), R(0.0)};
 #pragma unroll
       for (int d = 0; d < 2; ++d) {
@@ -1098,7 +1111,10 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
       double UH[4], out[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        if constexpr (kFP64<R>) U0[k] = T.U[k][a];
+        if constexpr (kFP64<R>)
+          U0[k] = T.U[k][a];
+        else
+          U0[k] = double(T.U[k][a]) + double(T.PL[k][s]);
         UH[k] = U0[k] + dt * double(Rs[k]);
       }
       if (ph.lim & LIM_POINT) {
