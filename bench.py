@@ -22,6 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "cell-DOF updates/s per RK stage, 2D viscous shock tube; % peak HBM BW; L1 err"
+APS = 4  # RK3 attempts per replayed slot of the device-resident step loop
 HBM_PEAK_GBS = 8000.0
 FP64_VALU_PEAK_TFLOPS = 78.6
 VALU_SIMDS = 1024      # 256 compute units x 4 SIMDs
@@ -135,13 +136,18 @@ def main() -> int:
     U = dev_U0.clone()
     K, Wm = args.steps, args.warmup
 
-    # warm-up (also loads the code objects)
+    # warm-up (also loads the code objects and builds the step loop's graph)
     if Wm > 0:
-        st, ns, _ = S.af_run(U, 0.0, 1e30, Wm, check_every=1)
+        st, ns, _, _ = S.af_run_graph(U, 0.0, 1e30, Wm, attempts_per_slot=APS)
         if st != af.AF_OK:
             raise RuntimeError(f"warm-up failed with status {st}")
+        U.copy_(dev_U0)
+        st, ns, _ = S.af_run(U, 0.0, 1e30, Wm, check_every=1)
 
-    # timed region: K steps from the initial state, resident in HBM
+    # timed region: K steps from the initial state, resident in HBM.  Every
+    # step decision (the CFL step, accepting an attempt or redoing it with
+    # dt/2, as the method prescribes) is taken on the device, and the step
+    # rounds are replayed from a HIP graph (af_run_graph)
     U.copy_(dev_U0)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -149,15 +155,27 @@ def main() -> int:
     ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev0.record(stream)
-    # the flags are checked after every step (a rejected step is redone with
-    # dt/2 at once, as the method prescribes); one host synchronisation per step
-    st, nsteps, t_end = S.af_run(U, 0.0, 1e30, K, check_every=1)
+    st, nsteps, t_end, attempts = S.af_run_graph(U, 0.0, 1e30, K, attempts_per_slot=APS)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     if st != af.AF_OK or nsteps != K:
         raise RuntimeError(f"timed run failed: status {st}, {nsteps}/{K} steps")
     gpu_ms = ev0.elapsed_time(ev1)
+    U_graph = U.clone()
+    # the same K steps with the decisions on the host (af_run, one
+    # synchronisation per attempt), for comparison: the same states
+    U.copy_(dev_U0)
+    torch.cuda.synchronize()
+    eh0 = torch.cuda.Event(enable_timing=True)
+    eh1 = torch.cuda.Event(enable_timing=True)
+    eh0.record(stream)
+    st_h, ns_h, _ = S.af_run(U, 0.0, 1e30, K, check_every=1)
+    eh1.record(stream)
+    torch.cuda.synchronize()
+    host_ms = eh0.elapsed_time(eh1)
+    if st_h != af.AF_OK or ns_h != K or not torch.equal(U, U_graph):
+        raise RuntimeError("host-decided run differs from the device-decided one")
     sec = gpu_ms / 1e3
     stages = 3 * K
     dof_sites = g.dof_sites
@@ -168,7 +186,9 @@ def main() -> int:
     stage_gbs = stage_bytes / (stage_ms * 1e-3) / 1e9
 
     # RK3 attempts per accepted step over the same window (a rejected attempt
-    # is redone with dt/2; its stages stop at the first flag): launch counts
+    # is redone with dt/2; its stages stop at the first flag)
+    attempts_per_step = attempts / K
+    # the stage launches of the window (host-decided run, timed per launch)
     U.copy_(dev_U0)
     torch.cuda.synchronize()
     S.af_timing(True)
@@ -176,7 +196,6 @@ def main() -> int:
     st, _, _ = S.af_run(U, 0.0, 1e30, K, check_every=1)
     kw_ = S.af_timing_read()
     stage_kind = "stage2d" if "stage2d" in kw_ else "lattice"
-    attempts_per_step = kw_[stage_kind][0] / (3.0 * K)
     # the same kernel over the K steps of the timed window: every launch,
     # the early exits of rejected attempts included (so a shorter mean)
     window = {"launches": kw_[stage_kind][0],
@@ -254,7 +273,12 @@ def main() -> int:
     # same K steps from t = 0, timed the same way, and its difference from
     # the FP64 form over fixed-dt steps (no halving, equal times)
     forms = {"fp64": {"value": value, "ms_per_step": gpu_ms / K,
-                      "stage_us": round(dom_avg_s * 1e6, 1)}}
+                      "stage_us": round(dom_avg_s * 1e6, 1),
+                      "step_loop": "af_run_graph: decisions on the device, graph replay"},
+             "fp64_host_loop": {"value": dof_sites * stages / (host_ms / 1e3),
+                                "ms_per_step": host_ms / K,
+                                "step_loop": "af_run: one host synchronisation per attempt",
+                                "state": "bitwise equal to the device-decided run"}}
     if not args.no_mixed:
         Sm = af.Solver(g, precision=af.PREC_MIXED, **kw)
         Um = dev_U0.clone()
@@ -264,8 +288,12 @@ def main() -> int:
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
+        if Wm > 0:
+            Sm.af_run_graph(Um, 0.0, 1e30, 1, attempts_per_slot=APS)
+            Um.copy_(dev_U0)
+            torch.cuda.synchronize()
         e0.record(stream)
-        stm, nm, _ = Sm.af_run(Um, 0.0, 1e30, K, check_every=1)
+        stm, nm, _, _ = Sm.af_run_graph(Um, 0.0, 1e30, K, attempts_per_slot=APS)
         e1.record(stream)
         torch.cuda.synchronize()
         if stm != af.AF_OK or nm != K:
@@ -391,8 +419,9 @@ def vortex_form(args, stream) -> dict:
 
 def whole_run(args, g, U0, kw) -> dict:
     """The 1000 x 500 tube from t = 0 to t = 1 (the configuration's end
-    time), once per listed precision: steps, RK3 attempts per step (stage
-    launches / 3), GPU time (HIP events around each chunk of af_run), DOF
+    time), once per listed precision, with the device-resident step loop:
+    steps, RK3 attempts per step, GPU time (HIP events around each chunk of
+    af_run_graph), DOF
     updates per second over the whole run, the admissibility count at the
     end, and the density along the bottom wall (y = 0) at t = 1."""
     import numpy as np
@@ -407,8 +436,7 @@ def whole_run(args, g, U0, kw) -> dict:
         S = af.Solver(g, precision=prec, **kw)
         U = S.to_device(U0)
         stream = torch.cuda.current_stream()
-        t, steps, launches, gpu_ms = 0.0, 0, 0, 0.0
-        S.af_timing(True)
+        t, steps, attempts, gpu_ms = 0.0, 0, 0, 0.0
         w0 = time.perf_counter()
         last = w0
         status = af.AF_OK
@@ -416,19 +444,18 @@ def whole_run(args, g, U0, kw) -> dict:
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            status, ns, t = S.af_run(U, t, 1.0, 2000, check_every=1)
+            status, ns, t, att = S.af_run_graph(U, t, 1.0, 4000, attempts_per_slot=APS)
             e1.record(stream)
             torch.cuda.synchronize()
             gpu_ms += e0.elapsed_time(e1)
             steps += ns
-            launches += S.af_timing_read().get("stage2d", (0, 0.0))[0]
+            attempts += att
             if status != af.AF_OK or ns == 0:
                 break
             if time.perf_counter() - last > 20:
                 last = time.perf_counter()
                 print(f"bench: whole run {pname}: step {steps} t {t:.4f} "
                       f"{last - w0:.0f} s", file=sys.stderr, flush=True)
-        S.af_timing(False)
         wall = time.perf_counter() - w0
         bad = S.af_check_admissible(U)
         P = g.split(U.cpu().numpy())
@@ -436,7 +463,7 @@ def whole_run(args, g, U0, kw) -> dict:
         rho_wall[0::2] = P["co"][0, 0, :]
         rho_wall[1::2] = P["ye"][0, 0, :]
         r = {"status": int(status), "t_end": t, "steps": steps,
-             "rk3_attempts_per_step": round(launches / 3.0 / max(steps, 1), 3),
+             "rk3_attempts_per_step": round(attempts / max(steps, 1), 3),
              "gpu_s": round(gpu_ms / 1e3, 2), "wall_s": round(wall, 1),
              "value": g.dof_sites * 3 * steps / (gpu_ms / 1e3), "unit": "DOF-updates/s",
              "inadmissible_dofs_at_end": int(bad),

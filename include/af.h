@@ -228,6 +228,23 @@ af_status af_step_source(af_ctx* ctx, double* U, void* ws, void* stream, double 
 af_status af_run(af_ctx* ctx, double* U, void* ws, void* stream, double t0, double t_final,
                  long max_steps, int check_every, long* nsteps_out, double* t_out);
 
+/* af_run with every step decision on the device (2D, SSP-RK3, without the
+ * learned blend): a round opens a step with the CFL dt of eq. (cfl) when the
+ * previous one was accepted (clipped to t_final - t), runs one RK3 attempt,
+ * and accepts it or redoes it with dt/2 in the next round (the remark on the
+ * time step at the end of Sec. 3.4), up to max_halvings times.  Rounds are
+ * enqueued in slots of attempts_per_slot (>= 1), captured once in a HIP graph
+ * and replayed on `stream`; the host synchronises only once per four slots,
+ * to stop (rounds after the last step do nothing).  The state rotates through U and the workspace's two stage buffers
+ * and ends in U.  Results equal af_run's bit for bit.  Synchronous.
+ * *nsteps_out, *t_out and *attempts_out (RK3 attempts, accepted and rejected;
+ * any may be NULL) receive the counts and the final time; AF_E_PP or
+ * AF_E_NONFINITE as in af_run, U then holding the state before the failed
+ * step. */
+af_status af_run_graph(af_ctx* ctx, double* U, void* ws, void* stream, double t0,
+                       double t_final, long max_steps, int attempts_per_slot, long* nsteps_out,
+                       double* t_out, long* attempts_out);
+
 /* Flags accumulated in the workspace (synchronous read), and their reset
  * (asynchronous). */
 af_status af_read_flags(af_ctx* ctx, const void* ws, int* flags, void* stream);

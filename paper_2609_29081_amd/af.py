@@ -51,7 +51,7 @@ EXPORTS = ["af_default_params", "af_init_grid", "af_destroy", "af_set_bc", "af_s
            "af_batch_set_variant", "af_batch_tune", "af_face_count", "af_mlp_param_count",
            "af_blend_features", "af_set_blend_net", "af_blend_infer", "af_rk_stage_blend",
            "af_mlp_grad_workspace_bytes", "af_mlp_grad", "af_mlp_adam", "af_mlp_train",
-           "af_stage_times", "af_step_source", "af_step_noalloc"]
+           "af_stage_times", "af_step_source", "af_step_noalloc", "af_run_graph"]
 
 # kernel kinds reported by af_timing_read
 KERNEL_KINDS = {0: "lattice", 1: "grad", 2: "cellpre", 3: "face", 4: "cells", 5: "points",
@@ -122,13 +122,15 @@ def lib():
                                       C.POINTER(C.c_int)]
         L.af_run.argtypes = [vp, vp, vp, vp, C.c_double, C.c_double, C.c_long, ip,
                              C.POINTER(C.c_long), dp]
+        L.af_run_graph.argtypes = [vp, vp, vp, vp, C.c_double, C.c_double, C.c_long, ip,
+                                   C.POINTER(C.c_long), dp, C.POINTER(C.c_long)]
         L.af_read_flags.argtypes = [vp, vp, C.POINTER(C.c_int), vp]
         L.af_reset_flags.argtypes = [vp, vp, vp]
         L.af_timing.argtypes = [vp, ip]
         L.af_timing_read.argtypes = [vp, C.POINTER(C.c_long), dp]
         L.af_last_error.restype = C.c_char_p
         for name in ("af_default_params", "af_init_grid", "af_set_bc", "af_rk_stage", "af_cfl_dt",
-                     "af_step", "af_step_noalloc", "af_run", "af_read_flags", "af_reset_flags", "af_timing",
+                     "af_step", "af_step_noalloc", "af_run", "af_run_graph", "af_read_flags", "af_reset_flags", "af_timing",
                      "af_timing_read"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -238,6 +240,20 @@ class Solver:
         if st in (AF_E_ARG, AF_E_HIP):
             _check(st)
         return st, ns.value, t.value
+
+    def af_run_graph(self, U, t0: float, t_final: float, max_steps: int,
+                     attempts_per_slot: int = 4, stream=None):
+        """af_run with the step decisions on the device and graph replay;
+        returns (status, steps, t, attempts)"""
+        ns = C.c_long()
+        t = C.c_double()
+        att = C.c_long()
+        st = lib().af_run_graph(self.ctx, _ptr(U), _ptr(self.ws), _stream(stream), t0, t_final,
+                                max_steps, attempts_per_slot, C.byref(ns), C.byref(t),
+                                C.byref(att))
+        if st in (AF_E_ARG, AF_E_HIP):
+            _check(st)
+        return st, ns.value, t.value, att.value
 
     def af_read_flags(self, stream=None) -> int:
         f = C.c_int()

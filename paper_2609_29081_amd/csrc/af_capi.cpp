@@ -70,6 +70,12 @@ struct af_ctx {
   af_params p;
   int bc[4];
   EventTimer* timer = nullptr;
+  // af_run_graph's executable graph, reused while its workspace and slot
+  // length stay the same (the stages read everything else from the device
+  // descriptor)
+  hipGraphExec_t run_exec = nullptr;
+  const void* run_ws = nullptr;
+  int run_slot = 0, run_dev = -1;
   const float* net = nullptr;  // learned-blend network parameters (device), or NULL
   double bcstate[2][3] = {{1.0, 0.0, 1.0}, {1.0, 0.0, 1.0}};  // 1D Dirichlet states
 };
@@ -328,6 +334,34 @@ hipError_t rk3(const afi::Geo& g, const afd::Phys& ph, const afi::Work& w, const
   return hipSuccess;
 }
 
+// the static part of one instance's batch descriptor: context c with grid
+// g, stage variant v, rotating state buffers b0 (the caller's state), b1,
+// b2, times t0..t_final and at most max_steps steps
+afi::BatchInst instance_of(const af_ctx* c, const afi::Geo& g, const afi::StageVariant* v,
+                           double* b0, double* b1, double* b2, double t0, double t_final,
+                           long max_steps) {
+  const af_params& p = c->p;
+  afi::BatchInst I;
+  memset(&I, 0, sizeof(I));
+  I.g = afi::stage_geo(g);
+  I.ph = physics(p);
+  I.buf[0] = b0;
+  I.buf[1] = b1;
+  I.buf[2] = b2;
+  I.ntx = g.n1 / 16 + 1;
+  I.ntiles = v->tiles(g);
+  I.ncell = (long)g.n1 * g.n2;
+  I.icx = 1.0 / (p.cfl_c * g.dx);
+  I.icy = 1.0 / (p.cfl_c * g.dy);
+  const double hmin = fmin(g.dx, g.dy);
+  I.vcoef = fmax(4.0 * p.mu / 3.0, p.gamma * p.mu / p.Pr) / (p.cfl_v * hmin * hmin);
+  I.t_final = t_final;
+  I.max_steps = max_steps;
+  I.max_halvings = p.max_halvings;
+  I.t = t0;
+  return I;
+}
+
 // host copies of the batch descriptors for states U, times t0..t_final and
 // the tile shape of stage variant v; *total_tiles receives the tiles of all
 // instances (a stage launch has at most that many)
@@ -338,28 +372,10 @@ af_status batch_descriptors(const af_batch* b, const afi::StageVariant* v, doubl
   h.assign(n, afi::BatchInst{});
   int total = 0;
   for (int i = 0; i < n; ++i) {
-    const af_params& p = b->ctx[i]->p;
-    const afi::Geo& g = b->geo[i];
     if (!U[i]) return fail(AF_E_ARG, "batch: state %d is NULL", i);
-    afi::BatchInst& I = h[i];
-    memset(&I, 0, sizeof(I));
-    I.g = afi::stage_geo(g);
-    I.ph = physics(p);
-    I.buf[0] = U[i];
-    I.buf[1] = (double*)(base + b->off_bufs[2 * i]);
-    I.buf[2] = (double*)(base + b->off_bufs[2 * i + 1]);
-    I.ntx = g.n1 / 16 + 1;
-    I.ntiles = v->tiles(g);
-    total += I.ntiles;
-    I.ncell = (long)g.n1 * g.n2;
-    I.icx = 1.0 / (p.cfl_c * g.dx);
-    I.icy = 1.0 / (p.cfl_c * g.dy);
-    const double hmin = fmin(g.dx, g.dy);
-    I.vcoef = fmax(4.0 * p.mu / 3.0, p.gamma * p.mu / p.Pr) / (p.cfl_v * hmin * hmin);
-    I.t_final = t_final;
-    I.max_steps = max_steps;
-    I.max_halvings = p.max_halvings;
-    I.t = t0;
+    h[i] = instance_of(b->ctx[i], b->geo[i], v, U[i], (double*)(base + b->off_bufs[2 * i]),
+                       (double*)(base + b->off_bufs[2 * i + 1]), t0, t_final, max_steps);
+    total += h[i].ntiles;
   }
   *total_tiles = total;
   return AF_OK;
@@ -373,14 +389,88 @@ af_status batch_descriptors(const af_batch* b, const afi::StageVariant* v, doubl
 hipError_t batch_slot(const afi::StageVariant* v, afi::BatchInst* dinst, int n, int total_tiles,
                       double* partial, int* nact, int rounds, hipStream_t q) {
   hipError_t e;
+  const int nb = n == 1 ? afi::kSingleCflBlocks : afi::kBatchCflBlocks;
   for (int a = 0; a < rounds; ++a) {
-    if ((e = afi::batch_cfl(dinst, n, partial, q)) != hipSuccess) return e;
-    if ((e = afi::batch_open(dinst, n, partial, nact, q)) != hipSuccess) return e;
+    if ((e = afi::batch_cfl(dinst, n, partial, nb, q)) != hipSuccess) return e;
+    if ((e = afi::batch_open(dinst, n, partial, nb, nact, q)) != hipSuccess) return e;
     for (int k = 0; k < 3; ++k)
       if ((e = v->batch(dinst, n, total_tiles, nact, k, q, nullptr)) != hipSuccess) return e;
     if ((e = afi::batch_decide(dinst, n, nact, q)) != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// Enqueue step slots (slot(stream) enqueues one) for the n instances whose
+// descriptors (host copies h, already on the device at dinst) are set, on
+// stream s: captured once in a HIP graph (use_graph) or launched directly,
+// in chunks of `chunk` slots with a read-back of the descriptors after each; stops
+// once no instance is active or may open a step.  h receives the final
+// descriptors.
+// keep (cache != NULL): the instantiated graph is taken from *cache if set
+// there, else built and left in *cache for the caller to reuse and destroy.
+template <typename Slot>
+af_status run_slots(Slot slot, afi::BatchInst* dinst, int n, int use_graph, hipStream_t s,
+                    long max_steps, double t_final, std::vector<afi::BatchInst>& h,
+                    const char* who, hipGraphExec_t* cache = nullptr, long chunk = 8) {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = cache ? *cache : nullptr;
+  if (use_graph && !exec) {
+    // the slot is captured on a private stream (the caller's may be the null
+    // stream, which cannot be captured) and replayed on the caller's
+    hipStream_t cs = nullptr;
+    AF_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) e = slot(cs);
+    hipGraph_t gcap = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cs, &gcap);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (gcap) (void)hipGraphDestroy(gcap);
+      return fail(AF_E_HIP, "%s: graph capture: %s", who,
+                  hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    graph = gcap;
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return fail(AF_E_HIP, "%s: graph instantiation failed", who);
+    }
+    (void)hipGraphDestroy(graph);  // the executable graph keeps what it needs
+    graph = nullptr;
+    if (cache) *cache = exec;
+  }
+  af_status st = AF_OK;
+  long progress = -1;  // sum of steps and attempts: it grows while any instance works
+  for (;;) {
+    for (long c = 0; c < chunk; ++c) {
+      const hipError_t e = exec ? hipGraphLaunch(exec, s) : slot(s);
+      if (e != hipSuccess) {
+        st = fail(AF_E_HIP, "%s: launch: %s", who, hipGetErrorString(e));
+        break;
+      }
+    }
+    if (st != AF_OK) break;
+    if (hipMemcpyAsync(h.data(), dinst, sizeof(afi::BatchInst) * n, hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      st = fail(AF_E_HIP, "%s: read-back failed", who);
+      break;
+    }
+    bool busy = false;
+    long prog = 0;
+    for (int i = 0; i < n; ++i) {
+      const afi::BatchInst& I = h[i];
+      if (I.active || (I.status == 0 && I.steps < max_steps && I.t < t_final)) busy = true;
+      prog += I.steps + I.attempts;
+    }
+    if (!busy) break;
+    if (prog == progress) {
+      st = fail(AF_E_HIP, "%s: no instance made progress", who);
+      break;
+    }
+    progress = prog;
+  }
+  if (exec && !cache) (void)hipGraphExecDestroy(exec);
+  return st;
 }
 
 }  // namespace
@@ -443,6 +533,7 @@ af_status af_init_grid(const af_params* p, af_ctx** out) {
 
 void af_destroy(af_ctx* c) {
   if (!c) return;
+  if (c->run_exec) (void)hipGraphExecDestroy(c->run_exec);
   delete c->timer;
   delete c;
 }
@@ -775,7 +866,8 @@ af_status af_batch_create(af_ctx* const* ctxs, int n, af_batch** out) {
     return o;
   };
   take(sizeof(afi::BatchInst) * n);
-  b->off_partial = take(sizeof(double) * 2 * afi::kBatchCflBlocks * n);
+  b->off_partial = take(sizeof(double) * 2 *
+                        (n == 1 ? afi::kSingleCflBlocks : afi::kBatchCflBlocks * n));
   b->off_nact = take(sizeof(int));
   for (int i = 0; i < n; ++i) {
     af_ctx* c = ctxs[i];
@@ -822,64 +914,8 @@ af_status af_batch_run(af_batch* b, double* const* U, void* ws, void* stream, do
   auto slot = [&](hipStream_t q) {
     return batch_slot(b->var, dinst, n, total_tiles, partial, nact, attempts_per_slot, q);
   };
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  if (use_graph) {
-    // the slot is captured on a private stream (the caller's may be the null
-    // stream, which cannot be captured) and replayed on the caller's
-    hipStream_t cs = nullptr;
-    AF_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
-    if (e == hipSuccess) e = slot(cs);
-    hipGraph_t gcap = nullptr;
-    const hipError_t e2 = hipStreamEndCapture(cs, &gcap);
-    (void)hipStreamDestroy(cs);
-    if (e != hipSuccess || e2 != hipSuccess) {
-      if (gcap) (void)hipGraphDestroy(gcap);
-      return hip_fail(e != hipSuccess ? e : e2, "af_batch_run: graph capture");
-    }
-    graph = gcap;
-    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-      (void)hipGraphDestroy(graph);
-      return fail(AF_E_HIP, "af_batch_run: graph instantiation failed");
-    }
-  }
-  // enqueue step slots in chunks; after each chunk, stop once no instance is
-  // active or may open a step
-  af_status st = AF_OK;
-  long progress = -1;  // sum of steps and attempts: it grows while any instance works
-  for (;;) {
-    const long chunk = 8;
-    for (long c = 0; c < chunk; ++c) {
-      const hipError_t e = exec ? hipGraphLaunch(exec, s) : slot(s);
-      if (e != hipSuccess) {
-        st = hip_fail(e, "af_batch_run: launch");
-        break;
-      }
-    }
-    if (st != AF_OK) break;
-    if (hipMemcpyAsync(h.data(), dinst, sizeof(afi::BatchInst) * n, hipMemcpyDeviceToHost, s) !=
-            hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) {
-      st = fail(AF_E_HIP, "af_batch_run: read-back failed");
-      break;
-    }
-    bool busy = false;
-    long prog = 0;
-    for (int i = 0; i < n; ++i) {
-      const afi::BatchInst& I = h[i];
-      if (I.active || (I.status == 0 && I.steps < max_steps && I.t < t_final)) busy = true;
-      prog += I.steps + I.attempts;
-    }
-    if (!busy) break;
-    if (prog == progress) {
-      st = fail(AF_E_HIP, "af_batch_run: no instance made progress");
-      break;
-    }
-    progress = prog;
-  }
-  if (exec) (void)hipGraphExecDestroy(exec);
-  if (graph) (void)hipGraphDestroy(graph);
+  const af_status st =
+      run_slots(slot, dinst, n, use_graph, s, max_steps, t_final, h, "af_batch_run");
   if (st != AF_OK) return st;
   // the current state of every instance back into its U
   for (int i = 0; i < n; ++i)
@@ -891,6 +927,67 @@ af_status af_batch_run(af_batch* b, double* const* U, void* ws, void* stream, do
     if (status) status[i] = h[i].status;
     if (attempts) attempts[i] = h[i].attempts;
   }
+  return AF_OK;
+}
+
+af_status af_run_graph(af_ctx* c, double* U, void* ws, void* stream, double t0, double t_final,
+                       long max_steps, int attempts_per_slot, long* nsteps_out, double* t_out,
+                       long* attempts_out) {
+  if (!c || !U || !ws) return fail(AF_E_ARG, "af_run_graph: NULL argument");
+  if (c->p.dim != 2 || c->p.rk != 3 || (c->p.limiter & AF_LIM_LEARNED))
+    return fail(AF_E_ARG, "af_run_graph: 2D, SSP-RK3, plain limiters only");
+  if (attempts_per_slot < 1) return fail(AF_E_ARG, "attempts_per_slot must be >= 1");
+  if (max_steps < 0 || !(t_final >= t0)) return fail(AF_E_ARG, "af_run_graph: bad steps or times");
+  afi::Geo g;
+  if (!geometry(c, &g)) return AF_E_ARG;
+  const afi::Work w = work_of(c, g, ws);
+  const hipStream_t s = (hipStream_t)stream;
+  const afi::StageVariant* v = afi::default_variant(g.mixed);
+  std::vector<afi::BatchInst> h(1);
+  h[0] = instance_of(c, g, v, U, w.S1, w.S2, t0, t_final, max_steps);
+  h[0].stage_nwg = v->dev_nwg(g);
+  AF_HIP(hipMemcpyAsync(w.binst, h.data(), sizeof(afi::BatchInst), hipMemcpyHostToDevice, s));
+  // the first step's CFL maxima; every later step opens from those its
+  // predecessor's last stage left (the dt reduction fused into that stage)
+  AF_HIP(afi::batch_cfl(w.binst, 1, w.bpartial, afi::kSingleCflBlocks, s));
+  int dev = 0;
+  AF_HIP(hipGetDevice(&dev));
+  if (c->run_exec && (c->run_ws != ws || c->run_slot != attempts_per_slot || c->run_dev != dev)) {
+    (void)hipGraphExecDestroy(c->run_exec);
+    c->run_exec = nullptr;
+  }
+  c->run_ws = ws;
+  c->run_slot = attempts_per_slot;
+  c->run_dev = dev;
+  const afd::Phys ph = physics(c->p);
+  // a round: open a step if the last one was accepted (CFL dt from the
+  // maxima its last stage left), one RK3 attempt with the single-instance
+  // stage kernel, accept or halve
+  auto slot = [&](hipStream_t q) {
+    hipError_t e;
+    for (int a = 0; a < attempts_per_slot; ++a) {
+      if ((e = afi::batch_open(w.binst, 1, w.bpartial, afi::kSingleCflBlocks, w.bnact, q)) !=
+          hipSuccess)
+        return e;
+      for (int k = 0; k < 3; ++k)
+        if ((e = v->dev(g, ph, w.binst, w.bpartial, k, q)) != hipSuccess) return e;
+      if ((e = afi::batch_decide(w.binst, 1, w.bnact, q)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+  const af_status st = run_slots(slot, w.binst, 1, 1, s, max_steps, t_final, h, "af_run_graph",
+                                 &c->run_exec, 4);
+  if (st != AF_OK) return st;
+  if (h[0].cur != 0) AF_HIP(afi::copy_state(U, h[0].buf[h[0].cur], g.state_len, s));
+  AF_HIP(hipStreamSynchronize(s));
+  if (nsteps_out) *nsteps_out = h[0].steps;
+  if (t_out) *t_out = h[0].t;
+  if (attempts_out) *attempts_out = h[0].attempts;
+  if (h[0].status == AF_E_NONFINITE)
+    return fail(AF_E_NONFINITE, "non-finite values at t=%g", h[0].t);
+  if (h[0].status == AF_E_PP)
+    return fail(AF_E_PP, "low-order states inadmissible at t=%g after %d halvings", h[0].t,
+                c->p.max_halvings);
   return AF_OK;
 }
 

@@ -184,9 +184,9 @@ __global__ void __launch_bounds__(kBlock) k_batch_cfl(afi::BatchInst* inst, doub
   }
   block_max2(a, v);
   if (threadIdx.x == 0) {
-    double* q = partial + 2L * afi::kBatchCflBlocks * blockIdx.y;
+    double* q = partial + 2L * gridDim.x * blockIdx.y;
     q[blockIdx.x] = a;
-    q[afi::kBatchCflBlocks + blockIdx.x] = v;
+    q[gridDim.x + blockIdx.x] = v;
   }
 }
 
@@ -202,29 +202,51 @@ __device__ void count_active(afi::BatchInst* inst, int n, int* n_active) {
   if (threadIdx.x == 0) n_active[0] = cnt;
 }
 
-// open a step for every instance that may: dt = 1/(a + v) (eq. cfl),
-// clipped to t_final - t
+// open a step for instance i if it may: dt = 1/(a + v) (eq. cfl) from its
+// nb pairs of partial maxima, clipped to t_final - t (one thread)
+__device__ void open_one(afi::BatchInst& I, double a, double v) {
+  double dt = 1.0 / (a + v);
+  if (I.t + dt > I.t_final) dt = I.t_final - I.t;
+  if (!(dt > 0.0)) {
+    I.status = 4;  // AF_E_NONFINITE: no finite time step from this state
+    return;
+  }
+  I.dt = dt;
+  I.halvings = 0;
+  I.flags = 0u;
+  I.active = 1;
+}
+
+// open a step for every instance that may.  Many instances: one thread per
+// instance over its nb partials; one instance: the whole block reduces its
+// partials (a single instance takes many CFL blocks)
 __global__ void __launch_bounds__(kBlock) k_batch_open(afi::BatchInst* inst, int n,
-                                                       const double* partial, int* n_active) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    afi::BatchInst& I = inst[i];
-    if (!may_open(I)) continue;
-    const double* q = partial + 2L * afi::kBatchCflBlocks * i;
-    double a = 0.0, v = 0.0;
-    for (int k = 0; k < afi::kBatchCflBlocks; ++k) {
-      a = mx(a, q[k]);
-      v = mx(v, q[afi::kBatchCflBlocks + k]);
+                                                       const double* partial, int nb,
+                                                       int* n_active) {
+  if (n == 1) {
+    afi::BatchInst& I = inst[0];
+    if (may_open(I)) {
+      double a = 0.0, v = 0.0;
+      const int nr = I.cfl_nb > 0 ? I.cfl_nb : nb;  // maxima from the last stage, or all
+      for (int k = threadIdx.x; k < nr; k += blockDim.x) {
+        a = mx(a, partial[k]);
+        v = mx(v, partial[nb + k]);
+      }
+      block_max2(a, v);
+      if (threadIdx.x == 0) open_one(I, a, v);
     }
-    double dt = 1.0 / (a + v);
-    if (I.t + dt > I.t_final) dt = I.t_final - I.t;
-    if (!(dt > 0.0)) {
-      I.status = 4;  // AF_E_NONFINITE: no finite time step from this state
-      continue;
+  } else {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      afi::BatchInst& I = inst[i];
+      if (!may_open(I)) continue;
+      const double* q = partial + 2L * nb * i;
+      double a = 0.0, v = 0.0;
+      for (int k = 0; k < nb; ++k) {
+        a = mx(a, q[k]);
+        v = mx(v, q[nb + k]);
+      }
+      open_one(I, a, v);
     }
-    I.dt = dt;
-    I.halvings = 0;
-    I.flags = 0u;
-    I.active = 1;
   }
   __syncthreads();
   count_active(inst, n, n_active);
@@ -245,6 +267,8 @@ __global__ void __launch_bounds__(kBlock) k_batch_decide(afi::BatchInst* inst, i
       I.steps += 1;
       I.cur = (I.cur + 1) % 3;
       I.active = 0;
+      // the accepted last stage left the new state's CFL maxima
+      if (I.stage_nwg > 0) I.cfl_nb = I.stage_nwg;
     } else if (I.halvings < I.max_halvings) {
       I.dt *= 0.5;
       I.halvings += 1;
@@ -300,6 +324,9 @@ size_t workspace_layout(const Geo& g, Work* w, char* base) {
   if (g.dim == 2) {
     r.blend = (float*)take(sizeof(float) * (nfx + nfy));
     r.mlp = (void*)take(kMlpPackedBytes);
+    r.binst = (BatchInst*)take(sizeof(BatchInst));
+    r.bpartial = (double*)take(2 * sizeof(double) * kSingleCflBlocks);
+    r.bnact = (int*)take(sizeof(int));
   }
   r.bytes = off;
   if (w) *w = r;
@@ -379,15 +406,15 @@ hipError_t count_inadmissible(const Geo& g, double gm1, const Work& w, const dou
   return hipGetLastError();
 }
 
-hipError_t batch_cfl(BatchInst* inst, int n, double* partial, hipStream_t s) {
-  hipLaunchKernelGGL(k_batch_cfl, dim3(kBatchCflBlocks, (unsigned)n), dim3(kBlock), 0, s, inst,
+hipError_t batch_cfl(BatchInst* inst, int n, double* partial, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_cfl, dim3((unsigned)nb, (unsigned)n), dim3(kBlock), 0, s, inst,
                      partial);
   return hipGetLastError();
 }
 
-hipError_t batch_open(BatchInst* inst, int n, const double* partial, int* n_active,
+hipError_t batch_open(BatchInst* inst, int n, const double* partial, int nb, int* n_active,
                       hipStream_t s) {
-  hipLaunchKernelGGL(k_batch_open, dim3(1), dim3(kBlock), 0, s, inst, n, partial, n_active);
+  hipLaunchKernelGGL(k_batch_open, dim3(1), dim3(kBlock), 0, s, inst, n, partial, nb, n_active);
   return hipGetLastError();
 }
 

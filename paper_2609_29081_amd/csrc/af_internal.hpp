@@ -66,12 +66,18 @@ struct BatchInst {
   double t_final;
   long max_steps;
   int max_halvings;
+  // a single instance whose last stage leaves the CFL maxima of the new
+  // state (af_run_graph): the number of its stage workgroups, else 0
+  int stage_nwg;
   // updated on the device
   double dt, t;
   long steps;
   int cur, active, halvings, status;
   unsigned flags;
   long attempts;  // RK3 attempts so far (accepted and rejected)
+  // partial CFL maxima the next step opens from: 0 for the CFL kernel's own
+  // count, else the number written by the last accepted stage
+  int cfl_nb;
 };
 
 
@@ -96,6 +102,11 @@ struct Work {
   // the inference kernel reads them (bfloat16 W1, W2, w3; FP32 biases)
   float* blend;
   void* mlp;
+  // 2D: one batch descriptor, its CFL partial maxima and active count, for
+  // the single instance's device-resident step loop (af_run_graph)
+  struct BatchInst* binst;
+  double* bpartial;
+  int* bnact;
   // host-side: the context's learned-blend network (device parameters), or NULL
   const float* net;
   size_t bytes;      // total
@@ -181,9 +192,12 @@ hipError_t count_inadmissible(const Geo& g, double gm1, const Work& w, const dou
 // may open a step (B blocks each); opening of steps (fresh CFL dt, active);
 // the decision after an attempt.  Both of the latter recount the active
 // instances into *n_active.
+// nb CFL blocks per instance: kBatchCflBlocks in a batch, kSingleCflBlocks
+// for the single instance of af_run_graph
 constexpr int kBatchCflBlocks = 32;
-hipError_t batch_cfl(BatchInst* inst, int n, double* partial, hipStream_t s);
-hipError_t batch_open(BatchInst* inst, int n, const double* partial, int* n_active,
+constexpr int kSingleCflBlocks = 1024;
+hipError_t batch_cfl(BatchInst* inst, int n, double* partial, int nb, hipStream_t s);
+hipError_t batch_open(BatchInst* inst, int n, const double* partial, int nb, int* n_active,
                       hipStream_t s);
 hipError_t batch_decide(BatchInst* inst, int n, int* n_active, hipStream_t s);
 // Compiled variants of the 2D stage (af_stage2d.hip, one object each): the
@@ -196,6 +210,13 @@ struct StageVariant {
                        double*, const double*, double, StageCoef, hipStream_t, Timer*);
   hipError_t (*batch)(BatchInst*, int, int, const int*, int, hipStream_t, Timer*);
   int (*tiles)(const Geo&);
+  // stage k of the current attempt of one instance whose step machinery is on
+  // the device (descriptor dinst): the single-instance kernel; its last stage
+  // writes the CFL maxima of the new state per workgroup into cfl_partial
+  // (stride kSingleCflBlocks); dev_nwg: its number of workgroups
+  hipError_t (*dev)(const Geo&, const afd::Phys&, BatchInst*, double* cfl_partial, int,
+                    hipStream_t);
+  int (*dev_nwg)(const Geo&);
 };
 // all variants; the first of each precision is its default
 extern const StageVariant kStageVariants[];

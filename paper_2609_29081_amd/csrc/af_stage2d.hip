@@ -515,6 +515,13 @@ struct StageArgs {
   afi::BatchInst* inst;
   int ninst, k;
   const int* n_active;
+  // one instance whose step machinery lives on the device (a single
+  // descriptor; stage k of its current attempt, nothing once it is
+  // inactive), or NULL: then Uk, Un, Uout, dt and flags above are used.
+  // Its last stage leaves the CFL maxima of the new state in cfl_partial
+  // (a at [wg], v at [kSingleCflBlocks + wg]), for the next step's dt
+  afi::BatchInst* dinst;
+  double* cfl_partial;
   // both
   double ca, cb;
   int first, skip_flagged, ntiles;
@@ -575,7 +582,9 @@ __device__ __forceinline__ TileArgs batch_tile(const StageArgs& sa, const int* t
 
 // BLEND: the single-instance kernel with per-face blend input/output arrays
 // (its own instance, so that the plain stage carries none of that code)
-template <typename R, bool BATCH, bool BLEND = false>
+// DEV: the single-instance kernel of a device-resident step loop, whose
+// buffers, dt and flag word come from the descriptor sa.dinst
+template <typename R, bool BATCH, bool BLEND = false, bool DEV = false>
 __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
   __shared__ Tile<R> T;
   __shared__ unsigned stop;  // workgroup-uniform copy of the flag word
@@ -583,6 +592,8 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
   const double ca = sa.ca, cb = sa.cb;
   const int first = sa.first, skip_flagged = sa.skip_flagged;
   bool nonfinite = false;
+  // DEV, last stage: CFL rate maxima of the cells this thread writes
+  double cfl_a = 0.0, cfl_v = 0.0;
   // a batch: only the tiles of its active instances are numbered, so that
   // every XCD band holds an equal share of the work whichever instances are
   // active (instances finish their steps after different numbers of
@@ -594,6 +605,17 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
   if constexpr (BATCH) {
     static_assert(kMaxBatch == NT, "one instance per thread in the scans");
     if (*sa.n_active == 0) return;  // every instance has finished its step
+  }
+  if (BATCH && sa.ninst == 1) {
+    // one instance, active (n_active is not 0): its tiles are all the tiles
+    if (tid == 0) {
+      bid[0] = 0;
+      bt0[0] = 0;
+    }
+    nact = 1;
+    ntiles = sa.inst[0].ntiles;
+    __syncthreads();
+  } else if constexpr (BATCH) {
     const bool act = tid < sa.ninst && sa.inst[tid].active;
     const int own = act ? sa.inst[tid].ntiles : 0;
     bid[tid] = act ? 1 : 0;
@@ -617,9 +639,28 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
     }
     __syncthreads();
   }
-  // the one instance's dt, read once (a per-tile read costs ~3% of the stage)
+  // the one instance's buffers, dt and flag word, read once (a per-tile read
+  // of dt costs ~3% of the stage)
   double dt1 = 0.0;
-  if constexpr (!BATCH) dt1 = sa.dt_dev ? *sa.dt_dev : sa.dt_host;
+  const double* Uk1 = nullptr;
+  const double* Un1 = nullptr;
+  double* Uout1 = nullptr;
+  unsigned* flags1 = nullptr;
+  if constexpr (!BATCH) {
+    if constexpr (DEV) {
+      const afi::BatchInst& I = *sa.dinst;
+      if (!I.active) return;  // its step is done; the round has nothing to do
+      // the three RK3 stages from buf[cur], through the other two buffers
+      const int c = I.cur, a = (c + 1) % 3, b = (c + 2) % 3;
+      Un1 = I.buf[c];
+      Uk1 = sa.k == 0 ? I.buf[c] : (sa.k == 1 ? I.buf[a] : I.buf[b]);
+      Uout1 = sa.k == 1 ? I.buf[b] : I.buf[a];
+      dt1 = I.dt;
+      flags1 = &sa.dinst->flags;
+    } else {
+      dt1 = sa.dt_dev ? *sa.dt_dev : sa.dt_host;
+    }
+  }
   // what tile t works on (built where used, from the kernel arguments or the
   // batch descriptors, so that nothing of it stays live across tiles)
   auto args = [&](int t) {
@@ -629,11 +670,11 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
       TileArgs A;
       A.g = &sa.g;
       A.phd = &sa.ph;
-      A.Uk = sa.Uk;
-      A.Un = sa.Un;
-      A.Uout = sa.Uout;
+      A.Uk = DEV ? Uk1 : sa.Uk;
+      A.Un = DEV ? Un1 : sa.Un;
+      A.Uout = DEV ? Uout1 : sa.Uout;
       A.dt = dt1;
-      A.flags = sa.flags;
+      A.flags = DEV ? flags1 : sa.flags;
       A.ntx = sa.ntx;
       A.lt = t;
       return A;
@@ -643,6 +684,9 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
   int tile = it.get();
   double pre[kRawPerThread][4];
   int flip[kRawPerThread] = {};
+  // a batch: whether pre holds the current tile's raw values (tiles of an
+  // instance whose attempt is rejected are passed over without loading them)
+  bool have_pre = true;
   if (tile >= 0) {
     const TileArgs A = args(tile);
     load_raw(*A.g, A.Uk, 2 * TX * (A.lt % A.ntx), 2 * TY * (A.lt / A.ntx), tid, pre, flip);
@@ -668,17 +712,22 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
   __syncthreads();  // the previous tile is done with the LDS; stop is visible
   if (stop) {
     if constexpr (BATCH) {
-      // every wave has read `stop` before thread 0 writes it for the next tile
+      // with one active instance every later tile is that instance's too
+      if (nact == 1) break;
+      // every wave has read `stop` before thread 0 writes it for the next
+      // tile, which is loaded only once it is known not to be skipped too
       __syncthreads();
-      const int nt = it.advance();
-      if (nt >= 0) {
-        const TileArgs An = args(nt);
-        load_raw(*An.g, An.Uk, 2 * TX * (An.lt % An.ntx), 2 * TY * (An.lt / An.ntx), tid, pre, flip);
-      }
-      tile = nt;
+      tile = it.advance();
+      have_pre = false;
       continue;
     } else {
       break;
+    }
+  }
+  if constexpr (BATCH) {
+    if (!have_pre) {
+      load_raw(g, Uk, X0, Y0, tid, pre, flip);
+      have_pre = true;
     }
   }
 
@@ -980,6 +1029,7 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) un[k] = Un[k * nc + gi];
       }
+      double o4[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const double dfx = double(T.FX[k][jj * (TX + 1) + ii + 1]) - double(T.FX[k][jj * (TX + 1) + ii]);
@@ -993,6 +1043,18 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
         const double o = first ? fe : ca * un[k] + cb * fe;
         if (!isfinite(o)) nonfinite = true;
         Uout[k * nc + gi] = o;
+        o4[k] = o;
+      }
+      if constexpr (DEV) {
+        // the last stage of a device-resident step: the CFL rates (eq. cfl)
+        // of the new average, as the CFL kernel takes them, for the next step
+        if (sa.k == 2) {
+          const double p = pressure2(o4[0], o4[1], o4[2], o4[3], phd.gm1);
+          const double cs = sqrt(phd.gam * p / o4[0]);
+          cfl_a = mx(cfl_a, (fabs(o4[1] / o4[0]) + cs) * sa.dinst->icx);
+          cfl_a = mx(cfl_a, (fabs(o4[2] / o4[0]) + cs) * sa.dinst->icy);
+          cfl_v = mx(cfl_v, sa.dinst->vcoef / o4[0]);
+        }
       }
     }
   }
@@ -1150,7 +1212,34 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
   tile = next;
   }  // tiles
   if constexpr (!BATCH) {
-    if (nonfinite) raise_flag(sa.flags, FLAG_NONFINITE);
+    if (nonfinite) raise_flag(DEV ? flags1 : sa.flags, FLAG_NONFINITE);
+  }
+  if constexpr (DEV) {
+    // the workgroup's CFL maxima of the new state, one pair per workgroup
+    // (rates of cells this workgroup did not write are 0, neutral for max)
+    if (sa.k == 2) {
+      __shared__ double cfl_w[2][NT / 64];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        cfl_a = mx(cfl_a, __shfl_xor(cfl_a, o, 64));
+        cfl_v = mx(cfl_v, __shfl_xor(cfl_v, o, 64));
+      }
+      __syncthreads();
+      if ((tid & 63) == 0) {
+        cfl_w[0][tid >> 6] = cfl_a;
+        cfl_w[1][tid >> 6] = cfl_v;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        double a = 0.0, v = 0.0;
+        for (int w = 0; w < NT / 64; ++w) {
+          a = mx(a, cfl_w[0][w]);
+          v = mx(v, cfl_w[1][w]);
+        }
+        sa.cfl_partial[blockIdx.x] = a;
+        sa.cfl_partial[afi::kSingleCflBlocks + blockIdx.x] = v;
+      }
+    }
   }
 }
 
@@ -1212,6 +1301,33 @@ hipError_t launch(const G2& g, const Phys& ph, const afi::Work& w, const double*
   return hipGetLastError();
 }
 
+// stage k of the current attempt of the one instance whose descriptor is
+// dinst (the device-resident step loop of af_run_graph): the single-instance
+// kernel, with its buffers, dt and flags read from the descriptor
+template <typename R>
+hipError_t launch_dev(const G2& g, const Phys& ph, afi::BatchInst* dinst, double* cfl_partial,
+                      int k, hipStream_t s) {
+  const int ntx = g.n1 / TX + 1, nty = g.n2 / TY + 1;
+  const int ntiles = ntx * nty;
+  int nwg = resident_workgroups<R>();
+  if (nwg > ntiles) nwg = ntiles;
+  if (nwg >= 8) nwg -= nwg % 8;
+  StageArgs sa{};
+  sa.g = g;
+  sa.ph = ph;
+  sa.dinst = dinst;
+  sa.cfl_partial = cfl_partial;
+  sa.k = k;
+  sa.ntx = ntx;
+  sa.ca = k == 0 ? 0.0 : (k == 1 ? 0.75 : 1.0 / 3.0);
+  sa.cb = k == 0 ? 1.0 : (k == 1 ? 0.25 : 2.0 / 3.0);
+  sa.first = k == 0;
+  sa.skip_flagged = 1;
+  sa.ntiles = ntiles;
+  hipLaunchKernelGGL((k_stage<R, false, false, true>), dim3((unsigned)nwg), dim3(NT), 0, s, sa);
+  return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_batch(afi::BatchInst* inst, int ninst, int total_tiles, const int* n_active,
                         int k, hipStream_t s, afi::Timer* tm) {
@@ -1246,6 +1362,21 @@ hipError_t AF_STAGE_ENTRY(const Geo& geo, const Phys& ph, const Work& w, const d
 
 // tiles of one 2D grid for this instance's tile shape
 int AF_STAGE_TILES(const Geo& geo) { return (geo.n1 / TX + 1) * (geo.n2 / TY + 1); }
+
+// stage k of the current attempt of the single instance described at dinst
+hipError_t AF_CAT(AF_STAGE_ENTRY, _dev)(const Geo& geo, const Phys& ph, BatchInst* dinst,
+                                        double* cfl_partial, int k, hipStream_t s) {
+  return launch_dev<AF_STAGE_REAL>(afi::stage_geo(geo), ph, dinst, cfl_partial, k, s);
+}
+
+// workgroups of a single-instance stage launch of grid geo
+int AF_CAT(AF_STAGE_ENTRY, _nwg)(const Geo& geo) {
+  const int ntiles = AF_STAGE_TILES(geo);
+  int nwg = resident_workgroups<AF_STAGE_REAL>();
+  if (nwg > ntiles) nwg = ntiles;
+  if (nwg >= 8) nwg -= nwg % 8;
+  return nwg;
+}
 
 // stage k of a step attempt of every active instance of a batch, one launch
 hipError_t AF_STAGE_BATCH(BatchInst* inst, int ninst, int total_tiles, const int* n_active, int k,

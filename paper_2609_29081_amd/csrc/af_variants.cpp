@@ -10,6 +10,8 @@ namespace afi {
   hipError_t name(const Geo&, const afd::Phys&, const Work&, const double*, const double*,    \
                   double*, const double*, double, StageCoef, hipStream_t, Timer*);            \
   hipError_t name##_batch(BatchInst*, int, int, const int*, int, hipStream_t, Timer*);        \
+  hipError_t name##_dev(const Geo&, const afd::Phys&, BatchInst*, double*, int, hipStream_t); \
+  int name##_nwg(const Geo&);                                                                 \
   int name##_tiles(const Geo&);
 
 AF_DECLARE_VARIANT(stage2d_fp64_t7)
@@ -18,7 +20,8 @@ AF_DECLARE_VARIANT(stage2d_mixed_t10)
 AF_DECLARE_VARIANT(stage2d_mixed_t7)
 AF_DECLARE_VARIANT(stage2d_mixed_t14)
 
-#define AF_VARIANT(name, mixed, ty) {#name, mixed, ty, name, name##_batch, name##_tiles}
+#define AF_VARIANT(name, mixed, ty) \
+  {#name, mixed, ty, name, name##_batch, name##_tiles, name##_dev, name##_nwg}
 
 const StageVariant kStageVariants[] = {
     AF_VARIANT(stage2d_fp64_t7, 0, 7),    AF_VARIANT(stage2d_fp64_t5, 0, 5),
