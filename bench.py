@@ -111,8 +111,10 @@ def main() -> int:
                     help="markdown file for the whole-run summary")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-blend form")
-    ap.add_argument("--learned-train-steps", type=int, default=20000,
+    ap.add_argument("--learned-train-steps", type=int, default=30000,
                     help="Adam steps of the learned blend's training")
+    ap.add_argument("--learned-rows", type=int, default=2000000,
+                    help="training rows of the learned blend")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -553,19 +555,26 @@ def cpu_baseline(args, g, kw, U0, S, dev_U0, K, dof_sites):
 
 
 def learned_form(args, stream) -> dict:
-    """The learned-blend form.  Training data: features and theta^s of every
-    face of the 1000 x 500 shock tube (FP64, plain limiter) after steps 1,
-    2, 3, 5, 10, 20 and 50 (7.0 M faces; the first steps, where the
-    diaphragm's jump turns into a viscous shock, are where the blend acts
-    most; a tenth held out, the rest balanced by workloads.balanced_rows); training: Adam (lr 2e-3, minibatches of 1024)
-    from the seeded initial weights.  Evaluation on the 2048 x 1024 shock tube
-    (FP64, Re = 200) from t = 0 to t = 1e-4: the plain limiter, the learned
-    blend (AF_LIM_LEARNED: the network's theta_nn in place of theta^s, then
-    the density/pressure limiter), the untrained network, and no smoothness
-    blend at all (theta^s = 1).  Each run is
-    timed with HIP events; value = DOF sites x 3 x accepted steps / second.
-    The plain limiter judges the error: L1 = sum |rho - rho_plain| dx dy of
-    the cell averages at t = 1e-4."""
+    """The learned-blend form.
+
+    Training data: features and theta^s of every face of the 1000 x 500
+    shock tube (FP64, plain limiter) after steps 1, 2, 3, 5, 10, 20, 50,
+    100, 200 and 400 (10.0 M faces; the first steps, where the diaphragm's
+    jump turns into a viscous shock, are where the blend acts most); a tenth
+    held out; from the rest a training set of --learned-rows rows (every
+    face with theta^s < 0.999 and random others, workloads.balanced_rows).
+    Training: Adam (lr 2e-3, minibatches of 1024) from the seeded initial
+    weights.
+
+    Evaluation, each run timed with HIP events (value = DOF sites x 3 x
+    accepted steps / second):
+    * equal error: the 500 x 250 tube from t = 0 to t = 1e-3 with the plain
+      limiter, the learned blend, the untrained network and no smoothness
+      blend, each with its L1 density error against the plain 1000 x 500 run
+      averaged onto the 500 x 250 cells (2 x 2 cell averages are exact);
+    * the 2048 x 1024 tube from t = 0 to t = 1e-4 and the 1000 x 500 tube to
+      the same time, with the L1 density distance of each form from the
+      plain run of its grid."""
     import numpy as np
     import torch
 
@@ -581,8 +590,9 @@ def learned_form(args, stream) -> dict:
     U = S3.to_device(W.make_state(g3, f3, gamma))
     Xs, ys, done = [], [], 0
     tmp = torch.empty_like(U)
-    for target in (1, 2, 3, 5, 10, 20, 50):
-        st, n, _ = S3.af_run(U, 0.0, 1e30, target - done, check_every=1)
+    snaps = (1, 2, 3, 5, 10, 20, 50, 100, 200, 400)
+    for target in snaps:
+        st, n, _, _ = S3.af_run_graph(U, 0.0, 1e30, target - done)
         if st != af.AF_OK:
             raise RuntimeError(f"training-data run failed: {st}")
         done = target
@@ -590,15 +600,18 @@ def learned_form(args, stream) -> dict:
         ts = torch.empty(S3.face_count, dtype=torch.float32, device=dev)
         S3.af_rk_stage_blend(0, None, U, tmp, dt=0.0, theta_s_out=ts)
         ys.append(ts)
+    del S3, U, tmp
     X, y = torch.cat(Xs), torch.cat(ys)
-    # a held-out tenth of the faces; the training rows are every face of the
-    # rest where theta^s < 0.999 and three times as many of the others
+    del Xs, ys
+    # a held-out tenth of the faces; the training rows come from the rest
     perm = torch.randperm(X.shape[0], generator=torch.Generator().manual_seed(0)).to(dev)
     X, y = X[perm].contiguous(), y[perm].contiguous()
     nhold = X.shape[0] // 10
-    Xh, yh = X[:nhold], y[:nhold]
-    idx = torch.as_tensor(W.balanced_rows(y[nhold:].cpu().numpy(), seed=0), device=dev) + nhold
+    Xh, yh = X[:nhold].contiguous(), y[:nhold].contiguous()
+    idx = torch.as_tensor(W.balanced_rows(y[nhold:].cpu().numpy(), seed=0,
+                                          total=args.learned_rows), device=dev) + nhold
     Xt, yt = X[idx].contiguous(), y[idx].contiguous()
+    del X, y
     P0 = torch.as_tensor(W.mlp_init(0), device=dev)
     P = P0.clone()
     m, v = torch.zeros_like(P), torch.zeros_like(P)
@@ -614,15 +627,19 @@ def learned_form(args, stream) -> dict:
     _, l_low = af.mlp_grad(Xh[low].contiguous(), yh[low].contiguous(), P)
     rmse_low = float(l_low.item()) ** 0.5
     rmse_one = float(((1.0 - yh[low]) ** 2).mean().item()) ** 0.5
+    ntrain = int(Xt.shape[0])
+    del Xt, yt, Xh, yh
 
-    t_final = 1e-4
+    forms = (("plain", af.LIM_ALL, None),
+             ("learned", af.LIM_ALL | af.LIM_LEARNED, P),
+             ("untrained", af.LIM_ALL | af.LIM_LEARNED, P0),
+             ("no_smoothness", af.LIM_PP | af.LIM_POINT | af.LIM_CENTRE, None))
 
-    def evaluate(gg, UU):
+    def evaluate(gg, UU, t_final, names=None):
         runs = {}
-        for name, lim, net in (("plain", af.LIM_ALL, None),
-                               ("learned", af.LIM_ALL | af.LIM_LEARNED, P),
-                               ("untrained", af.LIM_ALL | af.LIM_LEARNED, P0),
-                               ("no_smoothness", af.LIM_PP | af.LIM_POINT | af.LIM_CENTRE, None)):
+        for name, lim, net in forms:
+            if names and name not in names:
+                continue
             S = af.Solver(gg, limiter=lim, **kw)
             if net is not None:
                 S.af_set_blend_net(net)
@@ -631,6 +648,8 @@ def learned_form(args, stream) -> dict:
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
+            # the learned blend needs the host-decided loop (its inference
+            # runs before each stage)
             st, n, t = S.af_run(Ud, 0.0, t_final, 10 ** 6, check_every=1)
             e1.record(stream)
             torch.cuda.synchronize()
@@ -641,26 +660,40 @@ def learned_form(args, stream) -> dict:
             del S, Ud
         return runs
 
-    print("bench: learned blend, 2048x1024 runs", file=sys.stderr, flush=True)
-    g5, f5 = W.shock_tube_2d(2048, 1024, gamma=gamma)
-    runs = evaluate(g5, W.make_state(g5, f5, gamma))
-    rho_plain = runs["plain"][0]
-    out = {"workload": "2D viscous shock tube 2048x1024 (Re=200, FP64) from t=0 to t=1e-4; "
-                       "network trained on theta^s of the 1000x500 tube after steps "
-                       "1, 2, 3, 5, 10, 20, 50",
-           "train": {"samples": int(Xt.shape[0]), "held_out": nhold, "steps": args.learned_train_steps,
+    out = {"workload": "2D viscous shock tube (Re=200, FP64), plain limiter against the learned "
+                       "blend; network trained on theta^s of the 1000x500 tube after steps "
+                       + ", ".join(str(k) for k in snaps),
+           "train": {"samples": ntrain, "held_out": nhold, "steps": args.learned_train_steps,
                      "batch": 1024, "lr": 2e-3, "seconds": round(train_s, 2),
                      "loss_held_out_before": float(l0.item()),
                      "loss_held_out_after": float(l1.item()),
                      "fraction_theta_s_below_1": round(frac_lt1, 4),
                      "rmse_held_out_where_theta_s_below_1": round(rmse_low, 5),
                      "rmse_of_constant_1_there": round(rmse_one, 5)}}
+    # equal error: 500 x 250 against the plain 1000 x 500 run averaged onto it
+    print("bench: learned blend, equal-error runs", file=sys.stderr, flush=True)
+    te = 1e-3
+    ref_runs = evaluate(g3, W.make_state(g3, f3, gamma), te, names=("plain",))
+    rho_f = ref_runs["plain"][0]
+    rho_ref = 0.25 * (rho_f[0::2, 0::2] + rho_f[1::2, 0::2] + rho_f[0::2, 1::2] + rho_f[1::2, 1::2])
+    gc, fc = W.shock_tube_2d(500, 250, gamma=gamma)
+    runs_c = evaluate(gc, W.make_state(gc, fc, gamma), te)
+    eq = {"grid": "500x250", "t": te, "reference": "plain 1000x500 run, 2x2 cell averages"}
+    for name, (rho, n, ms) in runs_c.items():
+        eq[name] = {"value": gc.dof_sites * 3 * n / (ms / 1e3), "steps": n, "ms": round(ms, 1),
+                    "l1_rho_err": float(np.abs(rho - rho_ref).sum() * gc.dx * gc.dy)}
+    out["equal_error"] = eq
+    print("bench: learned blend, 2048x1024 runs", file=sys.stderr, flush=True)
+    t_final = 1e-4
+    g5, f5 = W.shock_tube_2d(2048, 1024, gamma=gamma)
+    runs = evaluate(g5, W.make_state(g5, f5, gamma), t_final)
+    rho_plain = runs["plain"][0]
     for name, (rho, n, ms) in runs.items():
         out[name] = {"value": g5.dof_sites * 3 * n / (ms / 1e3), "unit": "DOF-updates/s",
                      "steps": n, "ms": round(ms, 1),
                      "l1_rho_vs_plain": float(np.abs(rho - rho_plain).sum() * g5.dx * g5.dy)}
     # the same comparison at the training grid (1000 x 500, to the same t)
-    runs3 = evaluate(g3, W.make_state(g3, f3, gamma))
+    runs3 = evaluate(g3, W.make_state(g3, f3, gamma), t_final)
     out["at_1000x500"] = {name: {"steps": n, "l1_rho_vs_plain": float(
         np.abs(rho - runs3["plain"][0]).sum() * g3.dx * g3.dy)} for name, (rho, n, ms) in runs3.items()}
     out["value"] = out["learned"]["value"]

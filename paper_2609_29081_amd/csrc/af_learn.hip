@@ -22,7 +22,7 @@
 // theta_nn = min(max(z, 0), 1); parameters as one FP32 vector
 // [W1 (64 x 40, row-major), b1, W2 (64 x 64), b2, w3, b3].  Inference keeps
 // W1, W2, w3 and the layer inputs x, h1 in bfloat16 (round to nearest even)
-// and accumulates in FP32 (MFMA 32x32x8 bf16); training runs in FP32.
+// and accumulates in FP32 (MFMA 32x32x16 bf16); training runs in FP32.
 #include "af_device.hpp"
 #include "af_internal.hpp"
 #include "af_lattice.hpp"
@@ -165,32 +165,48 @@ __global__ void __launch_bounds__(256) k_features(G2 g, double gm1, float gam,
 // ---------------------------------------------------------------------------
 // inference.  A workgroup (four wave64s) takes 128 consecutive faces of one
 // row of one direction: it stages the primitives of their stencil cells in
-// LDS, writes the features as bfloat16, and each wave runs the network on
-// 32 faces with MFMA 32x32x8 bf16 (A: faces x inputs from LDS, B: weights
-// held in registers for the whole kernel).
+// LDS and writes the features as bfloat16 rows; each wave then runs the
+// network on 32 faces with MFMA 32x32x16 bf16 in the transposed form
+// H^T = W X^T: the weights are the A operand (units x inputs, in registers),
+// the faces the columns.  A 32 x 32 accumulator holds in lane (face c, half
+// h) the rows (units) 8 (r/4) + 4 h + r%4 of column c, r = 0..15, and the B
+// operand of the next layer needs in that lane the inputs 16 kb + 8 h + e,
+// e = 0..7, of the same face: registers 8q .. 8q+7 of the accumulator of
+// unit block nb are exactly that for kb = 2 nb + q, once the hidden units are
+// numbered in that (virtual) order, which is how layer 2's weights are
+// stored.  So hidden values never leave the registers, and the output layer's
+// sum over units ends with one exchange between the two halves of the wave.
 // ---------------------------------------------------------------------------
 constexpr int IB = 128;                 // faces per block
-constexpr int IPAD = 8;                 // bf16 padding of LDS rows
-constexpr int FROW = NIN + IPAD;        // feature row (bf16)
-constexpr int HROW = NH + IPAD;         // hidden row (bf16)
+constexpr int KIN = 48;                 // inputs padded to three K steps of 16
+constexpr int FROW = KIN + 8;           // feature row (bf16; 16-byte aligned)
 constexpr int CW = IB + 4;              // stencil cells per row
-constexpr int RROW = 33;                // FP32 row of the output reduction
-constexpr int W2ROW = NH + 4;           // padded LDS row of W2 (no bank conflicts)
-static_assert(32 * RROW * 4 <= 32 * HROW * 2, "the reduction fits a wave's hidden rows");
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 struct InferShared {
   float cell[4][4][CW];                 // [component][row][column]
   unsigned short feat[IB * FROW];
-  unsigned short hid[IB * HROW];
-  unsigned short w2[NH * W2ROW];        // layer-2 weights (bfloat16, padded rows)
+  float b1[NH], b2[NH], w3[NH];         // biases, and the output weights (bf16 values)
+  // layer 2's A operands, per lane (in LDS rather than registers: with them
+  // in registers the kernel holds 188 VGPRs, two waves per SIMD, and ran 18 %
+  // slower at 2048 x 1024)
+  bf16x8 a2[2][4][64];
 };
 
-// four consecutive bfloat16 values, 8-byte aligned (one 64-bit load)
-__device__ __forceinline__ bf16x4 load4(const unsigned short* p) {
-  return *reinterpret_cast<const bf16x4*>(p);
+__device__ __forceinline__ bf16x8 bf16x8_of(const unsigned short* p, int n) {
+  bf16x8 v;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) v[e] = __builtin_bit_cast(__bf16, e < n ? p[e] : (unsigned short)0);
+  return v;
+}
+
+// unit of layer-2 input (virtual) index k, for the half h of the lanes that
+// holds it: kb = k / 16 = 2 nb + q, e = k % 8 = 4 a + i (see above)
+__device__ __forceinline__ int hidden_unit(int kb, int h, int e) {
+  const int nb = kb >> 1, q = kb & 1, a = e >> 2, i = e & 3;
+  return 32 * nb + 8 * (2 * q + a) + 4 * h + i;
 }
 
 __global__ void __launch_bounds__(256) k_infer(G2 g, double gm1, float gam,
@@ -207,23 +223,30 @@ __global__ void __launch_bounds__(256) k_infer(G2 g, double gm1, float gam,
   const float* b1 = (const float*)(pk + PK_B1);
   const float* b2 = (const float*)(pk + PK_B2);
   const float b3 = *(const float*)(pk + PK_B3);
-  // B operands: lane holds W[n = 32 nb + c32][k = 8 kb + 4 h + 0..3]
-  // W1 stays in registers (20 VGPRs); W2 is read from LDS per use, which
-  // keeps the kernel at three waves per SIMD
-  bf16x4 B1[5][2];
-#pragma unroll
-  for (int kb = 0; kb < 5; ++kb)
-#pragma unroll
-    for (int nb = 0; nb < 2; ++nb) B1[kb][nb] = load4(W1 + (32 * nb + c32) * NIN + 8 * kb + 4 * h);
-  for (int e = tid; e < NH * NH / 4; e += 256)
-    *reinterpret_cast<bf16x4*>(S.w2 + (e / (NH / 4)) * W2ROW + 4 * (e % (NH / 4))) =
-        reinterpret_cast<const bf16x4*>(W2)[e];
-  float bias1[2], bias2[2], ow[2];
+  // A operands: lane (m = c32, h) holds row 32 nb + m, inputs 16 kb + 8 h + e
+  // (layer 2's written to LDS by the first wave, read after the first barrier)
+  bf16x8 A1[2][3];
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) {
-    bias1[nb] = b1[32 * nb + c32];
-    bias2[nb] = b2[32 * nb + c32];
-    ow[nb] = from_bf16(w3[32 * nb + c32]);
+#pragma unroll
+    for (int kb = 0; kb < 3; ++kb) {
+      const int k0 = 16 * kb + 8 * h;
+      A1[nb][kb] = bf16x8_of(W1 + (32 * nb + c32) * NIN + (k0 < NIN ? k0 : 0),
+                             k0 < NIN ? NIN - k0 : 0);
+    }
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+      bf16x8 v;
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        v[e] = __builtin_bit_cast(__bf16, W2[(32 * nb + c32) * NH + hidden_unit(kb, h, e)]);
+      if (wave == 0) S.a2[nb][kb][lane] = v;
+    }
+  }
+  for (int e = tid; e < NH; e += 256) {
+    S.b1[e] = b1[e];
+    S.b2[e] = b2[e];
+    S.w3[e] = from_bf16(w3[e]);
   }
   const long nfx = (long)g.n2 * (g.n1 + 1);
   const long nbx = (long)g.n2 * nsegx;
@@ -284,7 +307,8 @@ __global__ void __launch_bounds__(256) k_infer(G2 g, double gm1, float gam,
     }
     __syncthreads();
     {
-      // two threads per face, one half of its features each
+      // two threads per face, one half of its features each; inputs 40..47
+      // are zero
       const int fl = tid & (IB - 1), half = tid / IB;
       unsigned short* fo = S.feat + fl * FROW;
       if (fl < cnt) {
@@ -300,70 +324,66 @@ __global__ void __launch_bounds__(256) k_infer(G2 g, double gm1, float gam,
       } else {
         for (int n = half; n < NIN; n += 2) fo[n] = 0;
       }
+#pragma unroll
+      for (int n = 0; n < 4; ++n) fo[NIN + 4 * half + n] = 0;
     }
     __syncthreads();
     if (blk + gridDim.x < nblocks) fetch(block_of(blk + gridDim.x));
-    // the wave's 32 faces
-    const unsigned short* fa = S.feat + (32 * wave) * FROW;
-    unsigned short* hw = S.hid + (32 * wave) * HROW;
+    // the wave's 32 faces: lane (c32, h) works on face 32 wave + c32
+    const unsigned short* fa = S.feat + (32 * wave + c32) * FROW;
     f32x16 acc[2];
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[nb][r] = 0.0f;
 #pragma unroll
-    for (int kb = 0; kb < 5; ++kb) {
-      const bf16x4 a = load4(fa + c32 * FROW + 8 * kb + 4 * h);
+    for (int kb = 0; kb < 3; ++kb) {
+      const bf16x8 x = *reinterpret_cast<const bf16x8*>(fa + 16 * kb + 8 * h);
 #pragma unroll
       for (int nb = 0; nb < 2; ++nb)
-        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, B1[kb][nb], acc[nb], 0, 0, 0);
+        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1[nb][kb], x, acc[nb], 0, 0, 0);
     }
-    // h1 = tanh(.) as bfloat16 rows of the next layer's A operand; D element
-    // r of this lane is row 8 (r/4) + 4 h + r%4, column 32 nb + c32
+    // h1 = tanh(W1 x + b1) in bfloat16: layer 2's B operand, kb = 2 nb + q
+    bf16x8 hb[4];
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int m = 8 * (r >> 2) + 4 * h + (r & 3);
-        hw[m * HROW + 32 * nb + c32] = to_bf16(tanh_fast(acc[nb][r] + bias1[nb]));
+      for (int j = 0; j < 4; ++j) {
+        const float4 bias = *reinterpret_cast<const float4*>(&S.b1[32 * nb + 8 * j + 4 * h]);
+        const float bj[4] = {bias.x, bias.y, bias.z, bias.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          hb[2 * nb + (j >> 1)][4 * (j & 1) + i] = (__bf16)tanh_fast(acc[nb][4 * j + i] + bj[i]);
       }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[nb][r] = 0.0f;
 #pragma unroll
-    for (int kb = 0; kb < 8; ++kb) {
-      const bf16x4 a = load4(hw + c32 * HROW + 8 * kb + 4 * h);
+    for (int kb = 0; kb < 4; ++kb)
 #pragma unroll
       for (int nb = 0; nb < 2; ++nb)
-        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(
-            a, load4(S.w2 + (32 * nb + c32) * W2ROW + 8 * kb + 4 * h), acc[nb], 0, 0, 0);
-    }
-    // z = w3 . tanh(.) + b3: each lane sums its two columns of its 16 rows
-    // into an FP32 table in the wave's (now consumed) hidden rows, then lane
-    // m < 32 adds up row m
-    float* red = reinterpret_cast<float*>(hw);  // [32][RROW]
+        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(S.a2[nb][kb][lane], hb[kb], acc[nb], 0, 0, 0);
+    // z = w3 . tanh(W2 h1 + b2) + b3: this lane's 32 units of its face, then
+    // the other half's 32 from the lane 32 away
+    float z = 0.0f;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int m = 8 * (r >> 2) + 4 * h + (r & 3);
-      red[m * RROW + c32] =
-          ow[0] * tanh_fast(acc[0][r] + bias2[0]) + ow[1] * tanh_fast(acc[1][r] + bias2[1]);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    if (h == 0) {
-      float z = b3;
+    for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
-      for (int k = 0; k < 32; ++k) z += red[c32 * RROW + k];
-      const int m = 32 * wave + c32;
-      if (m < cnt) {
-        const long f = (d == 0 ? 0 : nfx) + (long)row * (d == 0 ? g.n1 + 1 : g.n1) + i0 + m;
-        theta[f] = fminf(fmaxf(z, 0.0f), 1.0f);
+      for (int j = 0; j < 4; ++j) {
+        const int u = 32 * nb + 8 * j + 4 * h;
+        const float4 bias = *reinterpret_cast<const float4*>(&S.b2[u]);
+        const float4 ow = *reinterpret_cast<const float4*>(&S.w3[u]);
+        z += ow.x * tanh_fast(acc[nb][4 * j] + bias.x);
+        z += ow.y * tanh_fast(acc[nb][4 * j + 1] + bias.y);
+        z += ow.z * tanh_fast(acc[nb][4 * j + 2] + bias.z);
+        z += ow.w * tanh_fast(acc[nb][4 * j + 3] + bias.w);
       }
+    z += __shfl_xor(z, 32, 64);
+    const int m = 32 * wave + c32;
+    if (h == 0 && m < cnt) {
+      const long f = (d == 0 ? 0 : nfx) + (long)row * (d == 0 ? g.n1 + 1 : g.n1) + i0 + m;
+      theta[f] = fminf(fmaxf(z + b3, 0.0f), 1.0f);
     }
   }
 }

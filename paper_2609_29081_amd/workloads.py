@@ -233,17 +233,22 @@ def mlp_init(seed: int = 0, nin: int = 40, nh: int = 64) -> np.ndarray:
     return np.concatenate(parts).astype(np.float32)
 
 
-def balanced_rows(y: np.ndarray, seed: int = 0, ratio: float = 3.0, below: float = 0.999) -> np.ndarray:
+def balanced_rows(y: np.ndarray, seed: int = 0, ratio: float = 3.0, below: float = 0.999,
+                  total: int = 0) -> np.ndarray:
     """Row indices of a training set for the blend network: every row whose
     target is below `below` (the faces where the smoothness blend acts, a
     few per cent of a shock-tube grid) and `ratio` times as many of the
-    other rows, drawn without replacement from default_rng(seed), in a
-    shuffled order."""
+    other rows -- or, with total > 0, as many of the others as make `total`
+    rows in all (at least `ratio` times as many when there are enough) --
+    drawn without replacement from default_rng(seed), in a shuffled order."""
     rng = np.random.default_rng(seed)
     y = np.asarray(y)
     lo = np.flatnonzero(y < below)
     hi = np.flatnonzero(~(y < below))
-    k = min(len(hi), int(ratio * max(len(lo), 1)))
+    k = int(ratio * max(len(lo), 1))
+    if total > 0:
+        k = max(k, total - len(lo))
+    k = min(len(hi), k)
     idx = np.concatenate([lo, rng.choice(hi, size=k, replace=False)])
     return idx[rng.permutation(len(idx))]
 
