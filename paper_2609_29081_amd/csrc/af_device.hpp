@@ -51,14 +51,18 @@ __device__ __forceinline__ double rcp<double>(double x) {
 }
 
 // NaN-propagating max/min: an inadmissible state anywhere in a stencil must
-// make the stage non-finite (and raise the flag), never be skipped
+// make the stage non-finite (and raise the flag), never be skipped.  The
+// hardware max/min returns the other operand for a NaN one; 0 * (a + b) is 0
+// for finite operands and NaN otherwise, and adding it leaves the exact
+// max/min of finite operands unchanged (three instructions, against six for
+// the compares and selects of the plain rule)
 template <typename R>
 __device__ __forceinline__ R mx(R a, R b) {
-  return (a != a || b != b) ? a + b : (a > b ? a : b);
+  return fma(R(0.0), a + b, fmax(a, b));
 }
 template <typename R>
 __device__ __forceinline__ R mn(R a, R b) {
-  return (a != a || b != b) ? a + b : (a < b ? a : b);
+  return fma(R(0.0), a + b, fmin(a, b));
 }
 
 // ---------------------------------------------------------------------------
@@ -193,6 +197,18 @@ __device__ __forceinline__ R bform(const R* a, const R* z) {
     s += a[m] * t;
   }
   return s;
+}
+
+// the quadratic form sum_m sum_n b_mn z_m z_n, from the symmetric part of B:
+// its twelve nonzero terms, grouped by the lower site index
+template <typename R>
+__device__ __forceinline__ R bquad(const R* z) {
+  const R t0 = R(-1.0 / 8.0) * z[0] + R(1.0 / 3.0) * z[1] - R(1.0 / 6.0) * z[2];
+  const R t1 = R(1.0 / 2.0) * z[1] - R(1.0 / 3.0) * z[2] + R(1.0 / 3.0) * z[3];
+  const R t2 = R(-3.0 / 4.0) * z[2] - R(1.0 / 3.0) * z[3] - R(1.0 / 6.0) * z[4];
+  const R t3 = R(1.0 / 2.0) * z[3] + R(1.0 / 3.0) * z[4];
+  const R t4 = R(-1.0 / 8.0) * z[4];
+  return z[0] * t0 + z[1] * t1 + z[2] * t2 + z[3] * t3 + z[4] * t4;
 }
 
 // sum_n (sum_m b_mn) z_n with column sums (-1/12, 4/3, -5/2, 4/3, -1/12)

@@ -21,7 +21,8 @@
 //   phase 5  point residual (biased inviscid operators with the downwind
 //            point, compact D^2, mixed terms; Sec. 2.2), point LLF on the
 //            lattice of point values and cell averages and the scaling limiter
-//            (Sec. 3.4), wall projection, RK combination
+//            (Sec. 3.4), wall projection, RK combination; two lanes per
+//            point, one per direction
 //
 // The kernel is a template over the arithmetic type R of the stencils, fluxes
 // and residuals (LDS included).  R = double is the FP64 stage.  R = float is
@@ -391,53 +392,141 @@ __device__ __forceinline__ void lo_site(Tile<R>& T, const PhysT<R>& ph, int lx, 
   }
 }
 
-// low-order point value U^L = U - sum_d (2 dt/h_d) (F^L(z, z+e_d) - F^L(z-e_d, z))
-// of the point at (lx, ly), with the LLF flux
+// direction-d part of the low-order point update of Sec. 3.4: the point at
+// (lx, ly) moves by U^L - U = -sum_d L_d with
+// L_d = (2 dt/h_d) (F^L(z, z+e_d) - F^L(z-e_d, z)) and the LLF flux
 // F^L(a, b) = (F_a + F_b)/2 - (max(|u_d|+c) + max(b_d))/2 (U_b - U_a),
-// from the site data of lo_site.  The update is subtracted from the FP64
-// point value U0d, so that U^L tends to it as dt does
+// from the site data of lo_site.  d is a lane value (lanes of one wave take
+// either direction)
 template <typename R>
-__device__ __forceinline__ void lo_point(const Tile<R>& T, int lx, int ly, double dx, double dy,
-                                         double dt, const double* U0d, double* UL) {
-  const R ihx = R(1.0 / dx), ihy = R(1.0 / dy);
+__device__ __forceinline__ void lo_point_dir(const Tile<R>& T, int lx, int ly, int d, double h,
+                                             double dt, R* L) {
   R U0[4], w0[5];
   lo_state(T, lx, ly, U0, w0);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) UL[k] = kFP64<R> ? double(U0[k]) : U0d[k];
   const int sx = lx - 3, sy = ly - 3;
+  const R* S = d ? &T.SY[0][0] : &T.SX[0][0];
+  const int n = d ? NSY : NSX;
+  const int o0 = d ? sy * (2 * TX) + sx - 1 : (sy - 1) * SW + sx;
+  const int st = d ? 2 * TX : 1;
+  const R F0[4] = {d ? U0[2] : U0[1], S[o0], S[n + o0], S[2 * n + o0]};
+  const R b0 = S[3 * n + o0];
+  const R r0 = fabs(d ? w0[1] : w0[0]) + w0[4];
+  R Fp[4];
 #pragma unroll
-  for (int d = 0; d < 2; ++d) {
-    const R* S = d == 0 ? &T.SX[0][0] : &T.SY[0][0];
-    const int n = d == 0 ? NSX : NSY;
-    const int o0 = d == 0 ? (sy - 1) * SW + sx : sy * (2 * TX) + sx - 1;
-    const int st = d == 0 ? 1 : 2 * TX;
-    const R F0[4] = {U0[1 + d], S[o0], S[n + o0], S[2 * n + o0]};
-    const R b0 = S[3 * n + o0];
-    const R r0 = fabs(w0[d]) + w0[4];
-    R Fp[4];
+  for (int sg = 1; sg >= -1; sg -= 2) {
+    const int nx = lx + (d ? 0 : sg), ny = ly + (d ? sg : 0);
+    const int on = o0 + sg * st;
+    R Un[4], wn[5];
+    lo_state(T, nx, ny, Un, wn);
+    const R Fn[4] = {d ? Un[2] : Un[1], S[on], S[n + on], S[2 * n + on]};
+    const R bn = S[3 * n + on];
+    const R lam = mx(r0, fabs(d ? wn[1] : wn[0]) + wn[4]) + mx(b0, bn);
+    if (sg == 1) {
 #pragma unroll
-    for (int sg = 1; sg >= -1; sg -= 2) {
-      const int nx = lx + (d == 0 ? sg : 0), ny = ly + (d == 1 ? sg : 0);
-      const int on = o0 + sg * st;
-      R Un[4], wn[5];
-      lo_state(T, nx, ny, Un, wn);
-      const R Fn[4] = {Un[1 + d], S[on], S[n + on], S[2 * n + on]};
-      const R bn = S[3 * n + on];
-      const R lam = mx(r0, fabs(wn[d]) + wn[4]) + mx(b0, bn);
-      if (sg == 1) {
+      for (int k = 0; k < 4; ++k)
+        Fp[k] = R(0.5) * (F0[k] + Fn[k]) - R(0.5) * lam * (Un[k] - U0[k]);
+    } else {
+      const R c = R(2.0 * dt / h);
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-          Fp[k] = R(0.5) * (F0[k] + Fn[k]) - R(0.5) * lam * (Un[k] - U0[k]);
-      } else {
-        const R c = R(2.0 * dt) * (d == 0 ? ihx : ihy);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const R Fm = R(0.5) * (Fn[k] + F0[k]) - R(0.5) * lam * (U0[k] - Un[k]);
-          UL[k] -= double(c * (Fp[k] - Fm));
-        }
+      for (int k = 0; k < 4; ++k) {
+        const R Fm = R(0.5) * (Fn[k] + F0[k]) - R(0.5) * lam * (U0[k] - Un[k]);
+        L[k] = c * (Fp[k] - Fm);
       }
     }
   }
+}
+
+// value of x in the other lane of this lane's pair (lanes 2m and 2m+1), by
+// a quad permutation (1, 0, 3, 2)
+__device__ __forceinline__ float pair_swap(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double pair_swap(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(v >> 32), 0xB1, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// direction-d terms of the residual of the point at LDS site a (block +- 2
+// index q), in components (rho, m_x, m_y, E): the biased inviscid operators
+// with the downwind point, written as D+(F+) + D-(F-) = D_c(F) + alpha/(6h)
+// times the fourth difference with alpha the max of |u_d| + c over the five
+// sites of the line; the compact D^{(d),2}(K_dd, Z); the mixed term
+// D_c^{(d)}(K_{d,o} D_c^{(o)} Z) with o the other direction (Sec. 2.2).  It
+// is computed in components (rho, m_d, m_o, E), m_d the momentum along d and
+// m_o the other, with a the velocity along d and b the other, so that both
+// directions run the same instructions (d may differ between the lanes of a
+// wave)
+template <typename R>
+__device__ __forceinline__ void point_resid_dir(const Tile<R>& T, const PhysT<R>& ph, int a, int q,
+                                                int d, double h, R* Rd) {
+  const int sa = d ? WA : 1, sq = d ? WG : 1;
+  const R i6h = R(1.0 / (6.0 * h));
+  const R* Md = T.U[1 + d];
+  const R* Mo = T.U[2 - d];
+  const R* Va = T.A[d];
+  const R* Vb = T.A[1 - d];
+  // derivatives across d of the velocity along d and of the other one
+  const R* Ga = T.G[d ? 1 : 3];
+  const R* Gb = T.G[d ? 0 : 4];
+  R alpha = R(0.0);
+#pragma unroll
+  for (int o = 0; o < 5; ++o) {
+    const int b = a + (o - 2) * sa;
+    alpha = mx(alpha, fabs(Va[b]) + T.A[4][b]);
+  }
+  R Rr[4];
+  // inviscid, one component at a time (short live ranges)
+  const R ai = alpha * i6h;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    R f[5], w[5];
+#pragma unroll
+    for (int o = 0; o < 5; ++o) {
+      const int b = a + (o - 2) * sa;
+      const R ud = Va[b], pb = T.A[2][b];
+      w[o] = k == 0 ? T.U[0][b] : (k == 1 ? Md[b] : (k == 2 ? Mo[b] : T.U[3][b]));
+      f[o] = k == 0 ? Md[b] : (k == 1 ? w[o] * ud + pb : (k == 2 ? w[o] * ud : (w[o] + pb) * ud));
+    }
+    Rr[k] = -(dc5(f[0], f[1], f[3], f[4], i6h) + ai * d4(w[0], w[1], w[2], w[3], w[4]));
+  }
+  R va[5], vb[5], Tt[5];
+#pragma unroll
+  for (int o = 0; o < 5; ++o) {
+    const int b = a + (o - 2) * sa;
+    va[o] = Va[b];
+    vb[o] = Vb[b];
+    Tt[o] = T.A[3][b];
+  }
+  // compact D^{(d),2}(K_dd, Z)
+  const R s4 = R(4.0 / (h * h));
+  const R mu = ph.mu, m43 = R(4.0 / 3.0) * ph.mu;
+  Rr[1] += s4 * m43 * bcol(va);
+  Rr[2] += s4 * mu * bcol(vb);
+  Rr[3] += s4 * (m43 * bquad(va) + mu * bquad(vb) + ph.kap * bcol(Tt));
+  // mixed
+  R m1[5], m2[5], m3[5];
+#pragma unroll
+  for (int o = 0; o < 5; ++o) {
+    if (o == 2) {
+      m1[o] = m2[o] = m3[o] = R(0.0);
+      continue;
+    }
+    const int qq = q + (o - 2) * sq;
+    const R ga = Ga[qq], gb = Gb[qq];
+    m1[o] = -R(2.0 / 3.0) * mu * gb;
+    m2[o] = mu * ga;
+    m3[o] = mu * (vb[o] * ga - R(2.0 / 3.0) * va[o] * gb);
+  }
+  Rr[1] += dc5(m1[0], m1[1], m1[3], m1[4], i6h);
+  Rr[2] += dc5(m2[0], m2[1], m2[3], m2[4], i6h);
+  Rr[3] += dc5(m3[0], m3[1], m3[3], m3[4], i6h);
+  // back to (rho, m_x, m_y, E)
+  Rd[0] = Rr[0];
+  Rd[1] = d ? Rr[2] : Rr[1];
+  Rd[2] = d ? Rr[1] : Rr[2];
+  Rd[3] = Rr[3];
 }
 
 // raw values of the lattice region of the tile at (X0, Y0): point sites hold
@@ -450,7 +539,25 @@ constexpr int kRawPerThread = (NA + NT - 1) / NT;
 __device__ __forceinline__ void load_raw(const G2& g, const double* __restrict__ Uk, int X0, int Y0,
                                          int tid, double (&pre)[kRawPerThread][4],
                                          int (&flip)[kRawPerThread]) {
-  const int Xlim = 2 * g.n1, Ylim = 2 * g.n2;
+  const int Xlim = 2 * __builtin_amdgcn_readfirstlane(g.n1);
+  const int Ylim = 2 * __builtin_amdgcn_readfirstlane(g.n2);
+  // a region inside the grid on both axes (no ghost site, no periodic seam):
+  // every site is read where it is, with no image map
+  if (X0 >= 4 && X0 - 4 + WA <= Xlim && Y0 >= 4 && Y0 - 4 + HA <= Ylim) {
+#pragma unroll
+    for (int r = 0; r < kRawPerThread; ++r) {
+      const int s = tid + r * NT;
+      if (s >= NA) continue;
+      flip[r] = 0;
+      long o;
+      int st;
+      site_ofs(g, X0 - 4 + s % WA, Y0 - 4 + s / WA, o, st);
+      const double* src = Uk + o;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) pre[r][k] = src[(long)k * st];
+    }
+    return;
+  }
 #pragma unroll
   for (int r = 0; r < kRawPerThread; ++r) {
     const int s = tid + r * NT;
@@ -1074,8 +1181,18 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
     __syncthreads();
   }
 
-  // ---- phase 5: point values (0 x-edge, 1 y-edge, 2 corner points) ----
-  for (int s = tid; s < NPT; s += NT) {
+  // ---- phase 5: point values (0 x-edge, 1 y-edge, 2 corner points).  The
+  //      FP64 stage gives each point two lanes: lane d of a pair takes the
+  //      direction-d terms of the residual and of the low-order point
+  //      update, the pair swaps them, and each lane finishes the point and
+  //      writes two of its four components (672 half-points spread over all
+  //      eight waves, where 336 whole points left two SIMDs with two waves
+  //      and two with one).  The FP32-stencil stage, whose tiles hold twice
+  //      the points, keeps one lane per point ----
+  constexpr int LPP = kFP64<R> ? 2 : 1;  // lanes per point
+  constexpr int NW = 4 / LPP;            // components a lane writes
+  for (int s2 = tid; s2 < LPP * NPT; s2 += NT) {
+    const int s = s2 / LPP, d = LPP == 2 ? (s2 & 1) : 0;
     const int t = s / (TX * TY), r = s % (TX * TY);
     const int ni = t == 1 ? g.n1 : g.n1x;
     const int nj = t == 0 ? g.n2 : g.n2y;
@@ -1083,94 +1200,35 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
     const long off = t == 0 ? g.off_xe : (t == 1 ? g.off_ye : g.off_co);
     {
       const int i = i0 + r % TX, j = j0 + r / TX;
+      // both lanes of a pair take this branch together
       if (i >= ni || j >= nj) continue;
       const int X = t == 1 ? 2 * i + 1 : 2 * i;
       const int Y = t == 0 ? 2 * j + 1 : 2 * j;
       const int a = (Y - Y0 + 4) * WA + (X - X0 + 4);
       const int q = (Y - Y0 + 2) * WG + (X - X0 + 2);
       const long gi = (long)j * ni + i;
-      // U^n for the RK combination, loaded while the residual is computed
-      double un[4] = {0.0, 0.0, 0.0, 0.0}, U0[4];
+      // U^n of the components this lane writes (NW * d onwards), loaded
+      // while the residual is computed
+      double un[NW];
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (!first) un[k] = Un[off + k * np + gi];
-      R Rs[4] = {R(0.0), R(0.0), R(0.0), R(0.0)};
+      for (int c = 0; c < NW; ++c) un[c] = first ? 0.0 : Un[off + (NW * d + c) * np + gi];
+      // the residual; the two directions' terms are added in the same order
+      // in both lanes of a pair
+      R Rs[4];
+      if constexpr (LPP == 2) {
+        R Rd[4];
+        point_resid_dir(T, ph, a, q, d, d ? g.dy : g.dx, Rd);
 #pragma unroll
-      for (int d = 0; d < 2; ++d) {
-        const int sa = d == 0 ? 1 : WA, sq = d == 0 ? 1 : WG;
-        const double h = d == 0 ? g.dx : g.dy;
-        const R i6h = R(1.0 / (6.0 * h));
-        // alpha: max of |u_d| + c over the five sites of the line
-        R alpha = R(0.0);
+        for (int k = 0; k < 4; ++k) Rs[k] = Rd[k] + pair_swap(Rd[k]);
+      } else {
+        R Rx[4], Ry[4];
+        point_resid_dir(T, ph, a, q, 0, g.dx, Rx);
+        point_resid_dir(T, ph, a, q, 1, g.dy, Ry);
 #pragma unroll
-        for (int o = 0; o < 5; ++o) {
-          const int b = a + (o - 2) * sa;
-          alpha = mx(alpha, fabs(T.A[d][b]) + T.A[4][b]);
-        }
-        // inviscid: D+(F+) + D-(F-) = D_c(F) + alpha/(6h) * fourth difference,
-        // one component at a time (short live ranges)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          R f[5], w[5];
-#pragma unroll
-          for (int o = 0; o < 5; ++o) {
-            const int b = a + (o - 2) * sa;
-            const R ud = T.A[d][b], pb = T.A[2][b];
-            w[o] = T.U[k][b];
-            f[o] = k == 0 ? T.U[1 + d][b]
-                          : (k == 3 ? (w[o] + pb) * ud : w[o] * ud + (k == 1 + d ? pb : R(0.0)));
-          }
-          Rs[k] -= dc5(f[0], f[1], f[3], f[4], i6h) + alpha * i6h * d4(w[0], w[1], w[2], w[3], w[4]);
-        }
-        R u[5], v[5], Tt[5];
-#pragma unroll
-        for (int o = 0; o < 5; ++o) {
-          const int b = a + (o - 2) * sa;
-          u[o] = T.A[0][b];
-          v[o] = T.A[1][b];
-          Tt[o] = T.A[3][b];
-        }
-        // compact D^{(d),2}(K_dd, Z)
-        const R s4 = R(4.0 / (h * h));
-        const R mu = ph.mu, m43 = R(4.0 / 3.0) * ph.mu;
-        const R cu = bcol(u), cv = bcol(v), cT = bcol(Tt);
-        const R fu = bform(u, u), fv = bform(v, v);
-        if (d == 0) {
-          Rs[1] += s4 * m43 * cu;
-          Rs[2] += s4 * mu * cv;
-          Rs[3] += s4 * (m43 * fu + mu * fv + ph.kap * cT);
-        } else {
-          Rs[1] += s4 * mu * cu;
-          Rs[2] += s4 * m43 * cv;
-          Rs[3] += s4 * (mu * fu + m43 * fv + ph.kap * cT);
-        }
-        // mixed: D_c^{(d)} (K_{d,o} D_c^{(o)} Z), o the other direction
-        R m1[5], m2[5], m3[5];
-#pragma unroll
-        for (int o = 0; o < 5; ++o) {
-          if (o == 2) {
-            m1[o] = m2[o] = m3[o] = R(0.0);
-            continue;
-          }
-          const int qq = q + (o - 2) * sq;
-          if (d == 0) {  // K_12 dZ/dy
-            const R uy = T.G[3][qq], vy = T.G[4][qq];
-            m1[o] = -R(2.0 / 3.0) * mu * vy;
-            m2[o] = mu * uy;
-            m3[o] = mu * (v[o] * uy - R(2.0 / 3.0) * u[o] * vy);
-          } else {  // K_21 dZ/dx
-            const R ux = T.G[0][qq], vx = T.G[1][qq];
-            m1[o] = mu * vx;
-            m2[o] = -R(2.0 / 3.0) * mu * ux;
-            m3[o] = mu * (u[o] * vx - R(2.0 / 3.0) * v[o] * ux);
-          }
-        }
-        Rs[1] += dc5(m1[0], m1[1], m1[3], m1[4], i6h);
-        Rs[2] += dc5(m2[0], m2[1], m2[3], m2[4], i6h);
-        Rs[3] += dc5(m3[0], m3[1], m3[3], m3[4], i6h);
+        for (int k = 0; k < 4; ++k) Rs[k] = Rx[k] + Ry[k];
       }
       // the point update and its blend in FP64, from the FP64 point value
-      double UH[4], out[4];
+      double U0[4], UH[4], out[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         if constexpr (kFP64<R>)
@@ -1180,12 +1238,26 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
         UH[k] = U0[k] + dt * double(Rs[k]);
       }
       if (ph.lim & LIM_POINT) {
+        double Ls[4];
+        if constexpr (LPP == 2) {
+          R Ld[4];
+          lo_point_dir(T, X - X0 + 4, Y - Y0 + 4, d, d ? g.dy : g.dx, dt, Ld);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) Ls[k] = double(Ld[k]) + double(pair_swap(Ld[k]));
+        } else {
+          R Lx[4], Ly[4];
+          lo_point_dir(T, X - X0 + 4, Y - Y0 + 4, 0, g.dx, dt, Lx);
+          lo_point_dir(T, X - X0 + 4, Y - Y0 + 4, 1, g.dy, dt, Ly);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) Ls[k] = double(Lx[k]) + double(Ly[k]);
+        }
         double UL[4];
-        lo_point(T, X - X0 + 4, Y - Y0 + 4, g.dx, g.dy, dt, U0, UL);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) UL[k] = U0[k] - Ls[k];
         bool lbad = false;
         double th = theta_pair2(UL, UH, phd.gm1, lbad);
         if (ph.lim & LIM_LOWONLY) th = 0.0;
-        if (lbad) raise_flag(flags, FLAG_POINT_LOW);
+        if (lbad && d == 0) raise_flag(flags, FLAG_POINT_LOW);
 #pragma unroll
         for (int k = 0; k < 4; ++k) out[k] = (th == 1.0) ? UH[k] : UL[k] + th * (UH[k] - UL[k]);
       } else {
@@ -1196,12 +1268,21 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
       if (X == Xlim) project(wall_of(g.bc1), 0, out);
       if (Y == 0) project(wall_of(g.bc2), 1, out);
       if (Y == Ylim) project(wall_of(g.bc3), 1, out);
+      // this lane's components (selected by value: an index computed from d
+      // would put out in scratch memory)
+      double v[NW];
+      if constexpr (LPP == 2) {
+        v[0] = d ? out[2] : out[0];
+        v[1] = d ? out[3] : out[1];
+      } else {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const long idx = off + k * np + gi;
-        const double o = first ? out[k] : ca * un[k] + cb * out[k];
+        for (int c = 0; c < NW; ++c) v[c] = out[c];
+      }
+#pragma unroll
+      for (int c = 0; c < NW; ++c) {
+        const double o = first ? v[c] : ca * un[c] + cb * v[c];
         if (!isfinite(o)) nonfinite = true;
-        Uout[idx] = o;
+        Uout[off + (NW * d + c) * np + gi] = o;
       }
     }
   }
