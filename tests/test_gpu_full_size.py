@@ -1,9 +1,12 @@
-"""The smooth periodic density wave with a vortex at the largest grid of its
-sweep (2048 x 2048), launched as af_run launches it on the GPU.
+"""The smooth periodic density wave with a vortex at the sizes of its sweep
+(256^2 to 2048^2), launched as af_run launches it on the GPU.
 
-* One RK3 step at the CFL dt (three complete stages) against the FP64
-  oracle, to the FP64 tolerance.
-* 100 RK3 steps in FP64 and with FP32 stencils, held to what holds at any
+* At 256^2, 512^2 and 1024^2: one RK3 step at the CFL dt in FP64 against
+  the FP64 oracle, to the FP64 tolerance, and the same step with FP32
+  stencils to the mixed-precision stage's bar.
+* At 2048^2, the largest: one RK3 step at the CFL dt (three complete
+  stages) against the FP64 oracle, to the FP64 tolerance, and 100 RK3
+  steps in FP64 and with FP32 stencils, held to what holds at any
   size: the cell averages' sums (mass, momentum, energy) stay what they
   were to round-off on a periodic grid, every DOF stays admissible, and the
   FP32-stencil run stays within a stated relative L1 distance of the FP64
@@ -21,6 +24,24 @@ pytestmark = pytest.mark.gpu
 GAMMA = 1.4
 N = 2048
 KW = dict(mu=1e-3, Pr=0.72)
+
+
+@pytest.mark.parametrize("n", [256, 512, 1024])
+def test_vortex_sweep_sizes_step_against_the_oracle(n):
+    g, f = W.vortex_wave_2d(n)
+    U0 = W.make_state(g, f, GAMMA)
+    U = U0.copy()
+    cfg = O.make_cfg(g, **KW)
+    st, dtu, h, fl = O.step(cfg, U, 0.0, 0.0)
+    assert st == 0 and h == 0
+    for prec, tol in ((af.PREC_FP64, 2e-12), (af.PREC_MIXED, 1e-5)):
+        S = af.Solver(g, precision=prec, **KW)
+        Ud = S.to_device(U0)
+        stg, nst, t = S.af_run(Ud, 0.0, 1e30, 1, check_every=1)
+        assert stg == af.AF_OK and nst == 1
+        assert t == pytest.approx(dtu, rel=1e-12)
+        worst = assert_close(g, Ud.cpu().numpy(), U, tol=tol, what=f"vortex {n}^2 precision {prec}")
+        print(f"vortex {n}^2, precision {prec}, one step: worst relative error {worst:.3e}")
 
 
 @pytest.fixture(scope="module")
