@@ -563,8 +563,9 @@ def learned_form(args, stream) -> dict:
     jump turns into a viscous shock, are where the blend acts most); a tenth
     held out; from the rest a training set of --learned-rows rows (every
     face with theta^s < 0.999 and random others, workloads.balanced_rows).
-    Training: Adam (lr 2e-3, minibatches of 1024) from the seeded initial
-    weights.
+    Training: Adam (minibatches of 1024) from the seeded initial weights,
+    the learning rate stepped down over the run: 2e-3 for the first two
+    thirds of the steps, 5e-4 for the next sixth, 1.25e-4 for the last.
 
     Evaluation, each run timed with HIP events (value = DOF sites x 3 x
     accepted steps / second):
@@ -618,7 +619,13 @@ def learned_form(args, stream) -> dict:
     _, l0 = af.mlp_grad(Xh, yh, P)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    af.mlp_train(Xt, yt, P, m, v, 0, args.learned_train_steps, 1024, 2e-3)
+    nsteps = args.learned_train_steps
+    done = 0
+    for frac, lr in ((2 / 3, 2e-3), (5 / 6, 5e-4), (1.0, 1.25e-4)):
+        upto = int(round(frac * nsteps))
+        if upto > done:
+            af.mlp_train(Xt, yt, P, m, v, done, upto - done, 1024, lr)
+            done = upto
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     _, l1 = af.mlp_grad(Xh, yh, P)
@@ -664,7 +671,9 @@ def learned_form(args, stream) -> dict:
                        "blend; network trained on theta^s of the 1000x500 tube after steps "
                        + ", ".join(str(k) for k in snaps),
            "train": {"samples": ntrain, "held_out": nhold, "steps": args.learned_train_steps,
-                     "batch": 1024, "lr": 2e-3, "seconds": round(train_s, 2),
+                     "batch": 1024, "lr": [2e-3, 5e-4, 1.25e-4],
+                     "lr_until_step": [int(round(f * nsteps)) for f in (2 / 3, 5 / 6, 1.0)],
+                     "seconds": round(train_s, 2),
                      "loss_held_out_before": float(l0.item()),
                      "loss_held_out_after": float(l1.item()),
                      "fraction_theta_s_below_1": round(frac_lt1, 4),
