@@ -163,21 +163,25 @@ __global__ void __launch_bounds__(256) k_features(G2 g, double gm1, float gam,
 }
 
 // ---------------------------------------------------------------------------
-// inference.  A workgroup (four wave64s) takes 128 consecutive faces of one
-// row of one direction: it stages the primitives of their stencil cells in
-// LDS and writes the features as bfloat16 rows; each wave then runs the
-// network on 32 faces with MFMA 32x32x16 bf16 in the transposed form
-// H^T = W X^T: the weights are the A operand (units x inputs, in registers),
-// the faces the columns.  A 32 x 32 accumulator holds in lane (face c, half
-// h) the rows (units) 8 (r/4) + 4 h + r%4 of column c, r = 0..15, and the B
-// operand of the next layer needs in that lane the inputs 16 kb + 8 h + e,
-// e = 0..7, of the same face: registers 8q .. 8q+7 of the accumulator of
-// unit block nb are exactly that for kb = 2 nb + q, once the hidden units are
-// numbered in that (virtual) order, which is how layer 2's weights are
-// stored.  So hidden values never leave the registers, and the output layer's
-// sum over units ends with one exchange between the two halves of the wave.
+// inference.  A workgroup (four wave64s) takes 128 consecutive faces of
+// each of eight rows of one direction: it stages the primitives of their
+// stencil cells in LDS once (ten rows of cells for eight rows of x-faces,
+// eleven for y-faces, where one face row at a time needed three or four),
+// and for each face row writes the features as bfloat16 rows; each wave
+// then runs the network on 32 faces with MFMA 32x32x16 bf16 in the
+// transposed form H^T = W X^T: the weights are the A operand (units x
+// inputs, in registers), the faces the columns.  A 32 x 32 accumulator holds
+// in lane (face c, half h) the rows (units) 8 (r/4) + 4 h + r%4 of column c,
+// r = 0..15, and the B operand of the next layer needs in that lane the
+// inputs 16 kb + 8 h + e, e = 0..7, of the same face: registers 8q .. 8q+7
+// of the accumulator of unit block nb are exactly that for kb = 2 nb + q,
+// once the hidden units are numbered in that (virtual) order, which is how
+// layer 2's weights are stored.  So hidden values never leave the
+// registers, and the output layer's sum over units ends with one exchange
+// between the two halves of the wave.
 // ---------------------------------------------------------------------------
-constexpr int IB = 128;                 // faces per block
+constexpr int IB = 128;                 // faces per row of a block
+constexpr int RB = 8;                   // face rows per block
 constexpr int KIN = 48;                 // inputs padded to three K steps of 16
 constexpr int FROW = KIN + 8;           // feature row (bf16; 16-byte aligned)
 constexpr int CW = IB + 4;              // stencil cells per row
@@ -186,7 +190,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 struct InferShared {
-  float cell[4][4][CW];                 // [component][row][column]
+  float cell[4][RB + 3][CW];            // [component][row][column]
   unsigned short feat[IB * FROW];
   float b1[NH], b2[NH], w3[NH];         // biases, and the output weights (bf16 values)
   // layer 2's A operands, per lane (in LDS rather than registers: with them
@@ -209,7 +213,8 @@ __device__ __forceinline__ int hidden_unit(int kb, int h, int e) {
   return 32 * nb + 8 * (2 * q + a) + 4 * h + i;
 }
 
-__global__ void __launch_bounds__(256) k_infer(G2 g, double gm1, float gam,
+// at least three waves per SIMD (at most 168 VGPRs)
+__global__ void __launch_bounds__(256, 3) k_infer(G2 g, double gm1, float gam,
                                                const double* __restrict__ U,
                                                const unsigned char* __restrict__ pk,
                                                float* __restrict__ theta, int nsegx, int nsegy,
@@ -249,38 +254,44 @@ __global__ void __launch_bounds__(256) k_infer(G2 g, double gm1, float gam,
     S.w3[e] = from_bf16(w3[e]);
   }
   const long nfx = (long)g.n2 * (g.n1 + 1);
-  const long nbx = (long)g.n2 * nsegx;
-  // block blk: direction, row, first face along the row, face count, and its
-  // stencil cells: x-faces need columns i0-2 .. i0+cnt and rows row-1..row+1,
-  // y-faces columns i0-1 .. i0+cnt and rows row-2..row+1
+  const long ngx = (g.n2 + RB - 1) / RB;  // row groups of the x-faces
+  const long nbx = ngx * nsegx;
+  // block blk: direction, first row and row count, first face along the
+  // rows, face count per row, and its stencil cells: x-faces need columns
+  // i0-2 .. i0+cnt and rows row0-1 .. row0+nr, y-faces columns i0-1 ..
+  // i0+cnt and rows row0-2 .. row0+nr-1
   struct Blk {
-    int d, row, i0, cnt, ncol, nrow, c0, r0;
+    int d, row0, nr, i0, cnt, ncol, nrow, c0, r0;
   };
   auto block_of = [&](long blk) {
     Blk b;
     if (blk < nbx) {
       b.d = 0;
-      b.row = (int)(blk / nsegx);
+      b.row0 = (int)(blk / nsegx) * RB;
+      b.nr = min(RB, g.n2 - b.row0);
       b.i0 = (int)(blk % nsegx) * IB;
       b.cnt = min(IB, g.n1 + 1 - b.i0);
     } else {
       b.d = 1;
       const long r = blk - nbx;
-      b.row = (int)(r / nsegy);
+      b.row0 = (int)(r / nsegy) * RB;
+      b.nr = min(RB, g.n2 + 1 - b.row0);
       b.i0 = (int)(r % nsegy) * IB;
       b.cnt = min(IB, g.n1 - b.i0);
     }
     b.ncol = b.d == 0 ? b.cnt + 3 : b.cnt + 2;
-    b.nrow = b.d == 0 ? 3 : 4;
+    b.nrow = (b.d == 0 ? 2 : 3) + b.nr;
     b.c0 = b.d == 0 ? b.i0 - 2 : b.i0 - 1;
-    b.r0 = b.d == 0 ? b.row - 1 : b.row - 2;
+    b.r0 = b.d == 0 ? b.row0 - 1 : b.row0 - 2;
     return b;
   };
-  // the FP64 averages of a block's stencil cells, three per thread at most
-  // (4 x 130 cells), loaded one block ahead so that the loads complete while
-  // the previous block runs through the network
-  constexpr int CPT = (4 * (IB + 2) + 255) / 256;
-  static_assert(3 * (IB + 3) <= CPT * 256, "cells per thread");
+  // the FP64 averages of a block's stencil cells, up to (RB + 3) x 130 cells,
+  // loaded at the start of the block (held one block ahead, they took more
+  // registers than three workgroups per CU leave; the other workgroups on the
+  // CU hide the wait)
+  constexpr int CPT = ((RB + 3) * (IB + 2) + 255) / 256;
+  static_assert((RB + 2) * (IB + 3) <= CPT * 256 && (RB + 3) * (IB + 2) <= CPT * 256,
+                "cells per thread");
   double pre[CPT][4];
   auto fetch = [&](const Blk& b) {
 #pragma unroll
@@ -290,10 +301,10 @@ __global__ void __launch_bounds__(256) k_infer(G2 g, double gm1, float gam,
     }
   };
   long blk = blockIdx.x;
-  if (blk < nblocks) fetch(block_of(blk));
   for (; blk < nblocks; blk += gridDim.x) {
     const Blk B = block_of(blk);
-    const int d = B.d, row = B.row, i0 = B.i0, cnt = B.cnt, c0 = B.c0, r0 = B.r0;
+    fetch(B);
+    const int d = B.d, i0 = B.i0, cnt = B.cnt, c0 = B.c0, r0 = B.r0;
     __syncthreads();  // the previous block is done with the cell and feature arrays
 #pragma unroll
     for (int r = 0; r < CPT; ++r) {
@@ -305,85 +316,87 @@ __global__ void __launch_bounds__(256) k_infer(G2 g, double gm1, float gam,
         for (int k = 0; k < 4; ++k) S.cell[k][e / B.ncol][e % B.ncol] = P[k];
       }
     }
-    __syncthreads();
-    {
-      // two threads per face, one half of its features each; inputs 40..47
-      // are zero
-      const int fl = tid & (IB - 1), half = tid / IB;
-      unsigned short* fo = S.feat + fl * FROW;
-      if (fl < cnt) {
-        const int i = i0 + fl;
-        features_of(d, gam,
-                    [&](int s, int q, float* P) {
-                      int ci, cj;
-                      stencil_cell(d, i, row, s, q, ci, cj);
+    for (int rr = 0; rr < B.nr; ++rr) {
+      const int row = B.row0 + rr;
+      __syncthreads();  // the cells are in; the previous row is done with the features
+      {
+        // two threads per face, one half of its features each; inputs 40..47
+        // are zero
+        const int fl = tid & (IB - 1), half = tid / IB;
+        unsigned short* fo = S.feat + fl * FROW;
+        if (fl < cnt) {
+          const int i = i0 + fl;
+          features_of(d, gam,
+                      [&](int s, int q, float* P) {
+                        int ci, cj;
+                        stencil_cell(d, i, row, s, q, ci, cj);
 #pragma unroll
-                      for (int k = 0; k < 4; ++k) P[k] = S.cell[k][cj - r0][ci - c0];
-                    },
-                    [&](int n, float v) { fo[n] = to_bf16(v); }, half);
-      } else {
-        for (int n = half; n < NIN; n += 2) fo[n] = 0;
+                        for (int k = 0; k < 4; ++k) P[k] = S.cell[k][cj - r0][ci - c0];
+                      },
+                      [&](int n, float v) { fo[n] = to_bf16(v); }, half);
+        } else {
+          for (int n = half; n < NIN; n += 2) fo[n] = 0;
+        }
+#pragma unroll
+        for (int n = 0; n < 4; ++n) fo[NIN + 4 * half + n] = 0;
       }
-#pragma unroll
-      for (int n = 0; n < 4; ++n) fo[NIN + 4 * half + n] = 0;
-    }
-    __syncthreads();
-    if (blk + gridDim.x < nblocks) fetch(block_of(blk + gridDim.x));
-    // the wave's 32 faces: lane (c32, h) works on face 32 wave + c32
-    const unsigned short* fa = S.feat + (32 * wave + c32) * FROW;
-    f32x16 acc[2];
-#pragma unroll
-    for (int nb = 0; nb < 2; ++nb)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[nb][r] = 0.0f;
-#pragma unroll
-    for (int kb = 0; kb < 3; ++kb) {
-      const bf16x8 x = *reinterpret_cast<const bf16x8*>(fa + 16 * kb + 8 * h);
+      __syncthreads();
+      // the wave's 32 faces: lane (c32, h) works on face 32 wave + c32
+      const unsigned short* fa = S.feat + (32 * wave + c32) * FROW;
+      f32x16 acc[2];
 #pragma unroll
       for (int nb = 0; nb < 2; ++nb)
-        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1[nb][kb], x, acc[nb], 0, 0, 0);
-    }
-    // h1 = tanh(W1 x + b1) in bfloat16: layer 2's B operand, kb = 2 nb + q
-    bf16x8 hb[4];
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb)
+        for (int r = 0; r < 16; ++r) acc[nb][r] = 0.0f;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const float4 bias = *reinterpret_cast<const float4*>(&S.b1[32 * nb + 8 * j + 4 * h]);
-        const float bj[4] = {bias.x, bias.y, bias.z, bias.w};
+      for (int kb = 0; kb < 3; ++kb) {
+        const bf16x8 x = *reinterpret_cast<const bf16x8*>(fa + 16 * kb + 8 * h);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          hb[2 * nb + (j >> 1)][4 * (j & 1) + i] = (__bf16)tanh_fast(acc[nb][4 * j + i] + bj[i]);
+        for (int nb = 0; nb < 2; ++nb)
+          acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1[nb][kb], x, acc[nb], 0, 0, 0);
       }
-#pragma unroll
-    for (int nb = 0; nb < 2; ++nb)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[nb][r] = 0.0f;
-#pragma unroll
-    for (int kb = 0; kb < 4; ++kb)
+      // h1 = tanh(W1 x + b1) in bfloat16: layer 2's B operand, kb = 2 nb + q
+      bf16x8 hb[4];
 #pragma unroll
       for (int nb = 0; nb < 2; ++nb)
-        acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(S.a2[nb][kb][lane], hb[kb], acc[nb], 0, 0, 0);
-    // z = w3 . tanh(W2 h1 + b2) + b3: this lane's 32 units of its face, then
-    // the other half's 32 from the lane 32 away
-    float z = 0.0f;
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb)
+        for (int j = 0; j < 4; ++j) {
+          const float4 bias = *reinterpret_cast<const float4*>(&S.b1[32 * nb + 8 * j + 4 * h]);
+          const float bj[4] = {bias.x, bias.y, bias.z, bias.w};
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int u = 32 * nb + 8 * j + 4 * h;
-        const float4 bias = *reinterpret_cast<const float4*>(&S.b2[u]);
-        const float4 ow = *reinterpret_cast<const float4*>(&S.w3[u]);
-        z += ow.x * tanh_fast(acc[nb][4 * j] + bias.x);
-        z += ow.y * tanh_fast(acc[nb][4 * j + 1] + bias.y);
-        z += ow.z * tanh_fast(acc[nb][4 * j + 2] + bias.z);
-        z += ow.w * tanh_fast(acc[nb][4 * j + 3] + bias.w);
+          for (int i = 0; i < 4; ++i)
+            hb[2 * nb + (j >> 1)][4 * (j & 1) + i] = (__bf16)tanh_fast(acc[nb][4 * j + i] + bj[i]);
+        }
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[nb][r] = 0.0f;
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+          acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(S.a2[nb][kb][lane], hb[kb], acc[nb], 0, 0, 0);
+      // z = w3 . tanh(W2 h1 + b2) + b3: this lane's 32 units of its face, then
+      // the other half's 32 from the lane 32 away
+      float z = 0.0f;
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int u = 32 * nb + 8 * j + 4 * h;
+          const float4 bias = *reinterpret_cast<const float4*>(&S.b2[u]);
+          const float4 ow = *reinterpret_cast<const float4*>(&S.w3[u]);
+          z += ow.x * tanh_fast(acc[nb][4 * j] + bias.x);
+          z += ow.y * tanh_fast(acc[nb][4 * j + 1] + bias.y);
+          z += ow.z * tanh_fast(acc[nb][4 * j + 2] + bias.z);
+          z += ow.w * tanh_fast(acc[nb][4 * j + 3] + bias.w);
+        }
+      z += __shfl_xor(z, 32, 64);
+      const int m = 32 * wave + c32;
+      if (h == 0 && m < cnt) {
+        const long f = (d == 0 ? 0 : nfx) + (long)row * (d == 0 ? g.n1 + 1 : g.n1) + i0 + m;
+        theta[f] = fminf(fmaxf(z + b3, 0.0f), 1.0f);
       }
-    z += __shfl_xor(z, 32, 64);
-    const int m = 32 * wave + c32;
-    if (h == 0 && m < cnt) {
-      const long f = (d == 0 ? 0 : nfx) + (long)row * (d == 0 ? g.n1 + 1 : g.n1) + i0 + m;
-      theta[f] = fminf(fmaxf(z + b3, 0.0f), 1.0f);
     }
   }
 }
@@ -618,7 +631,7 @@ hipError_t blend_infer(const Geo& geo, const Phys& ph, const double* U, const vo
                        float* theta, hipStream_t s, Timer* tm) {
   const G2 g = stage_geo(geo);
   const int nsegx = (g.n1 + 1 + IB - 1) / IB, nsegy = (g.n1 + IB - 1) / IB;
-  const long nblocks = (long)g.n2 * nsegx + (long)(g.n2 + 1) * nsegy;
+  const long nblocks = (long)((g.n2 + RB - 1) / RB) * nsegx + (long)((g.n2 + 1 + RB - 1) / RB) * nsegy;
   const long nwg = infer_workgroups();
   const long grid = nblocks < nwg ? nblocks : nwg;
   AFI_TIMED(tm, 8, s,
