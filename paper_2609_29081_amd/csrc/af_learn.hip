@@ -181,7 +181,7 @@ __global__ void __launch_bounds__(256) k_features(G2 g, double gm1, float gam,
 // between the two halves of the wave.
 // ---------------------------------------------------------------------------
 constexpr int IB = 128;                 // faces per row of a block
-constexpr int RB = 8;                   // face rows per block
+constexpr int RB = 8;                   // face rows per block, at most
 constexpr int KIN = 48;                 // inputs padded to three K steps of 16
 constexpr int FROW = KIN + 8;           // feature row (bf16; 16-byte aligned)
 constexpr int CW = IB + 4;              // stencil cells per row
@@ -218,7 +218,7 @@ __global__ void __launch_bounds__(256, 3) k_infer(G2 g, double gm1, float gam,
                                                const double* __restrict__ U,
                                                const unsigned char* __restrict__ pk,
                                                float* __restrict__ theta, int nsegx, int nsegy,
-                                               long nblocks) {
+                                               int rb, long nblocks) {
   __shared__ InferShared S;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int h = lane >> 5, c32 = lane & 31;
@@ -254,7 +254,7 @@ __global__ void __launch_bounds__(256, 3) k_infer(G2 g, double gm1, float gam,
     S.w3[e] = from_bf16(w3[e]);
   }
   const long nfx = (long)g.n2 * (g.n1 + 1);
-  const long ngx = (g.n2 + RB - 1) / RB;  // row groups of the x-faces
+  const long ngx = (g.n2 + rb - 1) / rb;  // row groups of the x-faces
   const long nbx = ngx * nsegx;
   // block blk: direction, first row and row count, first face along the
   // rows, face count per row, and its stencil cells: x-faces need columns
@@ -267,15 +267,15 @@ __global__ void __launch_bounds__(256, 3) k_infer(G2 g, double gm1, float gam,
     Blk b;
     if (blk < nbx) {
       b.d = 0;
-      b.row0 = (int)(blk / nsegx) * RB;
-      b.nr = min(RB, g.n2 - b.row0);
+      b.row0 = (int)(blk / nsegx) * rb;
+      b.nr = min(rb, g.n2 - b.row0);
       b.i0 = (int)(blk % nsegx) * IB;
       b.cnt = min(IB, g.n1 + 1 - b.i0);
     } else {
       b.d = 1;
       const long r = blk - nbx;
-      b.row0 = (int)(r / nsegy) * RB;
-      b.nr = min(RB, g.n2 + 1 - b.row0);
+      b.row0 = (int)(r / nsegy) * rb;
+      b.nr = min(rb, g.n2 + 1 - b.row0);
       b.i0 = (int)(r % nsegy) * IB;
       b.cnt = min(IB, g.n1 - b.i0);
     }
@@ -631,13 +631,20 @@ hipError_t blend_infer(const Geo& geo, const Phys& ph, const double* U, const vo
                        float* theta, hipStream_t s, Timer* tm) {
   const G2 g = stage_geo(geo);
   const int nsegx = (g.n1 + 1 + IB - 1) / IB, nsegy = (g.n1 + IB - 1) / IB;
-  const long nblocks = (long)((g.n2 + RB - 1) / RB) * nsegx + (long)((g.n2 + 1 + RB - 1) / RB) * nsegy;
   const long nwg = infer_workgroups();
+  // rows per block: the most (up to RB) that still leave every resident
+  // workgroup two blocks, so that a small grid keeps the device busy
+  auto blocks = [&](int rb) {
+    return (long)((g.n2 + rb - 1) / rb) * nsegx + (long)((g.n2 + 1 + rb - 1) / rb) * nsegy;
+  };
+  int rb = RB;
+  while (rb > 1 && blocks(rb) < 2 * nwg) rb /= 2;
+  const long nblocks = blocks(rb);
   const long grid = nblocks < nwg ? nblocks : nwg;
   AFI_TIMED(tm, 8, s,
             hipLaunchKernelGGL(k_infer, dim3((unsigned)grid), dim3(256), 0, s, g, ph.gm1,
                                float(ph.gam), U, (const unsigned char*)packed, theta, nsegx,
-                               nsegy, nblocks));
+                               nsegy, rb, nblocks));
   return hipGetLastError();
 }
 
