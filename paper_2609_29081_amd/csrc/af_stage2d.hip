@@ -936,11 +936,26 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
     for (int k = 0; k < 23; ++k) T.C[k][s] = o[k];
   }
   if constexpr (kFP64<R>) {
-    for (int s = tid; s < NA; s += NT) {
-      const int X = X0 - 4 + s % WA, Y = Y0 - 4 + s / WA;
-      if (X > Xlim + kMargin || Y > Ylim + kMargin || ((X & 1) && (Y & 1))) continue;
+    // the point sites of the lattice region, numbered p: each pair of rows
+    // (an even one, all 41 sites points; an odd one, its 21 even sites)
+    // holds 62 of them, so no lane falls on a centre
+    constexpr int PPR = WA + (WA + 1) / 2;  // points per pair of rows
+    constexpr int NPS = (HA + 1) / 2 * WA + HA / 2 * ((WA + 1) / 2);
+    auto aux_point = [&](int p) {
+      const int r2 = p / PPR, m = p % PPR;
+      const int ly = m < WA ? 2 * r2 : 2 * r2 + 1, lx = m < WA ? m : 2 * (m - WA);
+      const int s = ly * WA + lx;
+      const int X = X0 - 4 + lx, Y = Y0 - 4 + ly;
+      if (X > Xlim + kMargin || Y > Ylim + kMargin) return;
       const double V[4] = {T.U[0][s], T.U[1][s], T.U[2][s], T.U[3][s]};
       store_aux(T, phd64, s, V);
+    };
+    // one site per thread, then the rest on waves 3 and 7: the SIMD they
+    // share (waves go to the SIMDs round-robin) updates no cells
+    if (tid < NPS) aux_point(tid);
+    const int wv = tid >> 6;
+    if (wv == 3 || wv == 7) {
+      for (int p = NT + (tid & 63) + (wv == 7 ? 64 : 0); p < NPS; p += 128) aux_point(p);
     }
   }
   __syncthreads();
@@ -1171,13 +1186,18 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
   //      idle ----
   if (ph.lim & LIM_POINT) {
     const R ihx = R(1.0 / g.dx), ihy = R(1.0 / g.dy);
-    for (int s = (tid + NT - TX * TY) % NT; s < NSR; s += NT) {
+    auto site = [&](int s) {
       const int sx = s % SW, sy = s / SW;
       const bool need_x = sy >= 1 && sy <= 2 * TY, need_y = sx >= 1 && sx <= 2 * TX;
       if (need_x || need_y)
         lo_site(T, ph, sx + 3, sy + 3, ihx, ihy, need_x, need_y, (sy - 1) * SW + sx,
                 sy * (2 * TX) + sx - 1);
-    }
+    };
+    // the first NT sites from the first thread phase 4 leaves idle on; the
+    // rest from wave 3 on, away from the waves that also update cells
+    const int s1 = (tid + NT - TX * TY) % NT;
+    if (s1 < NSR) site(s1);
+    for (int s = NT + (tid + NT - 192) % NT; s < NSR; s += NT) site(s);
     __syncthreads();
   }
 
