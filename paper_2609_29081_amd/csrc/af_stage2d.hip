@@ -74,7 +74,6 @@ constexpr int NPT = 3 * TX * TY;           // point DOF sites of a tile
 // rows Y0..Y0+2TY-1, y-direction data on its columns X0..X0+2TX-1
 constexpr int SW = 2 * TX + 2, SH = 2 * TY + 2, NSR = SW * SH;
 constexpr int NSX = SW * 2 * TY, NSY = 2 * TX * SH;
-constexpr int kStage = 9 * NCEN > 4 * NSX ? 9 * NCEN : 4 * NSX;
 
 template <typename R>
 constexpr bool kFP64 = std::is_same<R, double>::value;
@@ -251,8 +250,10 @@ struct Tile {
     R SY[4][NSY];
   };
   union {
-    R STG[kStage];  // phase 2: centre values and their (u, v, p, T, c)
-    R SX[4][NSX];   // phase 5: x-direction flux (components 1-3) and b_x
+    // FP32 stencils, phase 2: centre values and their (u, v, p, T, c),
+    // staged while the cells read the averages in the centre slots
+    R STG[kFP64<R> ? 1 : 9 * NCEN];
+    R SX[4][NSX];  // phase 5: x-direction flux (components 1-3) and b_x
   };
   R FX[4][NFX];  // limited x-face fluxes of the tile's cells
   R FY[4][NFY];  // limited y-face fluxes
@@ -263,6 +264,9 @@ struct Tile {
   // each of the tile's point DOFs, so that phase 5 has V to 48 bits from
   // U (the high part) without reading the state again
   float PL[4][kFP64<R> ? 1 : NPT];
+  // FP64 stage: the cell averages at the centre sites of the lattice region
+  // (the centre slots of U take the Simpson centres in phase 2)
+  R AVG[4][kFP64<R> ? NCEN : 1];
 };
 static_assert(4 * NSY <= 14 * NC, "the y-direction site data fit in rows 0-13 of C");
 
@@ -849,7 +853,20 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
     for (int k = 0; k < 4; ++k) {
       const bool neg = (k == 1 && (flip[r] & 1)) || (k == 2 && (flip[r] & 2));
       V[k] = neg ? -pre[r][k] : pre[r][k];
-      T.U[k][s] = R(V[k]);
+    }
+    if constexpr (kFP64<R>) {
+      // FP64: averages to AVG, point values to U
+      if ((X & 1) && (Y & 1)) {
+        const int ci = ((s / WA - 1) >> 1) * (TX + 4) + ((s % WA - 1) >> 1);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) T.AVG[k][ci] = V[k];
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) T.U[k][s] = V[k];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) T.U[k][s] = R(V[k]);
     }
     // FP32 stencils: the point sites' (u, v, p, T, c) from the FP64 values
     // (centre sites get the Simpson centre's); the FP64 stage takes them in
@@ -905,31 +922,52 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
             const R* z = T.U[k];
-            Ub[k] = z[cs];
+            Ub[k] = kFP64<R> ? T.AVG[k][cidx] : z[cs];
             e[k] = z[cs - 1] + z[cs + 1] + z[cs - WA] + z[cs + WA];
             cc[k] = z[cs - WA - 1] + z[cs - WA + 1] + z[cs + WA - 1] + z[cs + WA + 1];
           }
           centre_value(ph, phd, Ub, e, cc, cV, cw);
         }
       }
+      if constexpr (kFP64<R>) {
+        // the cells read the averages from AVG: the centre goes in place
 #pragma unroll
-      for (int k = 0; k < 4; ++k) T.STG[k * NCEN + cidx] = cV[k];
+        for (int k = 0; k < 4; ++k) T.U[k][cs] = cV[k];
 #pragma unroll
-      for (int k = 0; k < 5; ++k) T.STG[(4 + k) * NCEN + cidx] = cw[k];
+        for (int k = 0; k < 5; ++k) T.A[k][cs] = cw[k];
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) T.STG[k * NCEN + cidx] = cV[k];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) T.STG[(4 + k) * NCEN + cidx] = cw[k];
+      }
     }
   }
   for (int s = tid; s < NC; s += NT) {
     const int i = i0 - 1 + s % WC, j = j0 - 1 + s / WC;
     if (i > g.n1 || j > g.n2) continue;
-    const int a = (2 * j + 1 - Y0 + 4) * WA + (2 * i + 1 - X0 + 4);
     R C0[4], Cxm[4], Cxp[4], Cym[4], Cyp[4], o[23];
+    if constexpr (kFP64<R>) {
+      // the cell's index among the centres of the region
+      const int c = (s / WC + 1) * (TX + 4) + s % WC + 1;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      C0[k] = T.U[k][a];
-      Cxm[k] = T.U[k][a - 2];
-      Cxp[k] = T.U[k][a + 2];
-      Cym[k] = T.U[k][a - 2 * WA];
-      Cyp[k] = T.U[k][a + 2 * WA];
+      for (int k = 0; k < 4; ++k) {
+        C0[k] = T.AVG[k][c];
+        Cxm[k] = T.AVG[k][c - 1];
+        Cxp[k] = T.AVG[k][c + 1];
+        Cym[k] = T.AVG[k][c - (TX + 4)];
+        Cyp[k] = T.AVG[k][c + (TX + 4)];
+      }
+    } else {
+      const int a = (2 * j + 1 - Y0 + 4) * WA + (2 * i + 1 - X0 + 4);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        C0[k] = T.U[k][a];
+        Cxm[k] = T.U[k][a - 2];
+        Cxp[k] = T.U[k][a + 2];
+        Cym[k] = T.U[k][a - 2 * WA];
+        Cyp[k] = T.U[k][a + 2 * WA];
+      }
     }
     cell_low(g, ph, C0, Cxm, Cxp, Cym, Cyp, o);
 #pragma unroll
@@ -959,15 +997,17 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
     }
   }
   __syncthreads();
-  for (int cidx = tid - NT / 2; cidx >= 0 && cidx < NCEN; cidx += NT / 2) {
-    const int cs = centre_slot(cidx);
-    if (cs < 0) continue;
+  if constexpr (!kFP64<R>) {
+    for (int cidx = tid - NT / 2; cidx >= 0 && cidx < NCEN; cidx += NT / 2) {
+      const int cs = centre_slot(cidx);
+      if (cs < 0) continue;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) T.U[k][cs] = T.STG[k * NCEN + cidx];
+      for (int k = 0; k < 4; ++k) T.U[k][cs] = T.STG[k * NCEN + cidx];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) T.A[k][cs] = T.STG[(4 + k) * NCEN + cidx];
+      for (int k = 0; k < 5; ++k) T.A[k][cs] = T.STG[(4 + k) * NCEN + cidx];
+    }
+    __syncthreads();
   }
-  __syncthreads();
 
   // prefetch the next tile's raw values; the loads complete while this tile
   // computes
