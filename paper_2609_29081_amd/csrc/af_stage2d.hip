@@ -943,9 +943,14 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
       }
     }
   }
-  for (int s = tid; s < NC; s += NT) {
+  // cells: the first NT/2 on waves 0-3, the rest from the top thread down
+  // (waves 7, 6, ...), away from the waves 4 and 5 that take the centres'
+  // second round when there is one
+  static_assert(NC <= NT, "one cell per thread");
+  {
+    const int s = tid < NT / 2 ? tid : NT / 2 + (NT - 1 - tid);
     const int i = i0 - 1 + s % WC, j = j0 - 1 + s / WC;
-    if (i > g.n1 || j > g.n2) continue;
+    if (s < NC && i <= g.n1 && j <= g.n2) {
     R C0[4], Cxm[4], Cxp[4], Cym[4], Cyp[4], o[23];
     if constexpr (kFP64<R>) {
       // the cell's index among the centres of the region
@@ -972,6 +977,7 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
     cell_low(g, ph, C0, Cxm, Cxp, Cym, Cyp, o);
 #pragma unroll
     for (int k = 0; k < 23; ++k) T.C[k][s] = o[k];
+    }
   }
   if constexpr (kFP64<R>) {
     // the point sites of the lattice region, numbered p: each pair of rows
