@@ -1053,6 +1053,19 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
     ts_out = sa.ts_out;
   }
   const int limc = (ph.lim & (LIM_SMOOTH | LIM_PP | LIM_LOWONLY)) | (blend ? 1 : 0);
+  // FP64: the faces take waves 0-3 only; waves 4-7 compute the
+  // x-direction site data of the low-order point scheme meanwhile (phase 5a
+  // keeps the y-direction data, which overlay cell data the faces read)
+  if constexpr (kFP64<R>) {
+    static_assert(!kFP64<R> || NFX + NFY <= NT / 2, "the faces on waves 0-3");
+    if ((ph.lim & LIM_POINT) && tid >= NT / 2) {
+      const R ihx = R(1.0 / g.dx), ihy = R(1.0 / g.dy);
+      for (int s = tid - NT / 2; s < NSX; s += NT / 2) {
+        const int sx = s % SW, sy = 1 + s / SW;
+        lo_site(T, ph, sx + 3, sy + 3, ihx, ihy, true, false, (sy - 1) * SW + sx, 0);
+      }
+    }
+  }
   for (int s = tid; s < NFX + NFY; s += NT) {
     const int d = s < NFX ? 0 : 1;
     int ff, jj, i, j, X, Y;  // face (i,j) between cells a (minus) and b (plus)
@@ -1234,16 +1247,26 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
     const R ihx = R(1.0 / g.dx), ihy = R(1.0 / g.dy);
     auto site = [&](int s) {
       const int sx = s % SW, sy = s / SW;
-      const bool need_x = sy >= 1 && sy <= 2 * TY, need_y = sx >= 1 && sx <= 2 * TX;
+      const bool need_x = !kFP64<R> && sy >= 1 && sy <= 2 * TY, need_y = sx >= 1 && sx <= 2 * TX;
       if (need_x || need_y)
         lo_site(T, ph, sx + 3, sy + 3, ihx, ihy, need_x, need_y, (sy - 1) * SW + sx,
                 sy * (2 * TX) + sx - 1);
     };
-    // the first NT sites from the first thread phase 4 leaves idle on; the
-    // rest from wave 3 on, away from the waves that also update cells
-    const int s1 = (tid + NT - TX * TY) % NT;
-    if (s1 < NSR) site(s1);
-    for (int s = NT + (tid + NT - 192) % NT; s < NSR; s += NT) site(s);
+    if constexpr (kFP64<R>) {
+      // the y-direction data (the x-direction data came during phase 3)
+      const int s = (tid + NT - TX * TY) % NT;
+      if (s < NSY) {
+        const int sx = 1 + s % (2 * TX), sy = s / (2 * TX);
+        lo_site(T, ph, sx + 3, sy + 3, ihx, ihy, false, true, 0, sy * (2 * TX) + sx - 1);
+      }
+      static_assert(!kFP64<R> || NSY <= NT, "one site per thread");
+    } else {
+      // the first NT sites from the first thread phase 4 leaves idle on; the
+      // rest from wave 3 on, away from the waves that also update cells
+      const int s1 = (tid + NT - TX * TY) % NT;
+      if (s1 < NSR) site(s1);
+      for (int s = NT + (tid + NT - 192) % NT; s < NSR; s += NT) site(s);
+    }
     __syncthreads();
   }
 
