@@ -126,43 +126,11 @@ __device__ __forceinline__ void centre_value(const PhysT<R>& ph, const Phys& phd
   aux_of(ph, V, ir, w);
 }
 
-// lattice value at a centre site beyond a wall or outflow side, from device
-// memory: the Simpson value (scaled) of the image centre, with its signs
-template <typename R>
-__device__ __forceinline__ void ghost_centre(const G2& g, const PhysT<R>& ph, const Phys& phd,
-                                             const double* __restrict__ U, int X, int Y, R* V,
-                                             R* aux) {
-  int kx, ky;
-  const int Xi = axis_image(X, 2 * g.n1, g.bc0, g.bc1, kx);
-  const int Yi = axis_image(Y, 2 * g.n2, g.bc2, g.bc3, ky);
-  const Signs sg = image_signs(kx, ky);
-  auto load4 = [&](int X, int Y, R* W) {
-    long o;
-    int st;
-    site_ofs(g, X, Y, o, st);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) W[k] = R(U[o + (long)k * st]);
-  };
-  R Ub[4], e[4] = {R(0.0), R(0.0), R(0.0), R(0.0)}, c[4] = {R(0.0), R(0.0), R(0.0), R(0.0)},
-    W[4];
-  load4(Xi, Yi, Ub);
-  // same summation order as the in-LDS path: (-x) + (+x) + (-y) + (+y)
-  const int ex[4] = {-1, 1, 0, 0}, ey[4] = {0, 0, -1, 1};
-  const int cx[4] = {-1, 1, -1, 1}, cy[4] = {-1, -1, 1, 1};
-#pragma unroll
-  for (int n = 0; n < 4; ++n) {
-    load4(Xi + ex[n], Yi + ey[n], W);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) e[k] += W[k];
-    load4(Xi + cx[n], Yi + cy[n], W);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) c[k] += W[k];
-  }
-  centre_value(ph, phd, Ub, e, c, V, aux);
-  V[1] *= R(sg.sx);
-  V[2] *= R(sg.sy);
-  aux[0] *= R(sg.sx);
-  aux[1] *= R(sg.sy);
+// whether the centre site (X, Y) of the lattice is a ghost beyond a wall or
+// outflow side (not a periodic one)
+__device__ __forceinline__ bool ghost_centre(const G2& g, int X, int Y) {
+  return ((X < 0 || X > 2 * g.n1) && g.bc0 != BC_PERIODIC) ||
+         ((Y < 0 || Y > 2 * g.n2) && g.bc2 != BC_PERIODIC);
 }
 
 // per-cell low-order data (Sec. 3.1-3.2):
@@ -907,28 +875,19 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
   };
   for (int cidx = tid - NT / 2; cidx >= 0 && cidx < NCEN; cidx += NT / 2) {
     const int cs = centre_slot(cidx);
-    if (cs >= 0) {
-      const int X = X0 - 3 + 2 * (cidx % (TX + 4)), Y = Y0 - 3 + 2 * (cidx / (TX + 4));
-      R cV[4], cw[5];
-      {
-        const bool ghost_x = (X < 0 || X > Xlim) && g.bc0 != BC_PERIODIC;
-        const bool ghost_y = (Y < 0 || Y > Ylim) && g.bc2 != BC_PERIODIC;
-        if (ghost_x || ghost_y) {
-          // a centre beyond a wall or outflow side is the image of an interior one
-          ghost_centre(g, ph, phd, Uk, X, Y, cV, cw);
-        } else {
-          // periodic ghosts included: their neighbours are the wrapped values
-          R Ub[4], e[4], cc[4];
+    const int X = X0 - 3 + 2 * (cidx % (TX + 4)), Y = Y0 - 3 + 2 * (cidx / (TX + 4));
+    // a centre beyond a wall or outflow side is taken from its image below;
+    // periodic ghosts are computed here, from the wrapped values
+    if (cs >= 0 && !ghost_centre(g, X, Y)) {
+      R Ub[4], e[4], cc[4], cV[4], cw[5];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const R* z = T.U[k];
-            Ub[k] = kFP64<R> ? T.AVG[k][cidx] : z[cs];
-            e[k] = z[cs - 1] + z[cs + 1] + z[cs - WA] + z[cs + WA];
-            cc[k] = z[cs - WA - 1] + z[cs - WA + 1] + z[cs + WA - 1] + z[cs + WA + 1];
-          }
-          centre_value(ph, phd, Ub, e, cc, cV, cw);
-        }
+      for (int k = 0; k < 4; ++k) {
+        const R* z = T.U[k];
+        Ub[k] = kFP64<R> ? T.AVG[k][cidx] : z[cs];
+        e[k] = z[cs - 1] + z[cs + 1] + z[cs - WA] + z[cs + WA];
+        cc[k] = z[cs - WA - 1] + z[cs - WA + 1] + z[cs + WA - 1] + z[cs + WA + 1];
       }
+      centre_value(ph, phd, Ub, e, cc, cV, cw);
       if constexpr (kFP64<R>) {
         // the cells read the averages from AVG: the centre goes in place
 #pragma unroll
@@ -1011,6 +970,33 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
       for (int k = 0; k < 4; ++k) T.U[k][cs] = T.STG[k * NCEN + cidx];
 #pragma unroll
       for (int k = 0; k < 5; ++k) T.A[k][cs] = T.STG[(4 + k) * NCEN + cidx];
+    }
+    __syncthreads();
+  }
+  // ghost centres: the value and (u, v, p, T, c) of the image centre, with
+  // the image's momentum and velocity signs.  The image is a centre of the
+  // same region that phase 2 computed from the same values in the same
+  // order (along a periodic axis, the unwrapped ghost itself)
+  if (!(X0 >= 4 && X0 - 4 + WA <= Xlim && Y0 >= 4 && Y0 - 4 + HA <= Ylim)) {
+    for (int cidx = tid; cidx < NCEN; cidx += NT) {
+      const int cs = centre_slot(cidx);
+      const int X = X0 - 3 + 2 * (cidx % (TX + 4)), Y = Y0 - 3 + 2 * (cidx / (TX + 4));
+      if (cs < 0 || !ghost_centre(g, X, Y)) continue;
+      int kx = -1, ky = -1;
+      const int Xi = g.bc0 == BC_PERIODIC ? X : axis_image(X, Xlim, g.bc0, g.bc1, kx);
+      const int Yi = g.bc2 == BC_PERIODIC ? Y : axis_image(Y, Ylim, g.bc2, g.bc3, ky);
+      const int f = image_flips(kx, ky);
+      const int si = (Yi - Y0 + 4) * WA + (Xi - X0 + 4);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const R v = T.U[k][si];
+        T.U[k][cs] = ((k == 1 && (f & 1)) || (k == 2 && (f & 2))) ? -v : v;
+      }
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        const R v = T.A[k][si];
+        T.A[k][cs] = ((k == 0 && (f & 1)) || (k == 1 && (f & 2))) ? -v : v;
+      }
     }
     __syncthreads();
   }
