@@ -18,6 +18,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 LIM_SMOOTH, LIM_PP, LIM_POINT, LIM_CENTRE, LIM_LOWONLY = 1, 2, 4, 8, 16
 DIRICHLET = 4
 LIM_ALL = LIM_SMOOTH | LIM_PP | LIM_POINT | LIM_CENTRE
+LIM_PEXACT = 64   # theta^p as the root of the pressure quadratic (reading R-pquad)
 FLAG_CELL_LOW, FLAG_POINT_LOW, FLAG_NONFINITE = 1, 2, 4
 
 
@@ -74,6 +75,8 @@ def lib():
         L.orc_run.restype = C.c_int
         L.orc_Theta.argtypes = [C.c_double, C.c_double, C.c_double]
         L.orc_Theta.restype = C.c_double
+        L.orc_theta_p_root.argtypes = [cp, dp, dp, C.c_double]
+        L.orc_theta_p_root.restype = C.c_double
         L.orc_pressure.argtypes = [cp, dp]
         L.orc_pressure.restype = C.c_double
         L.orc_flux_c.argtypes = [cp, C.c_int, dp, dp]
@@ -250,6 +253,13 @@ def run(cfg: Cfg, U: np.ndarray, t0: float, t_final: float, max_steps: int = 1 <
 
 def theta(zL, zH, eps):
     return lib().orc_Theta(zL, zH, eps)
+
+
+def theta_p_root(cfg, UL, UT, eps):
+    """theta^p of the exact rule from UL toward UT (reading R-pquad)"""
+    UL = np.ascontiguousarray(UL, dtype=np.float64)
+    UT = np.ascontiguousarray(UT, dtype=np.float64)
+    return lib().orc_theta_p_root(C.byref(cfg), _p(UL), _p(UT), eps)
 
 
 def pressure(cfg, U):

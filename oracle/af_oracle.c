@@ -41,6 +41,12 @@
  *              internal energy kept).
  *   R-eps    : eps = min(1e-13, z(U^L)) per state; a state with rho<=0 is
  *              flagged and its blend parameter set to 0.
+ *   R-pquad  : (optional, ORC_LIM_PEXACT) theta^p is the largest blend
+ *              keeping the pressure >= eps on the whole segment, the root of
+ *              the quadratic that p(blend) = eps becomes once multiplied by
+ *              the blended density, in place of the linear bound that the
+ *              concavity of p gives (Sec. 3.3).  It is never below the
+ *              linear one, and positivity holds with either.
  *   R-blend  : final cell flux F^L + theta^s theta^rho theta^p (F^H - F^L);
  *              with every cell limiter switched off the flux is F^H itself;
  *              a point whose blend parameter is 1 keeps U^H itself.
@@ -299,6 +305,67 @@ static void flux_tot(const orc_cfg* c, int dir, const double* U, const double* S
   for (int r = 0; r < ncomp(c); ++r) F[r] = Fc[r] - Fv[r];
 }
 
+/* theta^p by the exact rule (reading R-pquad): the largest t in [0, 1] such
+ * that p(UL + s (UT - UL)) >= eps for every s in [0, t].  Where the density
+ * is positive along the segment (theta^rho has made it so), p(s) - eps has
+ * the sign of the quadratic
+ *   q(s) = rho(s) (E(s) - eps / (gamma - 1)) - |m(s)|^2 / 2,
+ * with q(0) >= 0 because eps <= p(UL).  So t = 1 if p(UT) >= eps, and
+ * otherwise the smallest root of q in [0, 1], taken from the quadratic
+ * formula in its cancellation-free form (w = -(b + sign(b) sqrt(D)) / 2,
+ * roots w / a and c / w). */
+double orc_theta_p_root(const orc_cfg* c, const double* UL, const double* UT, double eps) {
+  int nc = ncomp(c);
+  if (orc_pressure(c, UT) >= eps) return 1.0;
+  double e1 = eps / (c->gamma - 1.0);
+  double dr = UT[0] - UL[0], dE = UT[nc - 1] - UL[nc - 1];
+  double mm = 0.0, mdm = 0.0, dmdm = 0.0;
+  for (int k = 1; k < nc - 1; ++k) {
+    double dm = UT[k] - UL[k];
+    mm += UL[k] * UL[k];
+    mdm += UL[k] * dm;
+    dmdm += dm * dm;
+  }
+  /* q(s) = qa s^2 + qb s + qc */
+  double qc = UL[0] * (UL[nc - 1] - e1) - 0.5 * mm;
+  double qb = dr * (UL[nc - 1] - e1) + UL[0] * dE - mdm;
+  double qa = dr * dE - 0.5 * dmdm;
+  if (!(qc > 0.0)) {
+    /* p(UL) = eps: s = 0 is a root, and the pressure stays >= eps past it
+     * only if it grows first (q'(0) > 0), up to the other root */
+    if (qc == 0.0 && qb > 0.0 && qa < 0.0) {
+      double r = -qb / qa;
+      return r < 1.0 ? r : 1.0;
+    }
+    return 0.0;
+  }
+  double roots[2];
+  int nr = 0;
+  if (qa == 0.0) {
+    if (qb != 0.0) roots[nr++] = -qc / qb;
+  } else {
+    double D = qb * qb - 4.0 * qa * qc;
+    if (D < 0.0) D = 0.0; /* q changes sign on [0, 1]: D < 0 only by rounding */
+    double w = -0.5 * (qb + (qb >= 0.0 ? sqrt(D) : -sqrt(D)));
+    if (w != 0.0) {
+      roots[nr++] = w / qa;
+      roots[nr++] = qc / w;
+    }
+  }
+  double t = -1.0;
+  for (int i = 0; i < nr; ++i)
+    if (roots[i] >= 0.0 && (t < 0.0 || roots[i] < t)) t = roots[i];
+  if (t < 0.0) return 0.0;
+  return t < 1.0 ? t : 1.0;
+}
+
+/* theta^p from UL (pressure pL) toward UT under the configured rule */
+static double theta_p(const orc_cfg* c, const double* UL, double pL, const double* UT,
+                      double eps) {
+  if (c->limiter & ORC_LIM_PEXACT) return orc_theta_p_root(c, UL, UT, eps);
+  return orc_Theta(pL, orc_pressure(c, UT), eps);
+}
+
 /* two-step Theta blend (density, then pressure through concavity), Sec. 3.3.
  * Returns theta^rho theta^p for moving from UL toward UH; *bad set if UL is not
  * admissible. */
@@ -315,7 +382,7 @@ static double theta_pair(const orc_cfg* c, const double* UL, const double* UH, i
   double Ut[4];
   for (int r = 0; r < nc; ++r) Ut[r] = UL[r] + tr * (UH[r] - UL[r]);
   double ep = dmin(PP_EPS, pL);
-  double tp = orc_Theta(pL, orc_pressure(c, Ut), ep);
+  double tp = theta_p(c, UL, pL, Ut, ep);
   return tr * tp;
 }
 
@@ -704,8 +771,8 @@ static int fe1(const orc_cfg* c, const double* U, double dt, double* Ufe, double
               Tp[k] = ULp[k] + tr * (UHp[k] - ULp[k]);
               Tm[k] = ULm[k] + tr * (UHm[k] - ULm[k]);
             }
-            double tp = dmin(orc_Theta(pLp, orc_pressure(c, Tp), dmin(PP_EPS, pLp)),
-                             orc_Theta(pLm, orc_pressure(c, Tm), dmin(PP_EPS, pLm)));
+            double tp = dmin(theta_p(c, ULp, pLp, Tp, dmin(PP_EPS, pLp)),
+                             theta_p(c, ULm, pLm, Tm, dmin(PP_EPS, pLm)));
             tpp = tr * tp;
           }
           if (bad) flags |= ORC_FLAG_CELL_LOW;
@@ -1247,8 +1314,8 @@ static int fe2(const orc_cfg* c, const double* U, double dt, double* Ufe, double
                   Tp[k] = ULp[k] + tr * (UHp[k] - ULp[k]);
                   Tm[k] = ULm[k] + tr * (UHm[k] - ULm[k]);
                 }
-                double tp = dmin(orc_Theta(pLp, orc_pressure(c, Tp), dmin(PP_EPS, pLp)),
-                                 orc_Theta(pLm, orc_pressure(c, Tm), dmin(PP_EPS, pLm)));
+                double tp = dmin(theta_p(c, ULp, pLp, Tp, dmin(PP_EPS, pLp)),
+                                 theta_p(c, ULm, pLm, Tm, dmin(PP_EPS, pLm)));
                 tpp = tr * tp;
               }
               if (bad) fl |= ORC_FLAG_CELL_LOW;

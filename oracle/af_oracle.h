@@ -38,8 +38,10 @@ enum {
   ORC_LIM_PP = 2,      /* density/pressure limiting of cell-average fluxes */
   ORC_LIM_POINT = 4,   /* scaling limiter of point values                 */
   ORC_LIM_CENTRE = 8,  /* scaling limiter of reconstructed centre values  */
-  ORC_LIM_LOWONLY = 16 /* diagnostic: low-order LLF cell fluxes and, with
-                          ORC_LIM_POINT, low-order point values          */
+  ORC_LIM_LOWONLY = 16, /* diagnostic: low-order LLF cell fluxes and, with
+                           ORC_LIM_POINT, low-order point values          */
+  ORC_LIM_PEXACT = 64   /* theta^p as the root of the pressure quadratic
+                           (reading R-pquad) in place of the linear rule  */
 };
 
 /* status flags raised by one forward-Euler stage */
@@ -116,6 +118,8 @@ int orc_run(const orc_cfg* c, double* U, double t0, double t_final,
 
 /* building blocks exposed for property tests */
 double orc_Theta(double zL, double zH, double eps);
+/* theta^p of the exact rule from UL toward UT (reading R-pquad) */
+double orc_theta_p_root(const orc_cfg* c, const double* UL, const double* UT, double eps);
 double orc_pressure(const orc_cfg* c, const double* U);
 void orc_flux_c(const orc_cfg* c, int dir, const double* U, double* F);
 void orc_flux_v(const orc_cfg* c, int dir, const double* U, const double* S,
