@@ -83,7 +83,15 @@ enum {
      admissible bound (Sec. 3.3), and positivity and conservation are as in
      the plain method; theta_nn = theta^s gives the plain stage.
      AF_LIM_SMOOTH is ignored. */
-  AF_LIM_LEARNED = 32
+  AF_LIM_LEARNED = 32,
+  /* the pressure factor theta^p of every density-then-pressure blend (cell
+     fluxes, point values, centres; Sec. 3.3) solved exactly: the largest
+     blend keeping p >= eps along the whole segment, the root of the
+     quadratic that p(blend) = eps becomes once multiplied by the blended
+     density, in place of the linear bound that the concavity of p gives.
+     Never below the linear one; positivity as with it.  1D and 2D, both
+     precisions (computed in FP64). */
+  AF_LIM_PEXACT = 64
 };
 
 /* sticky status flags accumulated in the workspace by af_rk_stage */

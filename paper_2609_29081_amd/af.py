@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libaf.so")
 AF_OK, AF_E_ARG, AF_E_HIP, AF_E_PP, AF_E_NONFINITE = 0, 1, 2, 3, 4
 PERIODIC, OUTFLOW, NOSLIP, SYMMETRY, DIRICHLET = 0, 1, 2, 3, 4
 LIM_SMOOTH, LIM_PP, LIM_POINT, LIM_CENTRE, LIM_LOWONLY, LIM_LEARNED = 1, 2, 4, 8, 16, 32
+LIM_PEXACT = 64   # theta^p by the root of the pressure quadratic
 LIM_ALL = 15
 PREC_FP64, PREC_MIXED = 0, 1
 FLAG_CELL_LOW, FLAG_POINT_LOW, FLAG_NONFINITE = 1, 2, 4

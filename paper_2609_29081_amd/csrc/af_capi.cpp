@@ -514,7 +514,7 @@ af_status af_init_grid(const af_params* p, af_ctx** out) {
   if (!(p->Pr > 0.0)) return fail(AF_E_ARG, "Pr must be > 0");
   if (!(p->cfl_c > 0.0) || !(p->cfl_v > 0.0)) return fail(AF_E_ARG, "CFL numbers must be > 0");
   if (!(p->Cs >= 0.0)) return fail(AF_E_ARG, "Cs must be >= 0");
-  if (p->limiter < 0 || p->limiter > 63) return fail(AF_E_ARG, "bad limiter bits");
+  if (p->limiter < 0 || p->limiter > 127) return fail(AF_E_ARG, "bad limiter bits");
   if ((p->limiter & AF_LIM_LEARNED) && p->dim != 2)
     return fail(AF_E_ARG, "the learned blend exists for 2D only");
   if (p->max_halvings < 0) return fail(AF_E_ARG, "max_halvings must be >= 0");

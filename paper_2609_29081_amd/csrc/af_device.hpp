@@ -18,7 +18,8 @@ constexpr double kDucros = 1.0e-13;   // Ducros-sensor regularisation (Sec. 3.2)
 
 enum : int { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_NOSLIP = 2, BC_SYMMETRY = 3, BC_DIRICHLET = 4 };
 enum : int {
-  LIM_SMOOTH = 1, LIM_PP = 2, LIM_POINT = 4, LIM_CENTRE = 8, LIM_LOWONLY = 16, LIM_LEARNED = 32
+  LIM_SMOOTH = 1, LIM_PP = 2, LIM_POINT = 4, LIM_CENTRE = 8, LIM_LOWONLY = 16, LIM_LEARNED = 32,
+  LIM_PEXACT = 64
 };
 enum : unsigned { FLAG_CELL_LOW = 1u, FLAG_POINT_LOW = 2u, FLAG_NONFINITE = 4u };
 
@@ -123,10 +124,54 @@ __device__ __forceinline__ double pressure1(double r, double m, double E, double
   return gm1 * (E - m * m / (2.0 * r));
 }
 
+// ---------------------------------------------------------------------------
+// theta^p solved exactly (the pressure quadratic; switch LIM_PEXACT): the
+// largest t in [0, 1] keeping p >= eps on the whole segment from the state
+// UL = (r, m1, m2, E) by (dr, dm1, dm2, dE), for p(UL) >= eps > p(UL + d).
+// With positive density on the segment (theta^rho sees to it), p(s) - eps
+// has the sign of q(s) = rho(s) (E(s) - eps/(gamma-1)) - |m(s)|^2 / 2 =
+// a s^2 + b s + c, where c >= 0 > q(1): its root in [0, 1] is
+// 2c / (-b + sqrt(b^2 - 4ac)) (no cancellation: -b + sqrt(.) > 0 there).
+// When p(UL) = eps exactly (c = 0) the blend runs to the other root if the
+// pressure rises first, else it is 0.  1D passes m2 = dm2 = 0.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double theta_p_root(double r, double m1, double m2, double E, double dr,
+                                            double dm1, double dm2, double dE, double eps,
+                                            double gm1) {
+  const double e1 = eps / gm1;
+  const double c = r * (E - e1) - 0.5 * (m1 * m1 + m2 * m2);
+  const double b = dr * (E - e1) + r * dE - (m1 * dm1 + m2 * dm2);
+  const double a = dr * dE - 0.5 * (dm1 * dm1 + dm2 * dm2);
+  if (!(c > 0.0)) return (c == 0.0 && b > 0.0 && a < 0.0) ? fmin(-b / a, 1.0) : 0.0;
+  const double den = -b + sqrt(fmax(b * b - 4.0 * a * c, 0.0));
+  if (!(den > 0.0)) return 0.0;
+  const double t = 2.0 * c / den;
+  return t < 1.0 ? t : 1.0;
+}
+
+// theta^p from UL (pressure pL) toward UT under the linear rule of Sec. 3.3,
+// or solved exactly; 1 where p(UT) >= eps
+__device__ __forceinline__ double theta_p2(const double* UL, double pL, const double* UT,
+                                           double eps, double gm1, bool exact) {
+  const double pT = pressure2(UT[0], UT[1], UT[2], UT[3], gm1);
+  if (exact && pT < eps)
+    return theta_p_root(UL[0], UL[1], UL[2], UL[3], UT[0] - UL[0], UT[1] - UL[1],
+                        UT[2] - UL[2], UT[3] - UL[3], eps, gm1);
+  return theta_lin(pL, pT, eps);
+}
+__device__ __forceinline__ double theta_p1(const double* UL, double pL, const double* UT,
+                                           double eps, double gm1, bool exact) {
+  const double pT = pressure1(UT[0], UT[1], UT[2], gm1);
+  if (exact && pT < eps)
+    return theta_p_root(UL[0], UL[1], 0.0, UL[2], UT[0] - UL[0], UT[1] - UL[1], 0.0,
+                        UT[2] - UL[2], eps, gm1);
+  return theta_lin(pL, pT, eps);
+}
+
 // Density-then-pressure blend from UL toward UH (2D, 4 components).  Returns
 // theta^rho theta^p; sets bad if UL is not admissible (rho<=0 gives 0).
 __device__ __forceinline__ double theta_pair2(const double* UL, const double* UH, double gm1,
-                                              bool& bad) {
+                                              bool& bad, bool exact) {
   if (!(UL[0] > 0.0)) {
     bad = true;
     return 0.0;
@@ -138,12 +183,13 @@ __device__ __forceinline__ double theta_pair2(const double* UL, const double* UH
   const double t1 = UL[1] + tr * (UH[1] - UL[1]);
   const double t2 = UL[2] + tr * (UH[2] - UL[2]);
   const double t3 = UL[3] + tr * (UH[3] - UL[3]);
-  const double tp = theta_lin(pL, pressure2(t0, t1, t2, t3, gm1), mn(kPPEps, pL));
+  const double Ut[4] = {t0, t1, t2, t3};
+  const double tp = theta_p2(UL, pL, Ut, mn(kPPEps, pL), gm1, exact);
   return tr * tp;
 }
 
 __device__ __forceinline__ double theta_pair1(const double* UL, const double* UH, double gm1,
-                                              bool& bad) {
+                                              bool& bad, bool exact) {
   if (!(UL[0] > 0.0)) {
     bad = true;
     return 0.0;
@@ -154,7 +200,8 @@ __device__ __forceinline__ double theta_pair1(const double* UL, const double* UH
   const double t0 = UL[0] + tr * (UH[0] - UL[0]);
   const double t1 = UL[1] + tr * (UH[1] - UL[1]);
   const double t2 = UL[2] + tr * (UH[2] - UL[2]);
-  const double tp = theta_lin(pL, pressure1(t0, t1, t2, gm1), mn(kPPEps, pL));
+  const double Ut[3] = {t0, t1, t2};
+  const double tp = theta_p1(UL, pL, Ut, mn(kPPEps, pL), gm1, exact);
   return tr * tp;
 }
 

@@ -75,7 +75,7 @@ __global__ void __launch_bounds__(kBlock) k_lattice1(G1 g, Phys ph, const double
         for (int k = 0; k < 3; ++k) V[k] = Ub[k];
       } else {
         bool bad = false;
-        const double th = theta_pair1(Ub, V, ph.gm1, bad);
+        const double th = theta_pair1(Ub, V, ph.gm1, bad, ph.lim & LIM_PEXACT);
         if (th < 1.0) {
 #pragma unroll
           for (int k = 0; k < 3; ++k) V[k] = Ub[k] + th * (V[k] - Ub[k]);
@@ -219,9 +219,9 @@ __global__ void __launch_bounds__(kBlock) k_face1(G1 g, Phys ph, const double* _
             Tp[k] = ULp[k] + tr * (UHp[k] - ULp[k]);
             Tm[k] = ULm[k] + tr * (UHm[k] - ULm[k]);
           }
-          const double tp =
-              mn(theta_lin(pLp, pressure1(Tp[0], Tp[1], Tp[2], ph.gm1), mn(kPPEps, pLp)),
-                   theta_lin(pLm, pressure1(Tm[0], Tm[1], Tm[2], ph.gm1), mn(kPPEps, pLm)));
+          const bool ex = ph.lim & LIM_PEXACT;
+          const double tp = mn(theta_p1(ULp, pLp, Tp, mn(kPPEps, pLp), ph.gm1, ex),
+                               theta_p1(ULm, pLm, Tm, mn(kPPEps, pLm), ph.gm1, ex));
           tpp = tr * tp;
         }
         if (bad) raise_flag(flags, FLAG_CELL_LOW);
@@ -362,7 +362,7 @@ __global__ void __launch_bounds__(kBlock) k_points1(G1 g, Phys ph, const double*
 #pragma unroll
     for (int k = 0; k < 3; ++k) UL[k] = U0[k] - c2 * (Fp[k] - Fm[k]);
     bool lbad = false;
-    double th = theta_pair1(UL, UH, ph.gm1, lbad);
+    double th = theta_pair1(UL, UH, ph.gm1, lbad, ph.lim & LIM_PEXACT);
     if (ph.lim & LIM_LOWONLY) th = 0.0;
     if (lbad) raise_flag(flags, FLAG_POINT_LOW);
 #pragma unroll

@@ -115,10 +115,27 @@ __device__ __forceinline__ void centre_value(const PhysT<R>& ph, const Phys& phd
         Vd[k] = V[k];
       }
       bool bad = false;
-      const double th = theta_pair2(Ud, Vd, phd.gm1, bad);
+      const double th = theta_pair2(Ud, Vd, phd.gm1, bad, ph.lim & LIM_PEXACT);
       if (th < 1.0) {
+        double Wd[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) V[k] = R(Ud[k] + th * (Vd[k] - Ud[k]));
+        for (int k = 0; k < 4; ++k) {
+          Wd[k] = Ud[k] + th * (Vd[k] - Ud[k]);
+          V[k] = R(Wd[k]);
+        }
+        if constexpr (!std::is_same<R, double>::value) {
+          // FP32 stencils: the scaled centre's pressure may sit at eps, far
+          // below the rounding of E - |m|^2 / (2 rho) in FP32, so its
+          // (u, v, p, T, c) are taken from the FP64 value
+          const double ird = rcp(Wd[0]);
+          const double pd = phd.gm1 * (Wd[3] - 0.5 * (Wd[1] * Wd[1] + Wd[2] * Wd[2]) * ird);
+          w[0] = R(Wd[1] * ird);
+          w[1] = R(Wd[2] * ird);
+          w[2] = R(pd);
+          w[3] = R(pd * ird);
+          w[4] = R(sqrt(phd.gam * (pd * ird)));
+          return;
+        }
       }
     }
     ir = rcp(V[0]);
@@ -1151,9 +1168,9 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
               Tp[k] = ULp[k] + tr * (UHp[k] - ULp[k]);
               Tm[k] = ULm[k] + tr * (UHm[k] - ULm[k]);
             }
-            const double tp =
-                mn(theta_lin(pLp, pressure2(Tp[0], Tp[1], Tp[2], Tp[3], phd.gm1), mn(kPPEps, pLp)),
-                   theta_lin(pLm, pressure2(Tm[0], Tm[1], Tm[2], Tm[3], phd.gm1), mn(kPPEps, pLm)));
+            const bool ex = ph.lim & LIM_PEXACT;
+            const double tp = mn(theta_p2(ULp, pLp, Tp, mn(kPPEps, pLp), phd.gm1, ex),
+                                 theta_p2(ULm, pLm, Tm, mn(kPPEps, pLm), phd.gm1, ex));
             tpp = tr * tp;
           }
           if (bad) raise_flag(flags, FLAG_CELL_LOW);
@@ -1330,7 +1347,7 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) UL[k] = U0[k] - Ls[k];
         bool lbad = false;
-        double th = theta_pair2(UL, UH, phd.gm1, lbad);
+        double th = theta_pair2(UL, UH, phd.gm1, lbad, ph.lim & LIM_PEXACT);
         if (ph.lim & LIM_LOWONLY) th = 0.0;
         if (lbad && d == 0) raise_flag(flags, FLAG_POINT_LOW);
 #pragma unroll

@@ -44,12 +44,19 @@ def make(**kw):
 @pytest.mark.parametrize("field,value", [("dim", 3), ("n1", 3), ("n2", 2), ("gamma", 1.0),
                                          ("mu", -1e-3), ("Pr", 0.0), ("cfl_c", 0.0),
                                          ("cfl_v", -1.0), ("x1", 0.0), ("max_halvings", -1),
-                                         ("limiter", 64)])
+                                         ("limiter", 128), ("limiter", -1)])
 def test_init_rejects_bad_parameters(field, value):
     st, h = make(**{field: value})
     assert st == af.AF_E_ARG
     assert af.lib().af_last_error()
     assert not h.value
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_init_takes_the_exact_pressure_rule(dim):
+    st, h = make(dim=dim, n1=16, n2=8, limiter=af.LIM_ALL | af.LIM_PEXACT)
+    assert st == af.AF_OK and h.value
+    af.lib().af_destroy(h)
 
 
 def test_sizes_match_the_documented_layout():

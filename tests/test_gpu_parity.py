@@ -124,6 +124,54 @@ def test_stage_2d_density_pressure_limiting_active(angle, limiter):
     check_stages(g, U, **kw)
 
 
+@pytest.mark.parametrize("angle", [0.0, 0.5])
+def test_stage_2d_exact_pressure_rule(angle):
+    """the pressure factor solved exactly (LIM_PEXACT) on the receding
+    rarefactions: it acts (the oracle's output differs from the linear
+    rule's) and the GPU follows it"""
+    g, f = W.double_rarefaction(40, 24, angle=angle)
+    U = W.make_state(g, f, GAMMA)
+    kw = dict(mu=1e-3, Pr=0.72, limiter=O.LIM_ALL | O.LIM_PEXACT)
+    cfg = O.make_cfg(g, **kw)
+    for _ in range(2):
+        assert O.step(cfg, U)[0] == 0
+    dt = accepted_dt(cfg, U)
+    lin = O.fe(O.make_cfg(g, mu=1e-3, Pr=0.72), U, dt)[0]
+    assert not np.array_equal(O.fe(cfg, U, dt)[0], lin)
+    check_stages(g, U, dt=dt, **kw)
+    check_stages(g, U, **kw)
+
+
+def test_stage_1d_exact_pressure_rule():
+    g, f = W.double_rarefaction(101)
+    U = W.make_state(g, f, GAMMA)
+    kw = dict(mu=0.0, limiter=O.LIM_PP | O.LIM_POINT | O.LIM_CENTRE | O.LIM_PEXACT)
+    cfg = O.make_cfg(g, **kw)
+    for _ in range(5):
+        assert O.step(cfg, U)[0] == 0
+    dt = O.dt(cfg, U)
+    lin = O.fe(O.make_cfg(g, mu=0.0, limiter=O.LIM_PP | O.LIM_POINT | O.LIM_CENTRE), U, dt)[0]
+    assert not np.array_equal(O.fe(cfg, U, dt)[0], lin)
+    check_stages(g, U, **kw)
+
+
+def test_steps_exact_pressure_rule_match_oracle():
+    """five steps of the 2D receding rarefactions under LIM_PEXACT: the
+    same time steps and halvings as the oracle, and the same state"""
+    g, f = W.double_rarefaction(40, 24, angle=0.5)
+    U = W.make_state(g, f, GAMMA)
+    kw = dict(mu=1e-3, Pr=0.72, limiter=O.LIM_ALL | O.LIM_PEXACT)
+    cfg = O.make_cfg(g, **kw)
+    S = solver_for(g, **kw)
+    Ud = S.to_device(U)
+    for n in range(5):
+        st, dtu, h, fl = O.step(cfg, U)
+        stg, dtg, hg = S.af_step(Ud)
+        assert st == 0 and stg == af.AF_OK
+        assert hg == h and dtg == pytest.approx(dtu, rel=1e-12), n
+    assert_close(g, Ud.cpu().numpy(), U, what="five steps under the exact pressure rule")
+
+
 def test_stage_1d_density_pressure_limiting_active():
     g, f = W.double_rarefaction(101)
     U = W.make_state(g, f, GAMMA)
