@@ -89,6 +89,8 @@ def main() -> int:
                     help="budget of the single-thread CPU-oracle sample (one step at least)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision form")
+    ap.add_argument("--no-pexact", action="store_true",
+                    help="skip the form with the pressure factor solved exactly")
     ap.add_argument("--roofline-reps", type=int, default=10,
                     help="repetitions of the three stage kinds timed for the roofline")
     ap.add_argument("--no-batched", action="store_true",
@@ -330,6 +332,8 @@ def main() -> int:
                     "traffic": trm["bytes_per_launch"],
                     "executed_TFLOPs": {"fp32": round(f32 / stage_s_m / 1e12, 2),
                                         "fp64": round(f64 / stage_s_m / 1e12, 2)}})
+    if not args.no_pexact:
+        forms["pexact"] = pexact_form(g, kw, dev_U0, U_graph, t_end, K, stream)
     if not args.no_vortex:
         forms["vortex_wave"] = vortex_form(args, stream)
     if not args.no_batched:
@@ -417,6 +421,40 @@ def vortex_form(args, stream) -> dict:
             del S, U, d0
         out[f"{n}x{n}"] = rec
     return out
+
+
+def pexact_form(g, kw, dev_U0, U_lin, t_lin, K, stream) -> dict:
+    """the same K steps from t = 0 with the limiter's pressure factor solved
+    from the pressure quadratic (AF_LIM_PEXACT) in place of the linear rule:
+    throughput, attempts per step, the time reached, and the final state's
+    relative L1 / L-inf difference from the linear rule's run"""
+    import numpy as np
+    import torch
+
+    from paper_2609_29081_amd import af
+    kwe = dict(kw)
+    kwe["limiter"] = kw.get("limiter", af.LIM_ALL) | af.LIM_PEXACT
+    Se = af.Solver(g, **kwe)
+    Ue = dev_U0.clone()
+    Se.af_run_graph(Ue, 0.0, 1e30, 1, attempts_per_slot=APS)
+    Ue.copy_(dev_U0)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    st, n, t_e, att = Se.af_run_graph(Ue, 0.0, 1e30, K, attempts_per_slot=APS)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    if st != af.AF_OK or n != K:
+        raise RuntimeError(f"exact-pressure-rule run failed: status {st}, {n}/{K} steps")
+    ms = e0.elapsed_time(e1)
+    a, b = U_lin.cpu().numpy(), Ue.cpu().numpy()
+    return {"value": g.dof_sites * 3 * K / (ms / 1e3), "ms_per_step": ms / K,
+            "rk3_attempts_per_step": round(att / K, 3), "t_reached": t_e,
+            "t_reached_linear_rule": t_lin,
+            "l1_rel_vs_linear_rule": float(np.abs(b - a).sum() / np.abs(a).sum()),
+            "linf_rel_vs_linear_rule": float(np.abs(b - a).max() / np.abs(a).max()),
+            "what": "theta^p as the root of the pressure quadratic (AF_LIM_PEXACT), same window"}
 
 
 def whole_run(args, g, U0, kw) -> dict:
