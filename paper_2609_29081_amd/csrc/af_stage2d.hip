@@ -991,9 +991,11 @@ __global__ void __launch_bounds__(NT) k_stage(StageArgs sa) {
     __syncthreads();
   }
   // ghost centres: the value and (u, v, p, T, c) of the image centre, with
-  // the image's momentum and velocity signs.  The image is a centre of the
-  // same region that phase 2 computed from the same values in the same
-  // order (along a periodic axis, the unwrapped ghost itself)
+  // the image's momentum and velocity signs.  Ghosts reach at most four
+  // lattice lines past a side, so the image (a mirror or the first interior
+  // centre; along a periodic axis the unwrapped ghost itself) lies in this
+  // tile's region, and phase 2 computed it from the same values in the same
+  // order as the image's own Simpson value: the copy is that value exactly
   if (!(X0 >= 4 && X0 - 4 + WA <= Xlim && Y0 >= 4 && Y0 - 4 + HA <= Ylim)) {
     for (int cidx = tid; cidx < NCEN; cidx += NT) {
       const int cs = centre_slot(cidx);
