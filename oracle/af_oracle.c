@@ -316,7 +316,8 @@ static void flux_tot(const orc_cfg* c, int dir, const double* U, const double* S
  * roots w / a and c / w). */
 double orc_theta_p_root(const orc_cfg* c, const double* UL, const double* UT, double eps) {
   int nc = ncomp(c);
-  if (orc_pressure(c, UT) >= eps) return 1.0;
+  /* not below eps (a non-finite pressure included, as in orc_Theta) */
+  if (!(orc_pressure(c, UT) < eps)) return 1.0;
   double e1 = eps / (c->gamma - 1.0);
   double dr = UT[0] - UL[0], dE = UT[nc - 1] - UL[nc - 1];
   double mm = 0.0, mdm = 0.0, dmdm = 0.0;
