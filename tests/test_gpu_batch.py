@@ -66,6 +66,24 @@ def test_batch_reproduces_single_runs(precision, use_graph, aps):
         assert np.array_equal(U.cpu().numpy(), ref)
 
 
+@pytest.mark.parametrize("precision", [af.PREC_FP64, af.PREC_MIXED])
+def test_batch_with_per_instance_pressure_rules(precision):
+    """instances under the exact pressure rule (AF_LIM_PEXACT) beside
+    instances under the linear one, in one batch: each reproduces its own
+    single run bit for bit"""
+    steps = 5
+    insts = [(g, f, dict(kw, limiter=af.LIM_ALL | (af.LIM_PEXACT if k % 2 == 0 else 0)))
+             for k, (g, f, kw) in enumerate(instances())]
+    solvers = [af.Solver(g, precision=precision, **kw) for g, f, kw in insts]
+    states = [S.to_device(W.make_state(g, f, GAMMA)) for S, (g, f, kw) in zip(solvers, insts)]
+    st, n, t, att = af.Batch(solvers).af_batch_run(states, 0.0, 1e30, steps)
+    assert st == [af.AF_OK] * len(insts) and n == [steps] * len(insts)
+    for (g, f, kw), U, ti in zip(insts, states, t):
+        ref, tr = run_single(g, f, kw, steps, precision)
+        assert ti == tr
+        assert np.array_equal(U.cpu().numpy(), ref)
+
+
 def test_batch_matches_the_oracle():
     insts = instances()[1:3]
     solvers = [af.Solver(g, **kw) for g, f, kw in insts]
