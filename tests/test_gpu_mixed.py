@@ -58,7 +58,8 @@ def stage_errors(grid, U, **kw):
     return worst
 
 
-@pytest.mark.parametrize("case", ["vortex", "walls", "tube", "rarefaction", "rarefaction_pexact"])
+@pytest.mark.parametrize("case", ["vortex", "walls", "smallest_walls", "tube", "rarefaction",
+                                  "rarefaction_pexact"])
 def test_mixed_stages_close_to_fp64_oracle(case):
     if case == "vortex":
         g, f = W.vortex_wave_2d(48)
@@ -67,6 +68,10 @@ def test_mixed_stages_close_to_fp64_oracle(case):
         g, f = W.random_smooth_2d(37, 22, seed=3, bc=(W.NOSLIP, W.OUTFLOW, W.SYMMETRY, W.NOSLIP),
                                   amp=0.15)
         kw = dict(mu=0.01, Pr=0.72)
+    elif case == "smallest_walls":   # 4x4 cells: one tile, ghosts past every side
+        g, f = W.random_smooth_2d(4, 4, seed=7, bc=(W.NOSLIP, W.SYMMETRY, W.SYMMETRY, W.NOSLIP),
+                                  amp=0.1)
+        kw = dict(mu=0.02, Pr=0.73)
     elif case == "tube":
         g, f = W.shock_tube_2d(48, 24, rho_left=3.0)
         kw = dict(mu=0.005, Pr=0.73)

@@ -197,6 +197,16 @@ def test_stage_2d_limiter_switches(limiter):
     check_stages(g, U, mu=0.005, Pr=0.73, limiter=limiter)
 
 
+@pytest.mark.parametrize("bc", [(W.NOSLIP, W.SYMMETRY, W.SYMMETRY, W.NOSLIP),
+                                (W.PERIODIC, W.PERIODIC, W.NOSLIP, W.OUTFLOW),
+                                (W.OUTFLOW, W.NOSLIP, W.PERIODIC, W.PERIODIC)])
+def test_stage_2d_smallest_grid_every_side_kind(bc):
+    """the smallest grid (4x4 cells, one tile): ghost centres beyond every
+    non-periodic side, whose images lie one and two cells from the side"""
+    g, f = W.random_smooth_2d(4, 4, seed=7, bc=bc, amp=0.1)
+    check_stages(g, W.make_state(g, f, GAMMA), mu=0.02, Pr=0.73)
+
+
 def test_stage_2d_inviscid_and_smallest_grid():
     g, f = W.random_smooth_2d(4, 4, seed=2, bc=(W.OUTFLOW,) * 4, amp=0.1)
     check_stages(g, W.make_state(g, f, GAMMA), mu=0.0)
