@@ -42,11 +42,11 @@
  *   R-eps    : eps = min(1e-13, z(U^L)) per state; a state with rho<=0 is
  *              flagged and its blend parameter set to 0.
  *   R-pquad  : (optional, ORC_LIM_PEXACT) theta^p is the largest blend
- *              keeping the pressure >= eps on the whole segment, the root of
- *              the quadratic that p(blend) = eps becomes once multiplied by
- *              the blended density, in place of the linear bound that the
- *              concavity of p gives (Sec. 3.3).  It is never below the
- *              linear one, and positivity holds with either.
+ *              keeping the pressure >= eps on the whole segment (where
+ *              p(blend) = eps, a quadratic once multiplied by the blended
+ *              density), in place of the linear bound that the concavity of
+ *              p gives (Sec. 3.3); 0 where p(U^L) is at the 1e-13 floor, as
+ *              under the linear rule.  It is never below the linear one.
  *   R-blend  : final cell flux F^L + theta^s theta^rho theta^p (F^H - F^L);
  *              with every cell limiter switched off the flux is F^H itself;
  *              a point whose blend parameter is 1 keeps U^H itself.
@@ -306,58 +306,30 @@ static void flux_tot(const orc_cfg* c, int dir, const double* U, const double* S
 }
 
 /* theta^p by the exact rule (reading R-pquad): the largest t in [0, 1] such
- * that p(UL + s (UT - UL)) >= eps for every s in [0, t].  Where the density
- * is positive along the segment (theta^rho has made it so), p(s) - eps has
- * the sign of the quadratic
- *   q(s) = rho(s) (E(s) - eps / (gamma - 1)) - |m(s)|^2 / 2,
- * with q(0) >= 0 because eps <= p(UL).  So t = 1 if p(UT) >= eps, and
- * otherwise the smallest root of q in [0, 1], taken from the quadratic
- * formula in its cancellation-free form (w = -(b + sign(b) sqrt(D)) / 2,
- * roots w / a and c / w). */
+ * that p(UL + s (UT - UL)) >= eps for every s in [0, t].  With positive
+ * density along the segment (theta^rho has made it so) p is concave on it,
+ * so the s with p >= eps form an interval that holds 0, and its end is found
+ * by bisection on the pressure of the state as formed (the iteration stops
+ * when the bracket no longer shrinks).  t = 1 if p(UT) >= eps.  Where p(UL)
+ * is itself at the floor (eps = p(UL), at most 1e-13) the blend is 0, as
+ * under the linear rule: the crossing would leave the state at that floor,
+ * below the rounding of E - |m|^2 / (2 rho). */
 double orc_theta_p_root(const orc_cfg* c, const double* UL, const double* UT, double eps) {
   int nc = ncomp(c);
   /* not below eps (a non-finite pressure included, as in orc_Theta) */
   if (!(orc_pressure(c, UT) < eps)) return 1.0;
-  double e1 = eps / (c->gamma - 1.0);
-  double dr = UT[0] - UL[0], dE = UT[nc - 1] - UL[nc - 1];
-  double mm = 0.0, mdm = 0.0, dmdm = 0.0;
-  for (int k = 1; k < nc - 1; ++k) {
-    double dm = UT[k] - UL[k];
-    mm += UL[k] * UL[k];
-    mdm += UL[k] * dm;
-    dmdm += dm * dm;
+  if (!(orc_pressure(c, UL) > eps)) return 0.0;
+  double lo = 0.0, hi = 1.0, W[4];
+  for (int it = 0; it < 1100; ++it) {
+    double mid = 0.5 * (lo + hi);
+    if (!(mid > lo && mid < hi)) break;
+    for (int r = 0; r < nc; ++r) W[r] = UL[r] + mid * (UT[r] - UL[r]);
+    if (orc_pressure(c, W) >= eps)
+      lo = mid;
+    else
+      hi = mid;
   }
-  /* q(s) = qa s^2 + qb s + qc */
-  double qc = UL[0] * (UL[nc - 1] - e1) - 0.5 * mm;
-  double qb = dr * (UL[nc - 1] - e1) + UL[0] * dE - mdm;
-  double qa = dr * dE - 0.5 * dmdm;
-  if (!(qc > 0.0)) {
-    /* p(UL) = eps: s = 0 is a root, and the pressure stays >= eps past it
-     * only if it grows first (q'(0) > 0), up to the other root */
-    if (qc == 0.0 && qb > 0.0 && qa < 0.0) {
-      double r = -qb / qa;
-      return r < 1.0 ? r : 1.0;
-    }
-    return 0.0;
-  }
-  double roots[2];
-  int nr = 0;
-  if (qa == 0.0) {
-    if (qb != 0.0) roots[nr++] = -qc / qb;
-  } else {
-    double D = qb * qb - 4.0 * qa * qc;
-    if (D < 0.0) D = 0.0; /* q changes sign on [0, 1]: D < 0 only by rounding */
-    double w = -0.5 * (qb + (qb >= 0.0 ? sqrt(D) : -sqrt(D)));
-    if (w != 0.0) {
-      roots[nr++] = w / qa;
-      roots[nr++] = qc / w;
-    }
-  }
-  double t = -1.0;
-  for (int i = 0; i < nr; ++i)
-    if (roots[i] >= 0.0 && (t < 0.0 || roots[i] < t)) t = roots[i];
-  if (t < 0.0) return 0.0;
-  return t < 1.0 ? t : 1.0;
+  return lo;
 }
 
 /* theta^p from UL (pressure pL) toward UT under the configured rule */

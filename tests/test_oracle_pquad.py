@@ -8,8 +8,9 @@ rule takes the bound that the concavity of p gives.
   (gamma - 1)(E - |m|^2 / (2 rho)) = eps, to 1e-11.
 * It is never below the linear rule's theta^p (concavity of p along a
   segment of positive density), and the pressure at it is eps.
-* With p(U^L) = eps and a pressure that first rises, the blend is the other
-  root, not 0.
+* With p(U^L) at the 1e-13 floor the blend is 0, as under the linear rule.
+* A segment from a dense state to a near-vacuum one (the crossing 1.4e-12
+  from the far end) still lands on eps.
 * Whole stages: the switch changes nothing where no pressure limiting acts
   (bit for bit), and where it acts each face's theta^rho theta^p is at least
   the linear rule's, the stage output stays admissible, and the wall-free
@@ -53,7 +54,7 @@ def _bisect_root(UL, UT, eps):
     e = Fraction(eps)
     lo, hi = Fraction(0), Fraction(1)
     assert _q(UL, UT, lo, g1, e) >= 0 > _q(UL, UT, hi, g1, e)
-    for _ in range(60):
+    for _ in range(90):
         mid = (lo + hi) / 2
         if _q(UL, UT, mid, g1, e) >= 0:
             lo = mid
@@ -107,23 +108,41 @@ def test_no_limiting_where_the_pressure_stays_above_eps():
     assert O.theta_p_root(cfg, UL, UT, 1e-13) == 1.0
 
 
-def test_pressure_at_eps_that_first_rises_takes_the_other_root():
-    """p(U^L) = eps exactly (built in rational arithmetic to be exact in
-    floating point): the blend runs to the second root of the quadratic"""
+def test_pressure_of_ul_at_the_floor_gives_zero():
+    """p(U^L) at the 1e-13 floor (eps = p(U^L)): the blend is 0, as under the
+    linear rule, even where the pressure would rise first along the segment
+    and return to the floor further on"""
     cfg = _cfg(1)
     g1 = GAMMA - 1.0
-    # U^L = (1, 0, eps / g1): p(U^L) = g1 * (eps / g1) = eps up to one rounding
-    eps = O.pressure(cfg, np.array([1.0, 0.0, 1e-13 / g1]))
-    UL = np.array([1.0, 0.0, 1e-13 / g1])
-    # toward a state with more internal energy at first and a negative
-    # pressure at the end: q(s) = rho(s) (E(s) - eps/g1) - m(s)^2/2 with
-    # rho = 1, E(s) = eps/g1 + s, m(s) = 2 s  ->  q = s - 2 s^2, root s = 1/2
-    UT = np.array([1.0, 2.0, 1e-13 / g1 + 1.0])
+    UL = np.array([1.0, 0.0, 1e-14 / g1])
+    eps = min(1e-13, O.pressure(cfg, UL))
+    # q(s) = rho (E - eps/g1) - m^2/2 = s - 2 s^2 with rho = 1, E = eps/g1 + s,
+    # m = 2 s: the pressure rises, then crosses the floor again at s = 1/2
+    UT = np.array([1.0, 2.0, 1e-14 / g1 + 1.0])
     assert O.pressure(cfg, UT) < 0.0
-    th = O.theta_p_root(cfg, UL, UT, eps)
-    assert th == pytest.approx(0.5, abs=1e-12)
-    # the linear rule stops at 0 there
+    assert O.theta_p_root(cfg, UL, UT, eps) == 0.0
     assert O.theta(eps, O.pressure(cfg, UT), eps) == 0.0
+
+
+def test_dense_to_near_vacuum_segment_lands_on_eps():
+    """a segment from a dense state to a near-vacuum one whose pressure is
+    just below zero (from a shock-tube point update): the crossing lies
+    1.4e-12 from the far end, where the pressure changes by about 1e3 per
+    unit of the blend; the blend must still put the pressure at eps, not
+    below (solving the quadratic about U^L put it at -1.3e-12)"""
+    cfg = _cfg(2)
+    UL = np.array([5.9171657912943427, 3.5634170000454102, -0.0081445259843001862,
+                   10.813840360482907])
+    UT = np.array([0.00044150857118543404, -0.001343933598765972, -0.00043192216630333135,
+                   0.0022567106760020919])
+    assert O.pressure(cfg, UT) < 0.0
+    eps = 1e-13
+    th = O.theta_p_root(cfg, UL, UT, eps)
+    ref = _bisect_root(UL, UT, eps)
+    assert 1.0 - th == pytest.approx(1.0 - ref, rel=1e-6)
+    p = O.pressure(cfg, UL + th * (UT - UL))
+    assert 0.9 * eps <= p <= 1.1e-12, p
+    assert th >= O.theta(O.pressure(cfg, UL), O.pressure(cfg, UT), eps)
 
 
 def _rarefaction_state(dim):
