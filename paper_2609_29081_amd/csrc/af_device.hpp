@@ -126,27 +126,41 @@ __device__ __forceinline__ double pressure1(double r, double m, double E, double
 
 // ---------------------------------------------------------------------------
 // theta^p solved exactly (the pressure quadratic; switch LIM_PEXACT): the
-// largest t in [0, 1] keeping p >= eps on the whole segment from the state
-// UL = (r, m1, m2, E) by (dr, dm1, dm2, dE), for p(UL) >= eps > p(UL + d).
-// With positive density on the segment (theta^rho sees to it), p(s) - eps
-// has the sign of q(s) = rho(s) (E(s) - eps/(gamma-1)) - |m(s)|^2 / 2 =
-// a s^2 + b s + c, where c >= 0 > q(1): its root in [0, 1] is
-// 2c / (-b + sqrt(b^2 - 4ac)) (no cancellation: -b + sqrt(.) > 0 there).
-// When p(UL) = eps exactly (c = 0) the blend runs to the other root if the
-// pressure rises first, else it is 0.  1D passes m2 = dm2 = 0.
+// largest t in [0, 1] keeping p >= eps on the whole segment from
+// UL = (rL, m1L, m2L, EL), of pressure pL, to UT = (rT, m1T, m2T, ET), of
+// pressure below eps.  With positive density on the segment (theta^rho
+// sees to it), p(s) - eps has the sign of the quadratic
+// q(s) = rho(s) (E(s) - eps/(gamma-1)) - |m(s)|^2 / 2, which is positive at
+// UL and negative at UT, so it has one root in (0, 1).  The root is taken
+// in its cancellation-free form about UL, and again about UT when it lies
+// nearer that end: near UT the value of q is a small difference of the
+// large terms of the expansion about UL, and p = q (gamma-1) / rho
+// magnifies that by 1/rho, so a dense-to-near-vacuum segment needs the
+// expansion about UT, whose terms are its own small ones.  Where pL is at
+// the 1e-13 floor (eps = pL) the blend is 0, as under the linear rule.
+// 1D passes m2 = 0 at both ends.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double theta_p_root(double r, double m1, double m2, double E, double dr,
-                                            double dm1, double dm2, double dE, double eps,
-                                            double gm1) {
+__device__ __forceinline__ double theta_p_root(double rL, double m1L, double m2L, double EL,
+                                               double rT, double m1T, double m2T, double ET,
+                                               double pL, double eps, double gm1) {
+  if (!(pL > eps)) return 0.0;
   const double e1 = eps / gm1;
-  const double c = r * (E - e1) - 0.5 * (m1 * m1 + m2 * m2);
-  const double b = dr * (E - e1) + r * dE - (m1 * dm1 + m2 * dm2);
-  const double a = dr * dE - 0.5 * (dm1 * dm1 + dm2 * dm2);
-  if (!(c > 0.0)) return (c == 0.0 && b > 0.0 && a < 0.0) ? fmin(-b / a, 1.0) : 0.0;
-  const double den = -b + sqrt(fmax(b * b - 4.0 * a * c, 0.0));
-  if (!(den > 0.0)) return 0.0;
-  const double t = 2.0 * c / den;
-  return t < 1.0 ? t : 1.0;
+  const double dr = rT - rL, d1 = m1T - m1L, d2 = m2T - m2L, dE = ET - EL;
+  const double a = dr * dE - 0.5 * (d1 * d1 + d2 * d2);
+  // about UL: q(s) = a s^2 + b s + c, c > 0
+  const double c = rL * (EL - e1) - 0.5 * (m1L * m1L + m2L * m2L);
+  const double b = dr * (EL - e1) + rL * dE - (m1L * d1 + m2L * d2);
+  const double sq = sqrt(fmax(b * b - 4.0 * a * c, 0.0));
+  double t = b <= 0.0 ? 2.0 * c / (-b + sq) : (-b - sq) / (2.0 * a);
+  if (t > 0.5) {
+    // about UT, toward UL: q = a u^2 + bT u + cT in u = 1 - s, cT < 0
+    const double cT = rT * (ET - e1) - 0.5 * (m1T * m1T + m2T * m2T);
+    const double bT = -(dr * (ET - e1) + rT * dE - (m1T * d1 + m2T * d2));
+    const double sqT = sqrt(fmax(bT * bT - 4.0 * a * cT, 0.0));
+    const double u = bT >= 0.0 ? 2.0 * cT / (-bT - sqT) : (-bT + sqT) / (2.0 * a);
+    t = 1.0 - u;
+  }
+  return t > 0.0 ? (t < 1.0 ? t : 1.0) : 0.0;
 }
 
 // theta^p from UL (pressure pL) toward UT under the linear rule of Sec. 3.3,
@@ -155,16 +169,14 @@ __device__ __forceinline__ double theta_p2(const double* UL, double pL, const do
                                            double eps, double gm1, bool exact) {
   const double pT = pressure2(UT[0], UT[1], UT[2], UT[3], gm1);
   if (exact && pT < eps)
-    return theta_p_root(UL[0], UL[1], UL[2], UL[3], UT[0] - UL[0], UT[1] - UL[1],
-                        UT[2] - UL[2], UT[3] - UL[3], eps, gm1);
+    return theta_p_root(UL[0], UL[1], UL[2], UL[3], UT[0], UT[1], UT[2], UT[3], pL, eps, gm1);
   return theta_lin(pL, pT, eps);
 }
 __device__ __forceinline__ double theta_p1(const double* UL, double pL, const double* UT,
                                            double eps, double gm1, bool exact) {
   const double pT = pressure1(UT[0], UT[1], UT[2], gm1);
   if (exact && pT < eps)
-    return theta_p_root(UL[0], UL[1], 0.0, UL[2], UT[0] - UL[0], UT[1] - UL[1], 0.0,
-                        UT[2] - UL[2], eps, gm1);
+    return theta_p_root(UL[0], UL[1], 0.0, UL[2], UT[0], UT[1], 0.0, UT[2], pL, eps, gm1);
   return theta_lin(pL, pT, eps);
 }
 
