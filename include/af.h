@@ -88,9 +88,12 @@ enum {
      fluxes, point values, centres; Sec. 3.3) solved exactly: the largest
      blend keeping p >= eps along the whole segment, the root of the
      quadratic that p(blend) = eps becomes once multiplied by the blended
-     density, in place of the linear bound that the concavity of p gives.
-     Never below the linear one; positivity as with it.  1D and 2D, both
-     precisions (computed in FP64). */
+     density, in place of the linear bound that the concavity of p gives;
+     0 where the low-order state's pressure is at the 1e-13 floor, as with
+     the linear rule.  Never below the linear one.  1D and 2D, both
+     precisions (computed in FP64).  Blends then sit at p = eps, and on
+     strong shock tubes steps are rejected far more often than with the
+     linear rule. */
   AF_LIM_PEXACT = 64
 };
 
