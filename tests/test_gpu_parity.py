@@ -334,6 +334,25 @@ def test_receding_rarefactions_whole_run_with_the_oracle(angle, mu, steps):
     print(f"rarefactions angle={angle} mu={mu}: {n} steps to t={t:.4g}, worst {worst:.3e}")
 
 
+def test_vortex_wave_two_hundred_steps_with_the_oracle():
+    """the smooth periodic vortex wave (64^2, mu = 1e-3) through 200 steps of
+    af_run beside the oracle's run: the same final time, and the final
+    states within the FP64 bar of single stages (smooth data: rounding
+    differences are not amplified from step to step)"""
+    g, f = W.vortex_wave_2d(64)
+    U0 = W.make_state(g, f, GAMMA)
+    kw = dict(mu=1e-3, Pr=0.72)
+    S = solver_for(g, **kw)
+    Ud = S.to_device(U0)
+    st, n, t = S.af_run(Ud, 0.0, 1e30, 200, check_every=1)
+    ref = U0.copy()
+    sto, no, to = O.run(O.make_cfg(g, **kw), ref, 0.0, 1e30, 200)
+    assert st == af.AF_OK and sto == 0 and n == no == 200
+    assert t == pytest.approx(to, rel=1e-12)
+    worst = assert_close(g, Ud.cpu().numpy(), ref, tol=1e-12, what="vortex wave 64^2, 200 steps")
+    print(f"vortex wave 64^2: 200 steps to t={t:.4g}, worst relative error {worst:.3e}")
+
+
 def test_halving_matches_oracle():
     g, f = W.leblanc_1d(160)
     U = W.make_state(g, f, GAMMA)
