@@ -62,7 +62,7 @@ def workload(name: str, n1: int, n2: int):
     return g, f, dict(mu=0.005, Pr=0.73)
 
 
-def target(reps: int = 3, mixed: bool = False, wl: str = "tube", n1: int = N1,
+def target(reps: int = 10, mixed: bool = False, wl: str = "tube", n1: int = N1,
            n2: int = N2) -> None:
     sys.path.insert(0, ROOT)
     import torch
@@ -218,7 +218,7 @@ def driver(outroot: str, mixed: bool = False, wl: str = "tube", n1: int = N1,
           f"Command: `{cmdline}` (three rocprofv3 passes, `--pmc FETCH_SIZE`,",
           f"`--pmc WRITE_SIZE`, `--pmc {' '.join(ilist)}`, each over",
           f"`python -m paper_2609_29081_amd.prof_counters {' '.join(_target_args(mixed, wl, n1, n2))}`: "
-          "three RK3 steps' worth of",
+          "ten rounds of the three RK3 stage kinds (the sequence bench.py times for its roofline):",
           "complete stage launches at the CFL dt of the initial state, then a 256 MiB device copy",
           "for calibration).", "",
           "| quantity | value |", "|---|---|",
